@@ -1,0 +1,255 @@
+"""Throughput of the whole mapping-loss step on one MI355X.
+
+One step = forward render (RGB + depth + 16-d feature) of every view, the L1
+loss gradient of Eq. (1) (without D-SSIM), and the full backward to the
+Gaussian parameters and the pose twists, as one captured hipGraph launch on
+device-resident inputs.  Metric: Mpixel/s = sum over views of W x H per step
+/ step time.
+
+Default workload: the batched configuration (500k Gaussians in a 6x6x3 m
+room, 8 keyframes: 4 at 640x480 and 4 at 320x240 on a 2 m circle looking
+inward, colours and features stored in BF16, FP32 arithmetic), with tile size
+and work chunking picked by the library's autotuner.  The plain FP32
+single-view form (300k Gaussians, 640x480) is measured beside it.  Inputs are
+seeded synthetic scenes shaped like the paper's indoor RGB-D workloads.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes as C
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mpixel/s fwd+bwd (RGB+D+16-d feat), BF16 batched vs FP32 plain; HBM GB/s"
+PEAK_FP32_TFLOPS = 157.3     # MI355X vector FP32 (256 CUs, 2.4 GHz, dual-issue)
+PEAK_HBM_GBS = 8000.0
+
+# Algorithmic FP32 operations of the compositing kernels, per (pixel, list
+# entry) unit, counted from the per-pixel definition (FMA = 2):
+#   evaluation  : offsets 2, quadratic form 8, exp argument 1, exp 1,
+#                 alpha 2, the two cut tests 2                      = 16
+#   forward contribution : T' 2, stop test 1, weight 1, 20 FMAs 40   = 44
+#   backward contribution: 1 - alpha, 1/(1-alpha), T_prev, weight 4,
+#                 g.y 40, dL/dalpha 5, running sum 2, chain to
+#                 mean'/conic/opacity 14, 20 colour partials 20,
+#                 sum of the 26 partials over pixels 26              = 111
+FLOPS_EVAL = 16
+FLOPS_FWD_CONTRIB = 44
+FLOPS_BWD_CONTRIB = 111
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_graph(ctx, P, wl, params, settings, dev, tune, cache=None):
+    import torch
+    from paper_2511_16144_amd import binding as B
+    V = len(wl.cams)
+    outs = []
+    imgs = (B.lgs_images * V)()
+    tgts = (B.lgs_images * V)()
+    keep = []
+    for v, c in enumerate(wl.cams):
+        H, W = c.height, c.width
+        o = {"rgb": torch.empty((3, H, W), device=dev), "depth": torch.empty((H, W), device=dev),
+             "feat": torch.empty((16, H, W), device=dev), "T": torch.empty((H, W), device=dev)}
+        outs.append(o)
+        imgs[v] = B.lgs_images(o["rgb"].data_ptr(), o["depth"].data_ptr(), o["feat"].data_ptr(),
+                               o["T"].data_ptr(), None)
+        t = wl.targets[v]
+        tt = {"rgb": torch.as_tensor(t.rgb).to(dev), "depth": torch.as_tensor(t.depth).to(dev),
+              "feat": torch.as_tensor(t.feat).to(dev)}
+        keep.append(tt)
+        tgts[v] = B.lgs_images(tt["rgb"].data_ptr(), tt["depth"].data_ptr(), tt["feat"].data_ptr(), None, None)
+    n = params["logits"].shape[0]
+    grads = {"means": torch.empty((3, n), device=dev), "log_scales": torch.empty((3, n), device=dev),
+             "quats": torch.empty((4, n), device=dev), "logits": torch.empty((n,), device=dev),
+             "rgb": torch.empty((3, n), device=dev), "feat": torch.empty((16, n), device=dev),
+             "twist": torch.empty((V, 6), device=dev)}
+    gr = B.lgs_grads(*[grads[k].data_ptr() for k in ("means", "log_scales", "quats", "logits", "rgb", "feat",
+                                                    "twist")])
+    g = B.gaussians_c(params["means"], params["log_scales"], params["quats"], params["logits"],
+                      params["rgb"], params["feat"])
+    cams = (B.lgs_camera * V)(*[B.camera_c(c) for c in wl.cams])
+    lw = (C.c_float * 3)(*wl.loss_w)
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    st = settings.to_c()
+    if tune:
+        best = B.lgs_settings()
+        rc = B.lib().lgs_autotune(ctx._h, C.byref(st), C.byref(g), V, cams, tgts, lw, imgs, C.byref(gr), 0,
+                                  stream, cache.encode() if cache else None, C.byref(best))
+        if rc != 0:
+            raise B.LgsError(rc, B.lib().lgs_last_error(ctx._h).decode())
+        st = best
+        st.profile = settings.profile
+    h = C.c_void_p()
+    rc = B.lib().lgs_graph_create(ctx._h, C.byref(st), C.byref(g), V, cams, tgts, lw, imgs, C.byref(gr), 0,
+                                  stream, C.byref(h))
+    if rc != 0:
+        raise B.LgsError(rc, B.lib().lgs_last_error(ctx._h).decode())
+    return h, st, (outs, keep, grads, imgs, tgts, gr, g, cams, lw)
+
+
+def graph_launch(h):
+    import torch
+    from paper_2511_16144_amd import binding as B
+    rc = B.lib().lgs_graph_launch(h, C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if rc != 0:
+        raise RuntimeError(f"graph launch failed: {rc}")
+
+
+def time_workload(ctx, wl, steps, warmup, dev, tune, settings):
+    import torch
+    import paper_2511_16144_amd as P
+    from paper_2511_16144_amd import binding as B
+    dt = torch.bfloat16 if wl.scene.dtype == "bf16" else torch.float32
+    s = wl.scene
+    params = P.params_from_arrays(s.means, s.log_scales, s.quats, s.logits, s.rgb, s.feat, device=dev,
+                                  appearance_dtype=dt)
+    h, st, keep = make_graph(ctx, P, wl, params, settings, dev, tune)
+    try:
+        for _ in range(warmup):
+            graph_launch(h)
+        torch.cuda.synchronize()
+        rc = B.lib().lgs_graph_status(h)
+        if rc != 0:
+            raise RuntimeError(f"graph status {rc}: {B.lib().lgs_last_error(ctx._h).decode()}")
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record()
+        for _ in range(steps):
+            graph_launch(h)
+        e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = e0.elapsed_time(e1) / steps
+        cnt = B.lgs_counts()
+        B.lib().lgs_graph_counts(h, C.byref(cnt))
+        counts = {k: getattr(cnt, k) for k, _ in B.lgs_counts._fields_}
+        stages = None
+        if st.profile:
+            acc = [0.0] * 5
+            buf = (C.c_float * 5)()
+            for _ in range(steps):
+                graph_launch(h)
+                B.lib().lgs_graph_stage_ms(h, buf)
+                for i in range(5):
+                    acc[i] += buf[i]
+            stages = [a / steps for a in acc]
+    finally:
+        torch.cuda.synchronize()
+        B.lib().lgs_graph_destroy(h)
+    return {"ms": ms, "wall_s": wall, "counts": counts, "stages": stages,
+            "settings": {"tile": st.tile, "chunk": st.chunk, "order": st.order}}
+
+
+def cpu_baseline(wl, budget_s=25.0):
+    """The FP64 oracle (forward + autodiff backward) on a bounded sample of
+    the same workload: 64x64 crops of the first view, as many as fit in about
+    `budget_s` seconds, with every host core."""
+    import numpy as np
+    import torch
+    import scenes
+    from oracle import raster_fp64 as R
+    torch.set_num_threads(os.cpu_count() or 1)
+    cam = wl.cams[0]
+    wins = scenes.crop_windows(11, cam, k=4, size=64)
+    done_px = 0
+    t0 = time.perf_counter()
+    n_crops = 0
+    for w in wins:
+        rects = [[w]] + [[] for _ in wl.cams[1:]]
+        ups = scenes.random_upstream(2, [cam], windows=[[w]])
+        R.render(wl.scene, [cam], R.Settings(), rects=[[w]], want_margin=False)
+        R.vjp(wl.scene, [cam], ups, R.Settings(), rects=[[w]])
+        done_px += w[2] * w[3]
+        n_crops += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": done_px / dt / 1e6, "unit": "Mpixel/s", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"{n_crops} crop(s) of 64x64 px of view 0 (forward + backward, FP64, "
+                      f"whole-scene projection included), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="batched", choices=["batched", "plain", "precision", "differentiation"])
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus})",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import scenes
+    import paper_2511_16144_amd as P
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = "cuda:0"
+    cfg = {"batched": 4, "plain": 2, "precision": 3, "differentiation": 5}[args.workload]
+    log(f"[bench] building workload C{cfg}")
+    wl = scenes.make_workload(cfg)
+    ctx = P.Context(0)
+    settings = P.Settings(profile=1)
+    log(f"[bench] timing C{cfg}: {wl.scene.n} Gaussians, {len(wl.cams)} views, {wl.pixels} px")
+    r = time_workload(ctx, wl, args.steps, args.warmup, dev, not args.no_tune, settings)
+    mpx = wl.pixels / (r["ms"] / 1e3) / 1e6
+    c = r["counts"]
+    st = r["stages"]
+    names = ["project+depth sort+scans", "pair emission+tile sort", "forward compositing",
+             "backward compositing", "gradient reduction+projection backward"]
+    stages = {n: round(v, 4) for n, v in zip(names, st)} if st else None
+    # dominant kernel: backward compositing (a single kernel between its events)
+    fl = FLOPS_EVAL * c["bwd_evals"] + FLOPS_BWD_CONTRIB * c["bwd_contrib"]
+    kms = st[3] if st else None
+    achieved = fl / (kms / 1e3) / 1e12 if kms else None
+    roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": (achieved / PEAK_FP32_TFLOPS) if achieved else None, "traffic": None,
+            "kernel": "k_raster_bwd", "kernel_ms": kms,
+            "units": {"bwd_evals": c["bwd_evals"], "bwd_contrib": c["bwd_contrib"]},
+            "flops_per_unit": {"eval": FLOPS_EVAL, "contrib": FLOPS_BWD_CONTRIB}}
+    fwd_fl = FLOPS_EVAL * c["fwd_evals"] + FLOPS_FWD_CONTRIB * c["fwd_contrib"]
+    fwd_tf = fwd_fl / (st[2] / 1e3) / 1e12 if st else None
+    out = {"metric": METRIC, "value": round(mpx, 3), "unit": "Mpixel/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(r["ms"], 4), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic (seeded room-surface scenes shaped like indoor RGB-D keyframes)",
+           "config": {"workload": wl.name, "gaussians": wl.scene.n,
+                      "views": [f"{cc.width}x{cc.height}" for cc in wl.cams],
+                      "appearance_storage": wl.scene.dtype, "loss_w": list(wl.loss_w), **r["settings"],
+                      "parallelism": "single GPU"},
+           "roofline": roof, "stages_ms": stages,
+           "forward_compositing": {"TFLOP/s": fwd_tf, "frac": fwd_tf / PEAK_FP32_TFLOPS if fwd_tf else None},
+           "counts": c}
+    if not args.no_plain and cfg != 2:
+        log("[bench] timing the plain FP32 single-view form (C2)")
+        wl2 = scenes.make_workload(2)
+        r2 = time_workload(ctx, wl2, args.steps, args.warmup, dev, not args.no_tune, P.Settings())
+        out["plain_fp32"] = {"workload": wl2.name, "Mpixel/s": round(wl2.pixels / (r2["ms"] / 1e3) / 1e6, 3),
+                             "ms_per_step": round(r2["ms"], 4), **r2["settings"]}
+        out["batched_bf16_over_plain_fp32"] = round(mpx / out["plain_fp32"]["Mpixel/s"], 3)
+    if not args.no_cpu_baseline:
+        log("[bench] timing the FP64 oracle on the host (bounded sample)")
+        out["cpu_baseline"] = cpu_baseline(wl)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,208 @@
+/*
+ * lego_raster.h -- C ABI of the MI355X (gfx950) differentiable Gaussian
+ * rasterizer: RGB + depth + 16-d language feature, forward and backward.
+ *
+ * What it computes.  LEGO-SLAM (arXiv 2511.16144) renders its
+ * language-embedded Gaussians Theta = {p, q, s, alpha, c, f in R^16}
+ * "following the standard 3DGS pipeline" into an RGB image and a feature map
+ * (Sec. III-B.1), uses the rendered depth in the L1 depth term of its mapping
+ * loss (Sec. III-B.3, Eq. (1)), optimises Theta through the renderer over
+ * several iterations per keyframe (Sec. III-B.3) and refines keyframe poses by
+ * the same rendering loss (Sec. III-B.2).  This library is that renderer and
+ * its exact gradient.  Per pixel (readings where the paper is silent):
+ *   s = exp(log_scale), q normalised, o = sigmoid(logit);
+ *   EWA screen covariance Sigma' = J R_cw R(q) diag(s^2) R(q)^T R_cw^T J^T
+ *     + eps I (J: pinhole Jacobian with the view-angle clamp);
+ *   contributors: m2 = d^T Sigma'^{-1} d <= cutoff2 and
+ *     alpha = min(alpha_max, o exp(-m2/2)) >= alpha_min, in (z, index) order;
+ *   front to back, T' = T (1 - alpha), stop before T' < T_eps,
+ *     Y += alpha T [rgb, z, f];  background 0.
+ *
+ * Conventions shared by every call.
+ *   - All pointers named "device" are HIP device memory owned by the caller;
+ *     the library never frees them.  Structure-of-arrays planes: a field
+ *     written [k][n] is k contiguous planes of n values.
+ *   - Cameras are world->camera (R_cw row-major, t_cw), OpenCV axes (x right,
+ *     y down, z forward); pixel (i, j) is evaluated at its centre (i, j).
+ *   - Every call enqueues work on the given stream and returns; an eager
+ *     forward performs one 4-byte device->host read (the pair count).
+ *   - Errors are returned as lgs_status; details via lgs_last_error().  No
+ *     call throws.  Arguments are validated on the host: NULL pointers,
+ *     n < 0, image sides outside [1, 2048], n_views outside [1, 1024],
+ *     unknown dtype, tile not in {8, 16, 32}, misaligned (< 4-byte) pointers.
+ *   - Gaussians with a non-finite input, a zero quaternion, or camera depth
+ *     <= z_near are culled: no contribution and zero gradient.
+ *   - One context serves one stream at a time; calls on a shared context are
+ *     not thread-safe.
+ */
+#ifndef LEGO_RASTER_H
+#define LEGO_RASTER_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LGS_OK = 0,
+  LGS_ERR_INVALID_ARG = 1,  /* bad argument (see lgs_last_error) */
+  LGS_ERR_HIP = 2,          /* a HIP runtime call failed */
+  LGS_ERR_CAPACITY = 3,     /* pair buffer too small (graph mode) */
+  LGS_ERR_UNSUPPORTED = 4,  /* valid but not supported by this build */
+  LGS_ERR_STATE = 5         /* object used in the wrong state */
+} lgs_status;
+
+typedef enum { LGS_F32 = 0, LGS_BF16 = 1 } lgs_dtype;
+
+/* Pinhole camera and world->camera pose (Sec. III-A: T_k in SE(3)). */
+typedef struct {
+  int32_t width, height;
+  float fx, fy, cx, cy;
+  float R_cw[9];   /* row-major */
+  float t_cw[3];
+} lgs_camera;
+
+/* Rasterizer constants (the paper publishes none; defaults are the readings
+ * listed beside each field) and execution tunables.  Results do not depend on
+ * the tunables: the forward is bitwise identical for every tile size. */
+typedef struct {
+  float z_near;     /* 0.2     near-plane cull */
+  float eps2d;      /* 0.3     px^2 added to Sigma' diagonal */
+  float fov_clamp;  /* 1.3     Jacobian view-angle clamp factor */
+  float alpha_max;  /* 0.99    alpha clamp */
+  float alpha_min;  /* 1/255   smallest alpha that contributes */
+  float T_eps;      /* 1e-4    stop before T' < T_eps */
+  float cutoff2;    /* 9.0     largest m2 that contributes */
+  int32_t tile;     /* 16      binning tile side: 8, 16 or 32 */
+  int32_t chunk;    /* 4       8x8 pixel blocks per work-group (1, 2, 4, 8) */
+  int32_t order;    /* 0       1: work queue in descending list length, 0: raster order */
+  int32_t profile;  /* 0       1: graphs record HIP events around each stage */
+} lgs_settings;
+
+/* Gaussians: SoA planes, n of each (Sec. III-B.1, Theta).  means [3][n],
+ * log_scales [3][n], quats [4][n] (w, x, y, z; need not be unit),
+ * opacity_logits [n] are FP32; rgb [3][n] and feat [16][n] are FP32 or BF16
+ * (appearance_dtype).  All device pointers. */
+typedef struct {
+  int64_t n;
+  const float *means, *log_scales, *quats, *opacity_logits;
+  const void *rgb, *feat;
+  lgs_dtype appearance_dtype;
+} lgs_gaussians;
+
+/* Per-view images, FP32 planes of the view's H x W pixels (device):
+ * rgb [3][H][W], depth [H][W], feat [16][H][W], final_T [H][W].
+ * n_contrib [H][W] (int32, optional, may be NULL) receives each pixel's
+ * contributor count.  As a backward input (dL/dY) rgb/depth/feat hold the
+ * upstream gradients and final_T (dL/dT) may be NULL. */
+typedef struct {
+  float *rgb, *depth, *feat, *final_T;
+  int32_t *n_contrib;
+} lgs_images;
+
+/* Parameter gradients, FP32 SoA planes shaped like the inputs (device):
+ * means [3][n], log_scales [3][n], quats [4][n], opacity_logits [n],
+ * rgb [3][n], feat [16][n] (always FP32, w.r.t. the stored values, summed
+ * over views), and twist [n_views][6] = dL/d(rho, phi) of the left pose
+ * perturbation T_cw <- Exp(xi) T_cw at xi = 0 (may be NULL). */
+typedef struct {
+  float *means, *log_scales, *quats, *opacity_logits, *rgb, *feat;
+  float *twist;
+} lgs_grads;
+
+typedef struct lgs_context lgs_context;
+typedef struct lgs_fwd_state lgs_fwd_state;
+typedef struct lgs_graph lgs_graph;
+
+/* Work counts of a forward (and of its backward once run), for measurement
+ * and tests. */
+typedef struct {
+  int64_t n_visible;    /* visible (view, Gaussian) pairs */
+  int64_t n_pairs;      /* (tile, Gaussian) pairs after binning */
+  int64_t n_slots;      /* (8x8 block, Gaussian) gradient slots */
+  int64_t n_tiles;      /* binning tiles over all views */
+  int64_t n_items;      /* 8x8 blocks (work items) over all views */
+  int64_t fwd_evals;    /* (pixel, list entry) evaluations, forward compositing */
+  int64_t fwd_contrib;  /* ... of which contributed */
+  int64_t bwd_evals;    /* (pixel, list entry) evaluations, backward compositing */
+  int64_t bwd_contrib;  /* ... of which contributed */
+} lgs_counts;
+
+const char *lgs_status_string(lgs_status s);
+/* Last error text of a context (never NULL; "" when none). */
+const char *lgs_last_error(const lgs_context *ctx);
+lgs_settings lgs_default_settings(void);
+
+/* Context: owns the device workspace (records, sort buffers, partials) of
+ * every state it creates.  hip_device is made current by every call. */
+lgs_status lgs_context_create(int hip_device, lgs_context **out);
+void lgs_context_destroy(lgs_context *ctx);
+
+/* Forward render of n_views views (Sec. III-B.1 render of I^ and F_render;
+ * Eq. (1) depth D^).  cams[n_views] and out[n_views] are host arrays of
+ * structs whose image pointers are device memory.  On success *state_out
+ * holds what lgs_backward needs; release it with lgs_state_release.  The
+ * Gaussian arrays must stay unmodified until the backward has run. */
+lgs_status lgs_forward(lgs_context *ctx, const lgs_settings *st,
+                       const lgs_gaussians *g, int32_t n_views,
+                       const lgs_camera *cams, const lgs_images *out,
+                       lgs_fwd_state **state_out, hipStream_t stream);
+
+/* Vector-Jacobian product of the forward that produced `state` (the
+ * gradient step of Sec. III-B.3 map optimisation and of the Sec. III-B.2
+ * pose refinement).  grad_out[n_views] holds dL/dY per view (final_T may be
+ * NULL).  Every plane of `grads` is overwritten.  Deterministic: no
+ * atomics in the gradient reduction. */
+lgs_status lgs_backward(lgs_context *ctx, const lgs_fwd_state *state,
+                        const lgs_gaussians *g, const lgs_images *grad_out,
+                        lgs_grads *grads, hipStream_t stream);
+
+lgs_status lgs_state_counts(const lgs_fwd_state *state, lgs_counts *out);
+lgs_status lgs_state_release(lgs_context *ctx, lgs_fwd_state *state);
+
+/* Whole mapping-loss step as one captured hipGraph: forward, L1 loss
+ * gradient of Eq. (1) without its D-SSIM term (sum over views of
+ * mean|RGB-RGB*| + w_depth mean|D-D*| + w_feat mean|F-F*|, sign(0) = 0,
+ * loss_w = {1, w_depth, w_feat}), backward.  targets[n_views] (device
+ * planes, final_T ignored), out[n_views] and grads are bound at creation;
+ * every launch recomputes them from the current contents of the Gaussian
+ * arrays.  pair_capacity bounds the (tile, Gaussian) pairs; a launch that
+ * would exceed it writes nothing valid and lgs_graph_status then returns
+ * LGS_ERR_CAPACITY (re-create with a larger capacity). */
+lgs_status lgs_graph_create(lgs_context *ctx, const lgs_settings *st,
+                            const lgs_gaussians *g, int32_t n_views,
+                            const lgs_camera *cams, const lgs_images *targets,
+                            const float loss_w[3], const lgs_images *out,
+                            const lgs_grads *grads, int64_t pair_capacity,
+                            hipStream_t stream, lgs_graph **graph_out);
+lgs_status lgs_graph_launch(lgs_graph *graph, hipStream_t stream);
+/* Synchronises with the graph's last launch; LGS_ERR_CAPACITY after an
+ * overflowing launch, else LGS_OK. */
+lgs_status lgs_graph_status(lgs_graph *graph);
+/* Work counts of the graph's last launch (synchronises with it). */
+lgs_status lgs_graph_counts(lgs_graph *graph, lgs_counts *out);
+/* With settings.profile = 1: elapsed milliseconds of the last launch's
+ * stages, ms[0..4] = projection + depth sort + scans, pair emission + tile
+ * sort, forward compositing, backward compositing (with the fused L1
+ * gradient), gradient reduction + projection backward.  Synchronises. */
+lgs_status lgs_graph_stage_ms(lgs_graph *graph, float ms[5]);
+void lgs_graph_destroy(lgs_graph *graph);
+
+/* Autotuner: times the graph step for every (tile, chunk, order) setting on
+ * the given workload and returns the fastest in *best_out (other fields
+ * copied from *st).  With cache_path non-NULL the result is stored in / read
+ * from a small JSON file keyed by the workload's shape. */
+lgs_status lgs_autotune(lgs_context *ctx, const lgs_settings *st,
+                        const lgs_gaussians *g, int32_t n_views,
+                        const lgs_camera *cams, const lgs_images *targets,
+                        const float loss_w[3], const lgs_images *out,
+                        const lgs_grads *grads, int64_t pair_capacity,
+                        hipStream_t stream, const char *cache_path,
+                        lgs_settings *best_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LEGO_RASTER_H */

@@ -1,0 +1,347 @@
+"""ctypes binding of ``liblego_raster.so`` (the C ABI of include/lego_raster.h).
+
+Argument marshalling only: every stage of the render and its gradient runs in
+the library's HIP kernels.  torch provides device memory and the stream.
+There is no CPU fallback: importing this module without the built library
+raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblego_raster.so")
+
+LGS_OK, LGS_ERR_INVALID_ARG, LGS_ERR_HIP, LGS_ERR_CAPACITY, LGS_ERR_UNSUPPORTED, LGS_ERR_STATE = range(6)
+LGS_F32, LGS_BF16 = 0, 1
+
+
+class lgs_camera(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("fx", C.c_float), ("fy", C.c_float),
+                ("cx", C.c_float), ("cy", C.c_float), ("R_cw", C.c_float * 9), ("t_cw", C.c_float * 3)]
+
+
+class lgs_settings(C.Structure):
+    _fields_ = [("z_near", C.c_float), ("eps2d", C.c_float), ("fov_clamp", C.c_float),
+                ("alpha_max", C.c_float), ("alpha_min", C.c_float), ("T_eps", C.c_float),
+                ("cutoff2", C.c_float), ("tile", C.c_int32), ("chunk", C.c_int32), ("order", C.c_int32),
+                ("profile", C.c_int32)]
+
+
+class lgs_gaussians(C.Structure):
+    _fields_ = [("n", C.c_int64), ("means", C.c_void_p), ("log_scales", C.c_void_p),
+                ("quats", C.c_void_p), ("opacity_logits", C.c_void_p), ("rgb", C.c_void_p),
+                ("feat", C.c_void_p), ("appearance_dtype", C.c_int32)]
+
+
+class lgs_images(C.Structure):
+    _fields_ = [("rgb", C.c_void_p), ("depth", C.c_void_p), ("feat", C.c_void_p),
+                ("final_T", C.c_void_p), ("n_contrib", C.c_void_p)]
+
+
+class lgs_grads(C.Structure):
+    _fields_ = [("means", C.c_void_p), ("log_scales", C.c_void_p), ("quats", C.c_void_p),
+                ("opacity_logits", C.c_void_p), ("rgb", C.c_void_p), ("feat", C.c_void_p),
+                ("twist", C.c_void_p)]
+
+
+class lgs_counts(C.Structure):
+    _fields_ = [("n_visible", C.c_int64), ("n_pairs", C.c_int64), ("n_slots", C.c_int64),
+                ("n_tiles", C.c_int64), ("n_items", C.c_int64), ("fwd_evals", C.c_int64),
+                ("fwd_contrib", C.c_int64), ("bwd_evals", C.c_int64), ("bwd_contrib", C.c_int64)]
+
+
+EXPORTS = ["lgs_status_string", "lgs_last_error", "lgs_default_settings", "lgs_context_create",
+           "lgs_context_destroy", "lgs_forward", "lgs_backward", "lgs_state_counts",
+           "lgs_state_release", "lgs_graph_create", "lgs_graph_launch", "lgs_graph_status",
+           "lgs_graph_counts", "lgs_graph_stage_ms", "lgs_graph_destroy", "lgs_autotune"]
+
+
+def load_library(path: str = LIB_PATH) -> C.CDLL:
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} is missing "
+                           "(run __graft_entry__.build() or paper_2511_16144_amd/build_lib.py)")
+    lib = C.CDLL(path)
+    P = C.c_void_p
+    lib.lgs_status_string.restype = C.c_char_p
+    lib.lgs_status_string.argtypes = [C.c_int]
+    lib.lgs_last_error.restype = C.c_char_p
+    lib.lgs_last_error.argtypes = [P]
+    lib.lgs_default_settings.restype = lgs_settings
+    lib.lgs_default_settings.argtypes = []
+    lib.lgs_context_create.restype = C.c_int
+    lib.lgs_context_create.argtypes = [C.c_int, C.POINTER(P)]
+    lib.lgs_context_destroy.restype = None
+    lib.lgs_context_destroy.argtypes = [P]
+    lib.lgs_forward.restype = C.c_int
+    lib.lgs_forward.argtypes = [P, C.POINTER(lgs_settings), C.POINTER(lgs_gaussians), C.c_int32,
+                                C.POINTER(lgs_camera), C.POINTER(lgs_images), C.POINTER(P), P]
+    lib.lgs_backward.restype = C.c_int
+    lib.lgs_backward.argtypes = [P, P, C.POINTER(lgs_gaussians), C.POINTER(lgs_images),
+                                 C.POINTER(lgs_grads), P]
+    lib.lgs_state_counts.restype = C.c_int
+    lib.lgs_state_counts.argtypes = [P, C.POINTER(lgs_counts)]
+    lib.lgs_state_release.restype = C.c_int
+    lib.lgs_state_release.argtypes = [P, P]
+    lib.lgs_graph_create.restype = C.c_int
+    lib.lgs_graph_create.argtypes = [P, C.POINTER(lgs_settings), C.POINTER(lgs_gaussians), C.c_int32,
+                                     C.POINTER(lgs_camera), C.POINTER(lgs_images), C.POINTER(C.c_float),
+                                     C.POINTER(lgs_images), C.POINTER(lgs_grads), C.c_int64, P,
+                                     C.POINTER(P)]
+    lib.lgs_graph_launch.restype = C.c_int
+    lib.lgs_graph_launch.argtypes = [P, P]
+    lib.lgs_graph_status.restype = C.c_int
+    lib.lgs_graph_status.argtypes = [P]
+    lib.lgs_graph_counts.restype = C.c_int
+    lib.lgs_graph_counts.argtypes = [P, C.POINTER(lgs_counts)]
+    lib.lgs_graph_stage_ms.restype = C.c_int
+    lib.lgs_graph_stage_ms.argtypes = [P, C.POINTER(C.c_float)]
+    lib.lgs_graph_destroy.restype = None
+    lib.lgs_graph_destroy.argtypes = [P]
+    lib.lgs_autotune.restype = C.c_int
+    lib.lgs_autotune.argtypes = [P, C.POINTER(lgs_settings), C.POINTER(lgs_gaussians), C.c_int32,
+                                 C.POINTER(lgs_camera), C.POINTER(lgs_images), C.POINTER(C.c_float),
+                                 C.POINTER(lgs_images), C.POINTER(lgs_grads), C.c_int64, P, C.c_char_p,
+                                 C.POINTER(lgs_settings)]
+    return lib
+
+
+_LIB = None
+
+
+def lib() -> C.CDLL:
+    global _LIB
+    if _LIB is None:
+        _LIB = load_library()
+    return _LIB
+
+
+class LgsError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{lib().lgs_status_string(status).decode()}: {msg}")
+        self.status = status
+
+
+@dataclass
+class Settings:
+    z_near: float = 0.2
+    eps2d: float = 0.3
+    fov_clamp: float = 1.3
+    alpha_max: float = 0.99
+    alpha_min: float = 1.0 / 255.0
+    T_eps: float = 1e-4
+    cutoff2: float = 9.0
+    tile: int = 16
+    chunk: int = 4
+    order: int = 0
+    profile: int = 0
+
+    def to_c(self) -> lgs_settings:
+        return lgs_settings(self.z_near, self.eps2d, self.fov_clamp, self.alpha_max, self.alpha_min,
+                            self.T_eps, self.cutoff2, self.tile, self.chunk, self.order, self.profile)
+
+    @staticmethod
+    def from_c(s: lgs_settings) -> "Settings":
+        return Settings(s.z_near, s.eps2d, s.fov_clamp, s.alpha_max, s.alpha_min, s.T_eps, s.cutoff2,
+                        s.tile, s.chunk, s.order, s.profile)
+
+
+def camera_c(cam) -> lgs_camera:
+    """Any object with width, height, fx, fy, cx, cy, R_cw (3x3), t_cw (3)."""
+    R = [float(x) for row in cam.R_cw for x in row]
+    t = [float(x) for x in cam.t_cw]
+    return lgs_camera(int(cam.width), int(cam.height), float(cam.fx), float(cam.fy), float(cam.cx),
+                      float(cam.cy), (C.c_float * 9)(*R), (C.c_float * 3)(*t))
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _check_param(t, rows, n, name, dtypes=(torch.float32,)):
+    if t.dtype not in dtypes or not t.is_cuda or not t.is_contiguous() or tuple(t.shape) != ((rows, n) if rows else (n,)):
+        raise ValueError(f"{name}: expected contiguous CUDA tensor of shape {(rows, n) if rows else (n,)} "
+                         f"and dtype in {dtypes}, got {tuple(t.shape)} {t.dtype}")
+
+
+def gaussians_c(means, log_scales, quats, logits, rgb, feat) -> lgs_gaussians:
+    n = logits.shape[0]
+    _check_param(means, 3, n, "means")
+    _check_param(log_scales, 3, n, "log_scales")
+    _check_param(quats, 4, n, "quats")
+    _check_param(logits, 0, n, "logits")
+    _check_param(rgb, 3, n, "rgb", (torch.float32, torch.bfloat16))
+    _check_param(feat, 16, n, "feat", (torch.float32, torch.bfloat16))
+    if rgb.dtype != feat.dtype:
+        raise ValueError("rgb and feat must share a dtype")
+    dt = LGS_BF16 if rgb.dtype == torch.bfloat16 else LGS_F32
+    return lgs_gaussians(n, _ptr(means), _ptr(log_scales), _ptr(quats), _ptr(logits), _ptr(rgb),
+                         _ptr(feat), dt)
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """One library context (device workspace) on a HIP device."""
+
+    def __init__(self, device: int = 0):
+        self.device = device
+        self._h = C.c_void_p()
+        st = lib().lgs_context_create(device, C.byref(self._h))
+        if st != LGS_OK:
+            raise LgsError(st, "lgs_context_create failed")
+
+    def close(self):
+        if self._h:
+            lib().lgs_context_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _raise(self, st):
+        raise LgsError(st, lib().lgs_last_error(self._h).decode())
+
+    # -- eager forward / backward ------------------------------------------
+    def forward(self, params, cams, settings: Settings | None = None, want_n: bool = False,
+                stream=None):
+        """params: dict of CUDA tensors means [3,N], log_scales [3,N], quats [4,N],
+        logits [N], rgb [3,N], feat [16,N].  Returns (list of per-view dicts
+        rgb [3,H,W], depth [H,W], feat [16,H,W], T [H,W] (and n [H,W] int32),
+        state)."""
+        settings = settings or Settings()
+        g = gaussians_c(params["means"], params["log_scales"], params["quats"], params["logits"],
+                        params["rgb"], params["feat"])
+        dev = params["means"].device
+        V = len(cams)
+        outs, imgs = [], (lgs_images * V)()
+        cams_c = (lgs_camera * V)(*[camera_c(c) for c in cams])
+        for v, c in enumerate(cams):
+            H, W = int(c.height), int(c.width)
+            o = {"rgb": torch.empty((3, H, W), device=dev), "depth": torch.empty((H, W), device=dev),
+                 "feat": torch.empty((16, H, W), device=dev), "T": torch.empty((H, W), device=dev)}
+            if want_n:
+                o["n"] = torch.empty((H, W), device=dev, dtype=torch.int32)
+            imgs[v] = lgs_images(_ptr(o["rgb"]), _ptr(o["depth"]), _ptr(o["feat"]), _ptr(o["T"]),
+                                 _ptr(o.get("n")))
+            outs.append(o)
+        state = C.c_void_p()
+        sc = settings.to_c()
+        st = lib().lgs_forward(self._h, C.byref(sc), C.byref(g), V, cams_c, imgs, C.byref(state),
+                               _stream(stream))
+        if st != LGS_OK:
+            self._raise(st)
+        return outs, State(self, state, V, [(int(c.height), int(c.width)) for c in cams])
+
+    def backward(self, state: "State", params, grad_outs, stream=None) -> dict:
+        """grad_outs: per view dict rgb [3,H,W], depth [H,W], feat [16,H,W],
+        optional T [H,W] (FP32 CUDA).  Returns FP32 gradients shaped like the
+        parameters plus twist [V, 6]."""
+        g = gaussians_c(params["means"], params["log_scales"], params["quats"], params["logits"],
+                        params["rgb"], params["feat"])
+        n = g.n
+        dev = params["means"].device
+        V = state.n_views
+        ups = (lgs_images * V)()
+        keep = []
+        for v, go in enumerate(grad_outs):
+            H, W = state.shapes[v]
+            t = {k: go[k].contiguous().float() for k in ("rgb", "depth", "feat")}
+            if go.get("T") is not None:
+                t["T"] = go["T"].contiguous().float()
+            for k, shp in (("rgb", (3, H, W)), ("depth", (H, W)), ("feat", (16, H, W))):
+                if tuple(t[k].shape) != shp or not t[k].is_cuda:
+                    raise ValueError(f"grad_outs[{v}][{k}] must be a CUDA tensor of shape {shp}")
+            keep.append(t)
+            ups[v] = lgs_images(_ptr(t["rgb"]), _ptr(t["depth"]), _ptr(t["feat"]), _ptr(t.get("T")), None)
+        out = {"means": torch.empty((3, n), device=dev), "log_scales": torch.empty((3, n), device=dev),
+               "quats": torch.empty((4, n), device=dev), "logits": torch.empty((n,), device=dev),
+               "rgb": torch.empty((3, n), device=dev), "feat": torch.empty((16, n), device=dev),
+               "twist": torch.empty((V, 6), device=dev)}
+        gr = lgs_grads(_ptr(out["means"]), _ptr(out["log_scales"]), _ptr(out["quats"]),
+                       _ptr(out["logits"]), _ptr(out["rgb"]), _ptr(out["feat"]), _ptr(out["twist"]))
+        st = lib().lgs_backward(self._h, state.handle, C.byref(g), ups, C.byref(gr), _stream(stream))
+        if st != LGS_OK:
+            self._raise(st)
+        return out
+
+
+class State:
+    def __init__(self, ctx: Context, handle, n_views, shapes):
+        self.ctx, self.handle, self.n_views, self.shapes = ctx, handle, n_views, shapes
+
+    def counts(self) -> dict:
+        c = lgs_counts()
+        lib().lgs_state_counts(self.handle, C.byref(c))
+        return {k: getattr(c, k) for k, _ in lgs_counts._fields_}
+
+    def release(self):
+        if self.handle:
+            lib().lgs_state_release(self.ctx._h, self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
+class RasterFn(torch.autograd.Function):
+    """Differentiable render of every view: returns per view (rgb, depth,
+    feat, T), flattened.  The pose twist input is a [V, 6] zero leaf whose
+    gradient is dL/d(rho, phi) of the left perturbation Exp(xi) T_cw."""
+
+    @staticmethod
+    def forward(ctx, context, cams, settings, means, log_scales, quats, logits, rgb, feat, twist):
+        params = {"means": means, "log_scales": log_scales, "quats": quats, "logits": logits,
+                  "rgb": rgb, "feat": feat}
+        outs, state = context.forward(params, cams, settings)
+        ctx.state = state
+        ctx.context = context
+        ctx.save_for_backward(means, log_scales, quats, logits, rgb, feat)
+        flat = []
+        for o in outs:
+            flat += [o["rgb"], o["depth"], o["feat"], o["T"]]
+        return tuple(flat)
+
+    @staticmethod
+    def backward(ctx, *grads):
+        means, log_scales, quats, logits, rgb, feat = ctx.saved_tensors
+        params = {"means": means, "log_scales": log_scales, "quats": quats, "logits": logits,
+                  "rgb": rgb, "feat": feat}
+        state = ctx.state
+        gos = []
+        for v in range(state.n_views):
+            H, W = state.shapes[v]
+            gr, gd, gf, gt = grads[4 * v: 4 * v + 4]
+            dev = means.device
+            gos.append({"rgb": gr if gr is not None else torch.zeros((3, H, W), device=dev),
+                        "depth": gd if gd is not None else torch.zeros((H, W), device=dev),
+                        "feat": gf if gf is not None else torch.zeros((16, H, W), device=dev),
+                        "T": gt})
+        g = ctx.context.backward(state, params, gos)
+        state.release()
+        return (None, None, None, g["means"], g["log_scales"], g["quats"], g["logits"],
+                g["rgb"].to(rgb.dtype), g["feat"].to(feat.dtype), g["twist"])
+
+
+def render(context: Context, params: dict, cams, settings: Settings | None = None, twist=None):
+    """Autograd-enabled render; returns a list of per-view dicts."""
+    V = len(cams)
+    if twist is None:
+        twist = torch.zeros((V, 6), device=params["means"].device, requires_grad=True)
+    flat = RasterFn.apply(context, cams, settings or Settings(), params["means"], params["log_scales"],
+                          params["quats"], params["logits"], params["rgb"], params["feat"], twist)
+    return [{"rgb": flat[4 * v], "depth": flat[4 * v + 1], "feat": flat[4 * v + 2], "T": flat[4 * v + 3]}
+            for v in range(V)]

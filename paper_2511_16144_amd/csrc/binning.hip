@@ -1,0 +1,348 @@
+// Tile binning (the step between projection and compositing): device-wide
+// exclusive scans, compaction of the visible (view, Gaussian) ids, the
+// load-balanced emission of (tile, Gaussian) pairs in depth order, and the
+// per-tile [start, end) ranges of the tile-sorted pair list.
+//
+// Every kernel reads its element count from device memory, so the same
+// launches serve the eager path (grid sized to the exact count) and the
+// captured graph (grid sized to a capacity; blocks past the count exit).
+#include "lgs_internal.h"
+
+namespace lgs {
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;   // 2048
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x, int lane) {
+  for (int off = 1; off < 64; off <<= 1) {
+    uint32_t y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  return x;
+}
+
+// exclusive scan of one value per thread over a 256-thread block
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* sh, uint32_t& total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t inc = wave_incl_scan(x, lane);
+  if (lane == 63) sh[wave] = inc;
+  __syncthreads();
+  uint32_t wsum = 0, tot = 0;
+  for (int w = 0; w < kScanThreads / 64; ++w) {
+    uint32_t s = sh[w];
+    if (w < wave) wsum += s;
+    tot += s;
+  }
+  __syncthreads();
+  total = tot;
+  return wsum + inc - x;
+}
+
+__device__ __forceinline__ uint32_t scan_in(int mode, const uint32_t* __restrict__ src,
+                                            const uint32_t* __restrict__ idx, int64_t i) {
+  if (mode == SCAN_FLAG_NONZERO) return src[i] != 0u ? 1u : 0u;
+  if (mode == SCAN_VALUE) return src[i];
+  return src[idx[i]];
+}
+
+__device__ __forceinline__ int64_t count_of(const uint32_t* n_dev, int64_t n_max) {
+  return n_dev ? (int64_t)*n_dev : n_max;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_reduce(int mode, const uint32_t* __restrict__ src,
+                                                              const uint32_t* __restrict__ idx,
+                                                              const uint32_t* n_dev, int64_t n_max,
+                                                              uint32_t* __restrict__ bsum) {
+  __shared__ uint32_t sh[4];
+  const int64_t n = count_of(n_dev, n_max);
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  if (base >= n) return;
+  uint32_t s = 0;
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t i = base + (int64_t)k * kScanThreads + threadIdx.x;
+    if (i < n) s += scan_in(mode, src, idx, i);
+  }
+  uint32_t total;
+  block_excl_scan(s, sh, total);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+// one work-group scans the block sums in place (exclusive) and writes total
+__global__ void __launch_bounds__(1024) k_scan_spine(uint32_t* __restrict__ bsum, const uint32_t* n_dev,
+                                                     int64_t n_max, uint32_t* __restrict__ total) {
+  __shared__ uint32_t sh[16];
+  const int64_t n = count_of(n_dev, n_max);
+  const int64_t nb = (n + kScanTile - 1) / kScanTile;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t carry = 0;
+  for (int64_t base = 0; base < nb; base += 1024) {
+    const int64_t i = base + threadIdx.x;
+    uint32_t x = i < nb ? bsum[i] : 0u;
+    uint32_t inc = wave_incl_scan(x, lane);
+    if (lane == 63) sh[wave] = inc;
+    __syncthreads();
+    uint32_t wsum = 0, tot = 0;
+    for (int w = 0; w < 16; ++w) {
+      uint32_t s = sh[w];
+      if (w < wave) wsum += s;
+      tot += s;
+    }
+    if (i < nb) bsum[i] = carry + wsum + inc - x;
+    carry += tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ void __launch_bounds__(kScanThreads) k_scan_down(int mode, const uint32_t* __restrict__ src,
+                                                            const uint32_t* __restrict__ idx,
+                                                            const uint32_t* n_dev, int64_t n_max,
+                                                            const uint32_t* __restrict__ bsum,
+                                                            uint32_t* __restrict__ out) {
+  __shared__ uint32_t sh[4];
+  const int64_t n = count_of(n_dev, n_max);
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  if (base >= n) return;
+  // thread t owns the contiguous items [base + t*8, base + t*8 + 8)
+  uint32_t v[kScanItems];
+  uint32_t s = 0;
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t i = base + (int64_t)threadIdx.x * kScanItems + k;
+    v[k] = i < n ? scan_in(mode, src, idx, i) : 0u;
+    s += v[k];
+  }
+  uint32_t total;
+  uint32_t run = block_excl_scan(s, sh, total) + bsum[blockIdx.x];
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t i = base + (int64_t)threadIdx.x * kScanItems + k;
+    if (i < n) out[i] = run;
+    run += v[k];
+  }
+}
+
+// reduce kernel must sum the same items as the down-sweep: both cover the
+// block's 2048 items, only the assignment to threads differs.
+
+__global__ void __launch_bounds__(256) k_compact(const uint32_t* __restrict__ cnt_t,
+                                                 const uint32_t* __restrict__ cidx,
+                                                 const uint64_t* __restrict__ dkey, int64_t n_rid,
+                                                 uint32_t* __restrict__ ent, uint64_t* __restrict__ keys) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= n_rid) return;
+  if (cnt_t[r] != 0u) {
+    const uint32_t c = cidx[r];
+    ent[c] = (uint32_t)r;
+    keys[c] = dkey[r];
+  }
+}
+
+constexpr int kEmitThreads = 256;
+constexpr int kEmitPerThread = 4;
+constexpr int kEmitTile = kEmitThreads * kEmitPerThread;   // 1024 pairs per block
+
+__device__ __forceinline__ int64_t upper_bound_u32(const uint32_t* a, int64_t n, uint32_t x) {
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    if (a[mid] <= x) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void __launch_bounds__(kEmitThreads) k_emit(
+    const GeomRec* __restrict__ geom, const ViewDesc* __restrict__ views,
+    const uint32_t* __restrict__ srid, const uint32_t* __restrict__ off_t,
+    const Counters* __restrict__ cnt, int64_t cap_pairs, int npad_shift, int tile_shift,
+    uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  __shared__ uint32_t s_off[kEmitTile + 2];
+  __shared__ uint32_t s_rid[kEmitTile + 2];
+  __shared__ int64_t s_j[2];
+  const int64_t M = cnt->n_visible;
+  const int64_t P = cnt->n_pairs;
+  if (P > cap_pairs) return;                 // overflow: nothing valid is written
+  const int64_t p0 = (int64_t)blockIdx.x * kEmitTile;
+  if (p0 >= P) return;
+  const int64_t p1 = (p0 + kEmitTile < P ? p0 + kEmitTile : P) - 1;   // last pair of the block
+  if (threadIdx.x < 2) {
+    const uint32_t x = (uint32_t)(threadIdx.x == 0 ? p0 : p1);
+    s_j[threadIdx.x] = upper_bound_u32(off_t, M, x) - 1;
+  }
+  __syncthreads();
+  const int64_t j0 = s_j[0], j1 = s_j[1];
+  const int nj = (int)(j1 - j0 + 1);         // <= kEmitTile: every entry owns >= 1 pair
+  for (int t = threadIdx.x; t < nj; t += kEmitThreads) {
+    s_off[t] = off_t[j0 + t];
+    s_rid[t] = srid[j0 + t];
+  }
+  __syncthreads();
+  for (int k = 0; k < kEmitPerThread; ++k) {
+    const int64_t pi = p0 + (int64_t)k * kEmitThreads + threadIdx.x;
+    if (pi > p1) break;
+    int lo = 0, hi = nj;                      // largest t with s_off[t] <= pi
+    while (hi - lo > 1) {
+      int mid = (lo + hi) >> 1;
+      if ((int64_t)s_off[mid] <= pi) lo = mid; else hi = mid;
+    }
+    const uint32_t rid = s_rid[lo];
+    const uint32_t local = (uint32_t)(pi - s_off[lo]);
+    const uint32_t bb = geom[rid].bbox;
+    const uint32_t tx0 = (bb & 255u) >> tile_shift, tx1 = ((bb >> 8) & 255u) >> tile_shift;
+    const uint32_t ty0 = ((bb >> 16) & 255u) >> tile_shift;
+    const uint32_t w = tx1 - tx0 + 1u;
+    const uint32_t ty = ty0 + local / w, tx = tx0 + local % w;
+    const ViewDesc& V = views[rid >> npad_shift];
+    keys[pi] = (uint32_t)V.tile_off + ty * (uint32_t)V.tiles_x + tx;
+    vals[pi] = rid;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_fill_u32(uint32_t* __restrict__ p, uint32_t v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void __launch_bounds__(256) k_fill_u8(uint8_t* __restrict__ p, uint8_t v,
+                                                 const uint32_t* n_dev, int64_t n_max) {
+  const int64_t n = count_of(n_dev, n_max);
+  const int64_t i4 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+  if (i4 + 3 < n) {
+    const uint32_t w = (uint32_t)v * 0x01010101u;
+    *(uint32_t*)(p + i4) = w;           // p is 4-byte aligned
+  } else {
+    for (int64_t i = i4; i < n; ++i) p[i] = v;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_tile_ranges(const uint32_t* __restrict__ keys,
+                                                     const Counters* __restrict__ cnt,
+                                                     uint2* __restrict__ ranges) {
+  const int64_t P = cnt->overflow ? 0 : (int64_t)cnt->n_pairs;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= P) return;
+  const uint32_t k = keys[i];
+  if (i == 0 || keys[i - 1] != k) ranges[k].x = (uint32_t)i;
+  if (i == P - 1 || keys[i + 1] != k) ranges[k].y = (uint32_t)(i + 1);
+}
+
+__global__ void k_set_overflow(Counters* cnt, uint64_t cap_pairs, uint64_t cap_slots) {
+  if (threadIdx.x == 0) {
+    const bool ov = (uint64_t)cnt->n_pairs > cap_pairs || (uint64_t)cnt->n_slots > cap_slots;
+    cnt->overflow = ov ? 1u : 0u;
+    cnt->n_pairs_eff = ov ? 0u : cnt->n_pairs;
+    cnt->n_slots_eff = ov ? 0u : cnt->n_slots;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_item_keys(const ViewDesc* __restrict__ views,
+                                                   const uint2* __restrict__ ranges, int tile_shift,
+                                                   const uint32_t* __restrict__ items, int64_t n_items,
+                                                   uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n_items) return;
+  const uint32_t it = items[i];
+  const uint32_t bx = it & 255u, by = (it >> 8) & 255u, v = it >> 16;
+  const ViewDesc& V = views[v];
+  const uint32_t t = (uint32_t)V.tile_off + (by >> tile_shift) * (uint32_t)V.tiles_x + (bx >> tile_shift);
+  const uint2 r = ranges[t];
+  const uint32_t len = r.y - r.x;
+  keys[i] = 65535u - (len < 65535u ? len : 65535u);   // ascending key = descending length
+  vals[i] = it;
+}
+
+__global__ void k_reset_counters(Counters* cnt) {
+  static_assert(sizeof(Counters) / 4 <= 64, "one wave clears the counters");
+  if (threadIdx.x < sizeof(Counters) / 4) ((uint32_t*)cnt)[threadIdx.x] = 0u;
+}
+
+__global__ void __launch_bounds__(256) k_slot_bases(const uint32_t* __restrict__ ent,
+                                                    const uint32_t* __restrict__ slot_off,
+                                                    const Counters* __restrict__ cnt,
+                                                    uint32_t* __restrict__ slot_base) {
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c >= (int64_t)cnt->n_visible) return;
+  slot_base[ent[c]] = slot_off[c];
+}
+
+}  // namespace
+
+size_t scan_temp_bytes(int64_t n) {
+  const int64_t nb = (n + kScanTile - 1) / kScanTile;
+  return (size_t)(nb > 0 ? nb : 1) * sizeof(uint32_t);
+}
+
+void launch_scan(int mode, const uint32_t* src, const uint32_t* idx, uint32_t* out, uint32_t* total,
+                 const uint32_t* n_dev, int64_t n_max, void* temp, hipStream_t s) {
+  const int64_t nb = (n_max + kScanTile - 1) / kScanTile;
+  uint32_t* bsum = (uint32_t*)temp;
+  if (nb > 0)
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, mode, src, idx,
+                       n_dev, n_max, bsum);
+  hipLaunchKernelGGL(k_scan_spine, dim3(1), dim3(1024), 0, s, bsum, n_dev, n_max, total);
+  if (nb > 0)
+    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanThreads), 0, s, mode, src, idx,
+                       n_dev, n_max, (const uint32_t*)bsum, out);
+}
+
+void launch_compact(const uint32_t* cnt_t, const uint32_t* cidx, const uint64_t* dkey, int64_t n_rid,
+                    uint32_t* ent, uint64_t* keys, hipStream_t s) {
+  if (n_rid <= 0) return;
+  hipLaunchKernelGGL(k_compact, dim3((unsigned)((n_rid + 255) / 256)), dim3(256), 0, s, cnt_t, cidx,
+                     dkey, n_rid, ent, keys);
+}
+
+void launch_emit(const GeomRec* geom, const ViewDesc* views, const uint32_t* srid, const uint32_t* off_t,
+                 const Counters* cnt, int64_t pair_grid_max, int64_t cap_pairs, int npad_shift,
+                 int tile_shift, uint32_t* keys, uint32_t* vals, hipStream_t s) {
+  const int64_t blocks = (pair_grid_max + kEmitTile - 1) / kEmitTile;
+  if (blocks <= 0) return;
+  hipLaunchKernelGGL(k_emit, dim3((unsigned)blocks), dim3(kEmitThreads), 0, s, geom, views, srid, off_t,
+                     cnt, cap_pairs, npad_shift, tile_shift, keys, vals);
+}
+
+void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, v, n);
+}
+
+void launch_fill_u8(uint8_t* p, uint8_t v, const uint32_t* n_dev, int64_t n_max, hipStream_t s) {
+  if (n_max <= 0) return;
+  const int64_t blocks = (n_max + 1023) / 1024;
+  hipLaunchKernelGGL(k_fill_u8, dim3((unsigned)blocks), dim3(256), 0, s, p, v, n_dev, n_max);
+}
+
+void launch_tile_ranges(const uint32_t* keys, const Counters* cnt, int64_t grid_max, uint2* ranges,
+                        hipStream_t s) {
+  if (grid_max <= 0) return;
+  hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)((grid_max + 255) / 256)), dim3(256), 0, s, keys,
+                     cnt, ranges);
+}
+
+void launch_set_overflow(Counters* cnt, uint64_t cap_pairs, uint64_t cap_slots, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_overflow, dim3(1), dim3(64), 0, s, cnt, cap_pairs, cap_slots);
+}
+
+uint32_t* launch_order_items(const ViewDesc* views, const uint2* ranges, int tile_shift, const uint32_t* items,
+                             int64_t n_items, uint32_t* keys_a, uint32_t* items_a, uint32_t* keys_b,
+                             uint32_t* items_b, void* radix_temp, hipStream_t s) {
+  if (n_items <= 0) return items_a;
+  hipLaunchKernelGGL(k_item_keys, dim3((unsigned)((n_items + 255) / 256)), dim3(256), 0, s, views, ranges,
+                     tile_shift, items, n_items, keys_a, items_a);
+  bool alt = false;
+  radix_sort_u32(keys_a, items_a, keys_b, items_b, nullptr, n_items, 0, 16, radix_temp, s, &alt);
+  return alt ? items_b : items_a;
+}
+
+void launch_reset_counters(Counters* cnt, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, cnt);
+}
+
+void launch_slot_bases(const uint32_t* ent, const uint32_t* slot_off, const Counters* cnt,
+                       int64_t grid_max, uint32_t* slot_base, hipStream_t s) {
+  if (grid_max <= 0) return;
+  hipLaunchKernelGGL(k_slot_bases, dim3((unsigned)((grid_max + 255) / 256)), dim3(256), 0, s, ent,
+                     slot_off, cnt, slot_base);
+}
+
+}  // namespace lgs

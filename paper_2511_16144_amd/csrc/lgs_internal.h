@@ -1,0 +1,152 @@
+// Internal declarations shared by the HIP translation units of the
+// rasterizer: device-side records, per-view descriptors, launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+namespace lgs {
+
+// Pixel blocks are 8x8: one wave64 renders one block, one pixel per lane.
+constexpr int kBlock = 8;
+constexpr int kMaxSide = 2048;          // 8-bit block coordinates in records
+constexpr int kChannels = 20;           // RGB 3 + depth 1 + feature 16
+constexpr int kPartials = 26;           // mu' 2, conic 3, opacity 1, y 20
+
+// Per-view constants, shared by every stage (device array of n_views).
+struct ViewDesc {
+  double fx, fy, cx, cy;
+  double R[9], t[3];
+  double limx, limy;          // Jacobian clamp limits on x/z, y/z
+  int32_t W, H;
+  int32_t blocks_x, blocks_y; // 8x8 blocks
+  int32_t tiles_x, tiles_y;   // binning tiles
+  int32_t tile_off;           // first global tile id of this view
+  int32_t item_off;           // first work item (8x8 block) of this view
+  int32_t pix_off;            // first pixel of this view in packed state
+  int32_t pad;
+};
+
+// Output / upstream image pointers of one view.
+struct ViewImages {
+  float *rgb, *depth, *feat, *T;
+  int32_t *n_contrib;
+};
+
+// Screen-space record of one visible (view, Gaussian), 32 bytes, read by the
+// compositing kernels through scalar loads (wave-uniform).
+//   mx, my : mean' relative to the pixel origin (8 bx0, 8 by0) of its bbox
+//   qa, qb2, qc : conic (Q_xx, 2 Q_xy, Q_yy)
+//   o      : opacity
+//   z      : camera depth (the depth channel value)
+//   bbox   : block rectangle bx0 | bx1 << 8 | by0 << 16 | by1 << 24 (inclusive)
+struct __attribute__((aligned(32))) GeomRec {
+  float mx, my, qa, qb2, qc, o, z;
+  uint32_t bbox;
+};
+
+struct Settings {
+  float z_near, eps2d, fov_clamp, alpha_max, alpha_min, T_eps, cutoff2;
+  int32_t tile, tile_shift;   // tile side and log2(tile / 8)
+};
+
+// Device-resident counters of one forward (written by kernels, read by
+// kernels; the host reads n_pairs in eager mode).
+struct Counters {
+  uint32_t n_visible;   // M
+  uint32_t n_pairs;     // P
+  uint32_t n_slots;     // S
+  uint32_t overflow;    // set when P exceeds the pair capacity
+  uint32_t work_next;   // persistent-kernel work counter (forward)
+  uint32_t work_next_b; // persistent-kernel work counter (backward)
+  uint32_t n_pairs_eff; // n_pairs, or 0 after an overflow
+  uint32_t n_slots_eff; // n_slots, or 0 after an overflow
+  // work actually done by the compositing kernels (one atomic per work item):
+  // (pixel, entry) evaluations and contributions, forward and backward
+  unsigned long long fwd_evals, fwd_contrib, bwd_evals, bwd_contrib;
+};
+
+// ---------------------------------------------------------------------------
+// launchers (each defined next to its kernels)
+// ---------------------------------------------------------------------------
+// projection (K1)
+void launch_project(const Settings& st, const ViewDesc* views, int n_views,
+                    const float* means, const float* log_scales, const float* quats,
+                    const float* logits, const void* rgb, const void* feat, int app_bf16,
+                    int64_t n, uint32_t npad_shift,
+                    GeomRec* geom, uint32_t* cnt_t, uint32_t* cnt_b, uint64_t* dkey,
+                    void* app, hipStream_t s);
+
+// scans
+size_t scan_temp_bytes(int64_t n);
+enum ScanInput { SCAN_FLAG_NONZERO = 0, SCAN_VALUE = 1, SCAN_GATHER = 2 };
+// out[i] = exclusive prefix of in(i); total written to *total.
+// in(i) = (src[i] != 0) / src[i] / src[idx[i]] by mode; n read from *n_dev
+// when n_dev != nullptr (n_max bounds the grid), else n_max.
+void launch_scan(int mode, const uint32_t* src, const uint32_t* idx, uint32_t* out,
+                 uint32_t* total, const uint32_t* n_dev, int64_t n_max,
+                 void* temp, hipStream_t s);
+
+// compaction of visible (view, Gaussian) ids
+void launch_compact(const uint32_t* cnt_t, const uint32_t* cidx, const uint64_t* dkey,
+                    int64_t n_rid, uint32_t* ent, uint64_t* keys, hipStream_t s);
+
+// pair emission (load-balanced over pairs), tile ranges
+void launch_emit(const GeomRec* geom, const ViewDesc* views, const uint32_t* srid,
+                 const uint32_t* off_t, const Counters* cnt, int64_t pair_grid_max,
+                 int64_t cap_pairs, int npad_shift, int tile_shift,
+                 uint32_t* keys, uint32_t* vals, hipStream_t s);
+void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+void launch_fill_u8(uint8_t* p, uint8_t v, const uint32_t* n_dev, int64_t n_max, hipStream_t s);
+void launch_tile_ranges(const uint32_t* keys, const Counters* cnt, int64_t grid_max,
+                        uint2* ranges, hipStream_t s);
+void launch_set_overflow(Counters* cnt, uint64_t cap_pairs, uint64_t cap_slots, hipStream_t s);
+void launch_reset_counters(Counters* cnt, hipStream_t s);
+void launch_slot_bases(const uint32_t* ent, const uint32_t* slot_off, const Counters* cnt,
+                       int64_t grid_max, uint32_t* slot_base, hipStream_t s);
+
+// radix sort (LSD, 8-bit digits, stable)
+size_t radix_temp_bytes(int64_t n_max);
+void radix_sort_u32(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,
+                    const uint32_t* n_dev, int64_t n_max, int begin_bit, int end_bit,
+                    void* temp, hipStream_t s, bool* result_in_alt);
+void radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
+                    const uint32_t* n_dev, int64_t n_max, int begin_bit, int end_bit,
+                    void* temp, hipStream_t s, bool* result_in_alt);
+
+// work queue ordering (blocks by descending tile-list length)
+// work items ordered by descending length of their tile's list (stable);
+// returns the buffer holding the result (items_a or items_b)
+uint32_t* launch_order_items(const ViewDesc* views, const uint2* ranges, int tile_shift,
+                             const uint32_t* items, int64_t n_items, uint32_t* keys_a,
+                             uint32_t* items_a, uint32_t* keys_b, uint32_t* items_b,
+                             void* radix_temp, hipStream_t s);
+
+// compositing
+void launch_raster_fwd(const Settings& st, const ViewDesc* views, const ViewImages* out,
+                       const uint2* ranges, const uint32_t* vals, const GeomRec* geom,
+                       const void* app, int app_bf16, uint32_t npad_mask,
+                       const uint32_t* items, int64_t n_items, Counters* cnt, int waves_per_group,
+                       int32_t* last_idx, float* T_state, hipStream_t s);
+void launch_raster_bwd(const Settings& st, const ViewDesc* views, const ViewImages* upstream,
+                       const ViewImages* fwd_out, const ViewImages* targets, const float* loss_w,
+                       const uint2* ranges, const uint32_t* vals, const GeomRec* geom,
+                       const void* app, int app_bf16, uint32_t npad_mask,
+                       const uint32_t* items, int64_t n_items, Counters* cnt, int waves_per_group,
+                       const int32_t* last_idx, const float* T_state, const uint32_t* slot_base,
+                       float* partials, uint8_t* mask, hipStream_t s);
+
+// gradient reduction and projection backward
+void launch_seg_reduce(const uint32_t* ent, const uint32_t* slot_base, const uint32_t* cnt_b,
+                       const float* partials, const uint8_t* mask, const Counters* cnt,
+                       int64_t grid_max, float* grad2d, hipStream_t s);
+size_t twist_temp_bytes(int64_t n, int n_views);
+void launch_project_bwd(const Settings& st, const ViewDesc* views, int n_views,
+                        const float* means, const float* log_scales, const float* quats,
+                        const float* logits, int64_t n, uint32_t npad_shift, const Counters* cnt,
+                        const uint32_t* cnt_t, const uint32_t* cidx, const float* grad2d,
+                        float* g_means, float* g_ls, float* g_q, float* g_logit,
+                        float* g_rgb, float* g_feat, float* twist, void* temp,
+                        hipStream_t s);
+
+}  // namespace lgs

@@ -1,0 +1,427 @@
+// Per-pixel compositing of RGB + depth + 16-d feature (forward) and its
+// reverse-order backward, plus the per-Gaussian segmented reduction of the
+// backward's partial sums.
+//
+// Paper: Sec. III-B.1 renders the image and the feature map "following the
+// standard 3DGS pipeline"; Eq. (1) uses the rendered depth; Sec. III-B.3
+// optimises the Gaussians through this renderer.  Per pixel, front to back
+// over the Gaussians of its tile in (depth, index) order:
+//   alpha = min(alpha_max, o exp(-m2/2)), skipped unless m2 <= cutoff2 and
+//   alpha >= alpha_min; T' = T (1 - alpha); stop before T' < T_eps;
+//   Y += alpha T [r, g, b, z, f0..f15]; T = T'.
+//
+// Execution.  One wave64 renders one 8x8 pixel block (one pixel per lane)
+// and walks the list of the binning tile that holds the block.  Everything a
+// list entry carries is wave-uniform, so it is fetched with scalar loads into
+// SGPRs and used directly as VALU operands: no LDS staging and no per-lane
+// gathers.  An entry whose pixel box misses the block is skipped on the
+// scalar unit; the wave leaves the list as soon as a ballot shows every lane
+// finished.  Waves pop blocks from a device work counter (persistent grid).
+//
+// Backward.  Each wave restarts from the last contributor of its pixels and
+// walks the list backwards, recovering T before each entry as T / (1 - alpha)
+// and the weighted sum of what lies behind as a single running scalar.  The
+// 26 per-lane partial derivatives of an entry (mean' 2, conic 3, opacity 1,
+// colour/depth/feature 20) are summed over the wave by a butterfly
+// transpose-reduction and written to the entry's own (Gaussian, block) slot;
+// a segmented reduction over each Gaussian's slots then forms its gradient.
+// No atomics: results are deterministic run to run.
+#include "lgs_internal.h"
+
+namespace lgs {
+namespace {
+
+// The forward and the backward evaluate an entry with this one function so
+// that their discrete decisions agree bit for bit.
+struct Eval {
+  float m2, G, araw, alpha;
+  bool pass;
+};
+
+__device__ __forceinline__ Eval eval_entry(float dx, float dy, float qa, float qb2, float qc, float o,
+                                           float cutoff2, float alpha_max, float alpha_min) {
+#pragma clang fp contract(off)
+  Eval e;
+  const float t1 = qc * dy;
+  const float t2 = t1 * dy;
+  const float t3 = qb2 * dx;
+  const float t4 = __builtin_fmaf(t3, dy, t2);
+  const float t5 = qa * dx;
+  e.m2 = __builtin_fmaf(t5, dx, t4);
+  e.G = __builtin_amdgcn_exp2f(e.m2 * -0.72134752044448170f);   // exp(-m2/2)
+  e.araw = o * e.G;
+  e.alpha = fminf(e.araw, alpha_max);
+  e.pass = (e.m2 <= cutoff2) && (e.alpha >= alpha_min);
+  return e;
+}
+
+__device__ __forceinline__ bool block_in_bbox(uint32_t bb, uint32_t bx, uint32_t by) {
+  return bx >= (bb & 255u) && bx <= ((bb >> 8) & 255u) && by >= ((bb >> 16) & 255u) && by <= (bb >> 24);
+}
+
+// Appearance of a Gaussian as the 20-vector [r, g, b, (z), f0..f15]; slot 3
+// is filled by the caller with the view's depth.
+template <bool BF16>
+__device__ __forceinline__ void load_y(const void* __restrict__ app, uint32_t g, float y[20]) {
+  if (BF16) {
+    const uint32_t* a = (const uint32_t*)app + (size_t)g * 10;
+    uint32_t w[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) w[k] = a[k];
+    y[0] = __uint_as_float(w[0] << 16);
+    y[1] = __uint_as_float(w[0] & 0xffff0000u);
+    y[2] = __uint_as_float(w[1] << 16);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      y[4 + 2 * k] = __uint_as_float(w[2 + k] << 16);
+      y[5 + 2 * k] = __uint_as_float(w[2 + k] & 0xffff0000u);
+    }
+  } else {
+    const float* a = (const float*)app + (size_t)g * 20;
+#pragma unroll
+    for (int k = 0; k < 20; ++k) y[k] = a[k];
+  }
+}
+
+__device__ __forceinline__ uint32_t pop_item(uint32_t* counter, int lane) {
+  uint32_t it = 0;
+  if (lane == 0) it = atomicAdd(counter, 1u);
+  return __builtin_amdgcn_readfirstlane(it);
+}
+
+template <bool BF16>
+__global__ void __launch_bounds__(256) k_raster_fwd(
+    Settings st, const ViewDesc* __restrict__ views, const ViewImages* __restrict__ out,
+    const uint2* __restrict__ ranges, const uint32_t* __restrict__ vals,
+    const GeomRec* __restrict__ geom, const void* __restrict__ app, uint32_t npad_mask,
+    const uint32_t* __restrict__ items, uint32_t n_items, Counters* __restrict__ cnt,
+    int32_t* __restrict__ last_idx, float* __restrict__ T_state) {
+  const int lane = threadIdx.x & 63;
+  if (cnt->overflow) return;
+  for (;;) {
+    const uint32_t it = pop_item(&cnt->work_next, lane);
+    if (it >= n_items) break;
+    const uint32_t item = items[it];
+    const uint32_t bx = item & 255u, by = (item >> 8) & 255u, v = item >> 16;
+    const ViewDesc* V = views + v;
+    const int W = V->W, H = V->H;
+    const int px = (int)bx * kBlock + (lane & 7), py = (int)by * kBlock + (lane >> 3);
+    const bool inside = px < W && py < H;
+    const uint32_t tile = (uint32_t)V->tile_off + (by >> st.tile_shift) * (uint32_t)V->tiles_x +
+                          (bx >> st.tile_shift);
+    const uint2 r = ranges[tile];
+    float T = 1.f;
+    float acc[20];
+#pragma unroll
+    for (int c = 0; c < 20; ++c) acc[c] = 0.f;
+    int32_t last = -1, ncon = 0;
+    bool done = !inside;
+    uint64_t n_eval = 0, n_con = 0;
+    for (uint32_t k = r.x; k < r.y; ++k) {
+      const uint64_t live = __builtin_amdgcn_ballot_w64(!done);
+      if (live == 0ull) break;
+      const uint32_t rid = vals[k];
+      const GeomRec gr = geom[rid];
+      if (!block_in_bbox(gr.bbox, bx, by)) continue;
+      n_eval += (uint64_t)__popcll(live);
+      const float dx = (float)(px - 8 * (int)(gr.bbox & 255u)) - gr.mx;
+      const float dy = (float)(py - 8 * (int)((gr.bbox >> 16) & 255u)) - gr.my;
+      const Eval e = eval_entry(dx, dy, gr.qa, gr.qb2, gr.qc, gr.o, st.cutoff2, st.alpha_max, st.alpha_min);
+      bool con = !done && e.pass;
+      const float Tn = T * (1.f - e.alpha);
+      const bool term = con && (Tn < st.T_eps);
+      done = done || term;
+      con = con && !term;
+      const uint64_t cmask = __builtin_amdgcn_ballot_w64(con);
+      if (cmask == 0ull) continue;
+      n_con += (uint64_t)__popcll(cmask);
+      float y[20];
+      load_y<BF16>(app, rid & npad_mask, y);
+      y[3] = gr.z;
+      const float w = con ? e.alpha * T : 0.f;
+#pragma unroll
+      for (int c = 0; c < 20; ++c) acc[c] = __builtin_fmaf(w, y[c], acc[c]);
+      T = con ? Tn : T;
+      last = con ? (int32_t)k : last;
+      ncon += con ? 1 : 0;
+    }
+    if (inside) {
+      const ViewImages o = out[v];
+      const size_t HW = (size_t)W * H, p = (size_t)py * W + px;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) o.rgb[c * HW + p] = acc[c];
+      o.depth[p] = acc[3];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) o.feat[c * HW + p] = acc[4 + c];
+      o.T[p] = T;
+      if (o.n_contrib) o.n_contrib[p] = ncon;
+      last_idx[(size_t)V->pix_off + p] = last;
+      T_state[(size_t)V->pix_off + p] = T;
+    }
+    if (lane == 0) {
+      atomicAdd(&cnt->fwd_evals, (unsigned long long)n_eval);
+      atomicAdd(&cnt->fwd_contrib, (unsigned long long)n_con);
+    }
+  }
+}
+
+// Butterfly transpose-reduction: on entry every lane holds v[0..31]; on exit
+// lanes 2i and 2i+1 hold the wave sum of value i (i < 32) in v[0].
+__device__ __forceinline__ float transpose_reduce32(float v[32], int lane) {
+#pragma unroll
+  for (int step = 0; step < 5; ++step) {
+    const int half = 16 >> step;
+    const int mask = 32 >> step;
+    const bool hi = (lane & mask) != 0;
+#pragma unroll
+    for (int i = 0; i < half; ++i) {
+      const float send = hi ? v[i] : v[half + i];
+      const float keep = hi ? v[half + i] : v[i];
+      v[i] = keep + __shfl_xor(send, mask, 64);
+    }
+  }
+  return v[0] + __shfl_xor(v[0], 1, 64);
+}
+
+__device__ __forceinline__ int wave_max_i32(int x) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) x = max(x, __shfl_xor(x, off, 64));
+  return x;
+}
+
+template <bool BF16, bool FUSED_L1>
+__global__ void __launch_bounds__(256) k_raster_bwd(
+    Settings st, const ViewDesc* __restrict__ views, const ViewImages* __restrict__ upstream,
+    const ViewImages* __restrict__ fwd_out, const ViewImages* __restrict__ targets,
+    const float* __restrict__ loss_w, const uint2* __restrict__ ranges,
+    const uint32_t* __restrict__ vals, const GeomRec* __restrict__ geom,
+    const void* __restrict__ app, uint32_t npad_mask, const uint32_t* __restrict__ items,
+    uint32_t n_items, Counters* __restrict__ cnt, const int32_t* __restrict__ last_idx,
+    const float* __restrict__ T_state, const uint32_t* __restrict__ slot_base,
+    float* __restrict__ partials, uint8_t* __restrict__ mask) {
+  const int lane = threadIdx.x & 63;
+  if (cnt->overflow) return;
+  for (;;) {
+    const uint32_t it = pop_item(&cnt->work_next_b, lane);
+    if (it >= n_items) break;
+    const uint32_t item = items[it];
+    const uint32_t bx = item & 255u, by = (item >> 8) & 255u, v = item >> 16;
+    const ViewDesc* V = views + v;
+    const int W = V->W, H = V->H;
+    const int px = (int)bx * kBlock + (lane & 7), py = (int)by * kBlock + (lane >> 3);
+    const bool inside = px < W && py < H;
+    const size_t HW = (size_t)W * H, p = (size_t)py * W + px;
+    int32_t last = -1;
+    float Tfin = 1.f, gT = 0.f;
+    float g[20];
+#pragma unroll
+    for (int c = 0; c < 20; ++c) g[c] = 0.f;
+    if (inside) {
+      last = last_idx[(size_t)V->pix_off + p];
+      Tfin = T_state[(size_t)V->pix_off + p];
+      if (FUSED_L1) {
+        const ViewImages Y = fwd_out[v], Yt = targets[v];
+        const float s_rgb = loss_w[0] / (3.f * (float)HW), s_d = loss_w[1] / (float)HW;
+        const float s_f = loss_w[2] / (16.f * (float)HW);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const float d = Y.rgb[c * HW + p] - Yt.rgb[c * HW + p];
+          g[c] = d > 0.f ? s_rgb : (d < 0.f ? -s_rgb : 0.f);
+        }
+        {
+          const float d = Y.depth[p] - Yt.depth[p];
+          g[3] = d > 0.f ? s_d : (d < 0.f ? -s_d : 0.f);
+        }
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          const float d = Y.feat[c * HW + p] - Yt.feat[c * HW + p];
+          g[4 + c] = d > 0.f ? s_f : (d < 0.f ? -s_f : 0.f);
+        }
+      } else {
+        const ViewImages U = upstream[v];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) g[c] = U.rgb[c * HW + p];
+        g[3] = U.depth[p];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) g[4 + c] = U.feat[c * HW + p];
+        if (U.T) gT = U.T[p];
+      }
+    }
+    const int kmax = wave_max_i32(last);
+    if (kmax < 0) continue;
+    const uint32_t tile = (uint32_t)V->tile_off + (by >> st.tile_shift) * (uint32_t)V->tiles_x +
+                          (bx >> st.tile_shift);
+    const uint32_t kbeg = ranges[tile].x;
+    const float gTT = gT * Tfin;
+    float Tc = Tfin, sB = 0.f;
+    uint64_t n_eval = 0, n_con = 0;
+    for (int k = kmax; k >= (int)kbeg; --k) {
+      const uint32_t rid = vals[k];
+      const GeomRec gr = geom[rid];
+      if (!block_in_bbox(gr.bbox, bx, by)) continue;
+      n_eval += (uint64_t)__popcll(__builtin_amdgcn_ballot_w64(k <= last));
+      const int bx0 = (int)(gr.bbox & 255u), by0 = (int)((gr.bbox >> 16) & 255u);
+      const float dx = (float)(px - 8 * bx0) - gr.mx;
+      const float dy = (float)(py - 8 * by0) - gr.my;
+      const Eval e = eval_entry(dx, dy, gr.qa, gr.qb2, gr.qc, gr.o, st.cutoff2, st.alpha_max, st.alpha_min);
+      const bool con = (k <= last) && e.pass;
+      const uint64_t cmask = __builtin_amdgcn_ballot_w64(con);
+      if (cmask == 0ull) continue;
+      n_con += (uint64_t)__popcll(cmask);
+      float y[20];
+      load_y<BF16>(app, rid & npad_mask, y);
+      y[3] = gr.z;
+      float vv[32];
+      {
+        const float rinv = __builtin_amdgcn_rcpf(1.f - e.alpha);
+        const float Tp = Tc * rinv;
+        const float w = e.alpha * Tp;
+        float gy = 0.f;
+#pragma unroll
+        for (int c = 0; c < 20; ++c) gy = __builtin_fmaf(g[c], y[c], gy);
+        const float dal = Tp * gy - (sB + gTT) * rinv;
+        const float wc = con ? w : 0.f;
+        sB = con ? __builtin_fmaf(w, gy, sB) : sB;
+        Tc = con ? Tp : Tc;
+        const float dgeo = (con && !(e.araw > st.alpha_max)) ? dal : 0.f;
+        const float dm2 = dgeo * (-0.5f * e.alpha);
+        vv[0] = -dm2 * (2.f * gr.qa * dx + gr.qb2 * dy);
+        vv[1] = -dm2 * (gr.qb2 * dx + 2.f * gr.qc * dy);
+        vv[2] = dm2 * dx * dx;
+        vv[3] = dm2 * 2.f * dx * dy;
+        vv[4] = dm2 * dy * dy;
+        vv[5] = dgeo * e.G;
+#pragma unroll
+        for (int c = 0; c < 20; ++c) vv[6 + c] = wc * g[c];
+#pragma unroll
+        for (int c = 26; c < 32; ++c) vv[c] = 0.f;
+      }
+      const float s = transpose_reduce32(vv, lane);
+      const uint32_t bb = gr.bbox;
+      const uint32_t bw = ((bb >> 8) & 255u) - (bb & 255u) + 1u;
+      const uint32_t slot = slot_base[rid] + (by - (uint32_t)by0) * bw + (bx - (uint32_t)bx0);
+      const int idx = lane >> 1;
+      if ((lane & 1) == 0 && idx < kPartials) partials[(size_t)slot * kPartials + idx] = s;
+      if (lane == 0) mask[slot] = 1;
+    }
+    if (lane == 0) {
+      atomicAdd(&cnt->bwd_evals, (unsigned long long)n_eval);
+      atomicAdd(&cnt->bwd_contrib, (unsigned long long)n_con);
+    }
+  }
+}
+
+// One wave per visible (view, Gaussian): sum its valid slots, fixed order.
+__global__ void __launch_bounds__(256) k_seg_reduce(const uint32_t* __restrict__ ent,
+                                                    const uint32_t* __restrict__ slot_base,
+                                                    const uint32_t* __restrict__ cnt_b,
+                                                    const float* __restrict__ partials,
+                                                    const uint8_t* __restrict__ mask,
+                                                    const Counters* __restrict__ cnt,
+                                                    float* __restrict__ grad2d) {
+  const int lane = threadIdx.x & 63;
+  const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (cnt->overflow || c >= (int64_t)cnt->n_visible) return;
+  const uint32_t rid = ent[c];
+  const uint32_t base = slot_base[rid], nb = cnt_b[rid];
+  float vv[32];
+#pragma unroll
+  for (int i = 0; i < 32; ++i) vv[i] = 0.f;
+  for (uint32_t s = lane; s < nb; s += 64) {
+    if (mask[base + s]) {
+      const float* pp = partials + (size_t)(base + s) * kPartials;
+#pragma unroll
+      for (int i = 0; i < kPartials; ++i) vv[i] += pp[i];
+    }
+  }
+  const float tot = transpose_reduce32(vv, lane);
+  const int idx = lane >> 1;
+  if ((lane & 1) == 0 && idx < kPartials) grad2d[c * kPartials + idx] = tot;
+}
+
+}  // namespace
+
+void launch_raster_fwd(const Settings& st, const ViewDesc* views, const ViewImages* out, const uint2* ranges,
+                       const uint32_t* vals, const GeomRec* geom, const void* app, int app_bf16,
+                       uint32_t npad_mask, const uint32_t* items, int64_t n_items, Counters* cnt,
+                       int waves_per_group, int32_t* last_idx, float* T_state, hipStream_t s) {
+  if (n_items <= 0) return;
+  const int threads = 64 * waves_per_group;
+  int dev = 0, cus = 256;
+  hipGetDevice(&dev);
+  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  int occ = 1;
+  if (app_bf16)
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_raster_fwd<true>, threads, 0);
+  else
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_raster_fwd<false>, threads, 0);
+  int64_t grid = (int64_t)cus * (occ > 0 ? occ : 1);
+  const int64_t need = (n_items + waves_per_group - 1) / waves_per_group;
+  if (grid > need) grid = need;
+  if (app_bf16)
+    hipLaunchKernelGGL(k_raster_fwd<true>, dim3((unsigned)grid), dim3(threads), 0, s, st, views, out,
+                       ranges, vals, geom, app, npad_mask, items, (uint32_t)n_items, cnt, last_idx, T_state);
+  else
+    hipLaunchKernelGGL(k_raster_fwd<false>, dim3((unsigned)grid), dim3(threads), 0, s, st, views, out,
+                       ranges, vals, geom, app, npad_mask, items, (uint32_t)n_items, cnt, last_idx, T_state);
+}
+
+template <bool BF16, bool FUSED>
+static void launch_bwd_t(const Settings& st, const ViewDesc* views, const ViewImages* upstream,
+                         const ViewImages* fwd_out, const ViewImages* targets, const float* loss_w,
+                         const uint2* ranges, const uint32_t* vals, const GeomRec* geom, const void* app,
+                         uint32_t npad_mask, const uint32_t* items, int64_t n_items, Counters* cnt,
+                         int waves_per_group, const int32_t* last_idx, const float* T_state,
+                         const uint32_t* slot_base, float* partials, uint8_t* mask, hipStream_t s) {
+  const int threads = 64 * waves_per_group;
+  int dev = 0, cus = 256;
+  hipGetDevice(&dev);
+  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  int occ = 1;
+  hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_raster_bwd<BF16, FUSED>, threads, 0);
+  int64_t grid = (int64_t)cus * (occ > 0 ? occ : 1);
+  const int64_t need = (n_items + waves_per_group - 1) / waves_per_group;
+  if (grid > need) grid = need;
+  hipLaunchKernelGGL((k_raster_bwd<BF16, FUSED>), dim3((unsigned)grid), dim3(threads), 0, s, st, views,
+                     upstream, fwd_out, targets, loss_w, ranges, vals, geom, app, npad_mask, items,
+                     (uint32_t)n_items, cnt, last_idx, T_state, slot_base, partials, mask);
+}
+
+void launch_raster_bwd(const Settings& st, const ViewDesc* views, const ViewImages* upstream,
+                       const ViewImages* fwd_out, const ViewImages* targets, const float* loss_w,
+                       const uint2* ranges, const uint32_t* vals, const GeomRec* geom, const void* app,
+                       int app_bf16, uint32_t npad_mask, const uint32_t* items, int64_t n_items,
+                       Counters* cnt, int waves_per_group, const int32_t* last_idx, const float* T_state,
+                       const uint32_t* slot_base, float* partials, uint8_t* mask, hipStream_t s) {
+  if (n_items <= 0) return;
+  const bool fused = targets != nullptr;
+  if (app_bf16) {
+    if (fused)
+      launch_bwd_t<true, true>(st, views, upstream, fwd_out, targets, loss_w, ranges, vals, geom, app,
+                               npad_mask, items, n_items, cnt, waves_per_group, last_idx, T_state,
+                               slot_base, partials, mask, s);
+    else
+      launch_bwd_t<true, false>(st, views, upstream, fwd_out, targets, loss_w, ranges, vals, geom, app,
+                                npad_mask, items, n_items, cnt, waves_per_group, last_idx, T_state,
+                                slot_base, partials, mask, s);
+  } else {
+    if (fused)
+      launch_bwd_t<false, true>(st, views, upstream, fwd_out, targets, loss_w, ranges, vals, geom, app,
+                                npad_mask, items, n_items, cnt, waves_per_group, last_idx, T_state,
+                                slot_base, partials, mask, s);
+    else
+      launch_bwd_t<false, false>(st, views, upstream, fwd_out, targets, loss_w, ranges, vals, geom, app,
+                                 npad_mask, items, n_items, cnt, waves_per_group, last_idx, T_state,
+                                 slot_base, partials, mask, s);
+  }
+}
+
+void launch_seg_reduce(const uint32_t* ent, const uint32_t* slot_base, const uint32_t* cnt_b,
+                       const float* partials, const uint8_t* mask, const Counters* cnt, int64_t grid_max,
+                       float* grad2d, hipStream_t s) {
+  if (grid_max <= 0) return;
+  hipLaunchKernelGGL(k_seg_reduce, dim3((unsigned)((grid_max + 3) / 4)), dim3(256), 0, s, ent, slot_base,
+                     cnt_b, partials, mask, cnt, grad2d);
+}
+
+}  // namespace lgs

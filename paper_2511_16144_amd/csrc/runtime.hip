@@ -1,0 +1,872 @@
+// Host runtime behind the C ABI of include/lego_raster.h: argument checks,
+// a caching device allocator per context, the launch sequences of the eager
+// forward / backward, the captured whole-step hipGraph, and the autotuner.
+#include "lgs_internal.h"
+#include "../../include/lego_raster.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <string>
+#include <vector>
+
+using namespace lgs;
+
+// ---------------------------------------------------------------------------
+// context, allocator
+// ---------------------------------------------------------------------------
+struct lgs_context {
+  int device = 0;
+  std::string err;
+  std::multimap<size_t, void*> free_blocks;   // size -> ptr (cached)
+  std::map<void*, size_t> live;               // ptr -> size
+  // items tables per (views signature, tile) cached on the device
+  std::map<std::string, std::pair<uint32_t*, int64_t>> items_cache;
+};
+
+namespace {
+
+lgs_status fail(lgs_context* ctx, lgs_status s, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return s;
+}
+
+#define HIP_TRY(ctx, expr)                                                              \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(ctx, LGS_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+void* pool_alloc(lgs_context* ctx, size_t bytes) {
+  bytes = ((bytes + 255) / 256) * 256;
+  if (bytes == 0) bytes = 256;
+  auto it = ctx->free_blocks.lower_bound(bytes);
+  if (it != ctx->free_blocks.end() && it->first <= 2 * bytes + (64u << 20)) {
+    void* p = it->second;
+    ctx->live[p] = it->first;
+    ctx->free_blocks.erase(it);
+    return p;
+  }
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    // drop the cache and retry once
+    for (auto& kv : ctx->free_blocks) hipFree(kv.second);
+    ctx->free_blocks.clear();
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  }
+  ctx->live[p] = bytes;
+  return p;
+}
+
+void pool_free(lgs_context* ctx, void* p) {
+  if (!p) return;
+  auto it = ctx->live.find(p);
+  if (it == ctx->live.end()) return;
+  ctx->free_blocks.emplace(it->second, p);
+  ctx->live.erase(it);
+}
+
+uint32_t ceil_log2(uint64_t x) {
+  uint32_t b = 0;
+  while ((1ull << b) < x) ++b;
+  return b;
+}
+
+lgs_status check_settings(lgs_context* ctx, const lgs_settings* st) {
+  if (!st) return fail(ctx, LGS_ERR_INVALID_ARG, "settings is NULL");
+  if (st->tile != 8 && st->tile != 16 && st->tile != 32)
+    return fail(ctx, LGS_ERR_INVALID_ARG, "tile must be 8, 16 or 32");
+  if (st->chunk != 1 && st->chunk != 2 && st->chunk != 4 && st->chunk != 8)
+    return fail(ctx, LGS_ERR_INVALID_ARG, "chunk must be 1, 2, 4 or 8");
+  if (st->order != 0 && st->order != 1) return fail(ctx, LGS_ERR_INVALID_ARG, "order must be 0 or 1");
+  if (!(st->z_near > 0.f) || !(st->eps2d >= 0.f) || !(st->fov_clamp > 0.f) ||
+      !(st->alpha_max > 0.f && st->alpha_max < 1.f) || !(st->alpha_min > 0.f) ||
+      !(st->T_eps > 0.f && st->T_eps < 1.f) || !(st->cutoff2 > 0.f))
+    return fail(ctx, LGS_ERR_INVALID_ARG, "settings constants out of range");
+  return LGS_OK;
+}
+
+bool aligned4(const void* p) { return ((uintptr_t)p & 3u) == 0; }
+
+lgs_status check_gaussians(lgs_context* ctx, const lgs_gaussians* g) {
+  if (!g) return fail(ctx, LGS_ERR_INVALID_ARG, "gaussians is NULL");
+  if (g->n < 0) return fail(ctx, LGS_ERR_INVALID_ARG, "n < 0");
+  if (g->n > (int64_t)1 << 30) return fail(ctx, LGS_ERR_UNSUPPORTED, "n > 2^30");
+  if (g->appearance_dtype != LGS_F32 && g->appearance_dtype != LGS_BF16)
+    return fail(ctx, LGS_ERR_INVALID_ARG, "unknown appearance dtype");
+  if (g->n > 0) {
+    const void* ps[6] = {g->means, g->log_scales, g->quats, g->opacity_logits, g->rgb, g->feat};
+    for (int i = 0; i < 6; ++i) {
+      if (!ps[i]) return fail(ctx, LGS_ERR_INVALID_ARG, "NULL Gaussian array");
+      if (!aligned4(ps[i]) && !(i >= 4 && g->appearance_dtype == LGS_BF16 && ((uintptr_t)ps[i] & 1u) == 0))
+        return fail(ctx, LGS_ERR_INVALID_ARG, "misaligned Gaussian array");
+    }
+  }
+  return LGS_OK;
+}
+
+lgs_status check_cams(lgs_context* ctx, int32_t n_views, const lgs_camera* cams) {
+  if (n_views < 1 || n_views > 1024) return fail(ctx, LGS_ERR_INVALID_ARG, "n_views must be in [1, 1024]");
+  if (!cams) return fail(ctx, LGS_ERR_INVALID_ARG, "cams is NULL");
+  for (int v = 0; v < n_views; ++v) {
+    const lgs_camera& c = cams[v];
+    if (c.width < 1 || c.height < 1 || c.width > kMaxSide || c.height > kMaxSide)
+      return fail(ctx, LGS_ERR_INVALID_ARG, "image sides must be in [1, 2048]");
+    if (!(c.fx > 0.f) || !(c.fy > 0.f) || !isfinite(c.cx) || !isfinite(c.cy))
+      return fail(ctx, LGS_ERR_INVALID_ARG, "bad intrinsics");
+    for (int k = 0; k < 9; ++k)
+      if (!isfinite(c.R_cw[k])) return fail(ctx, LGS_ERR_INVALID_ARG, "non-finite pose");
+    for (int k = 0; k < 3; ++k)
+      if (!isfinite(c.t_cw[k])) return fail(ctx, LGS_ERR_INVALID_ARG, "non-finite pose");
+  }
+  return LGS_OK;
+}
+
+lgs_status check_images(lgs_context* ctx, int32_t n_views, const lgs_images* im, bool need_T,
+                        const char* what) {
+  if (!im) return fail(ctx, LGS_ERR_INVALID_ARG, std::string(what) + " is NULL");
+  for (int v = 0; v < n_views; ++v) {
+    if (!im[v].rgb || !im[v].depth || !im[v].feat || (need_T && !im[v].final_T))
+      return fail(ctx, LGS_ERR_INVALID_ARG, std::string(what) + ": NULL image plane");
+    if (!aligned4(im[v].rgb) || !aligned4(im[v].depth) || !aligned4(im[v].feat) ||
+        (im[v].final_T && !aligned4(im[v].final_T)) || (im[v].n_contrib && !aligned4(im[v].n_contrib)))
+      return fail(ctx, LGS_ERR_INVALID_ARG, std::string(what) + ": misaligned image plane");
+  }
+  return LGS_OK;
+}
+
+// Per-call geometry of the batch: view descriptors and work sizes.
+struct Plan {
+  std::vector<ViewDesc> views;
+  int64_t n_tiles = 0, n_items = 0, n_pix = 0;
+  int tile_shift = 1;
+  std::string sig;
+};
+
+Plan make_plan(const lgs_settings* st, int32_t n_views, const lgs_camera* cams) {
+  Plan P;
+  P.tile_shift = st->tile == 8 ? 0 : (st->tile == 16 ? 1 : 2);
+  char buf[128];
+  snprintf(buf, sizeof buf, "t%d:", st->tile);
+  P.sig = buf;
+  for (int v = 0; v < n_views; ++v) {
+    const lgs_camera& c = cams[v];
+    ViewDesc d;
+    memset(&d, 0, sizeof d);
+    d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy;
+    for (int k = 0; k < 9; ++k) d.R[k] = c.R_cw[k];
+    for (int k = 0; k < 3; ++k) d.t[k] = c.t_cw[k];
+    // view-angle clamp of the Jacobian (reading: fov_clamp x the half-extent
+    // of the image seen from the principal point)
+    d.limx = (double)st->fov_clamp * fmax((double)c.cx + 0.5, (double)c.width - 0.5 - (double)c.cx) / (double)c.fx;
+    d.limy = (double)st->fov_clamp * fmax((double)c.cy + 0.5, (double)c.height - 0.5 - (double)c.cy) / (double)c.fy;
+    d.W = c.width; d.H = c.height;
+    d.blocks_x = (c.width + kBlock - 1) / kBlock;
+    d.blocks_y = (c.height + kBlock - 1) / kBlock;
+    d.tiles_x = (c.width + st->tile - 1) / st->tile;
+    d.tiles_y = (c.height + st->tile - 1) / st->tile;
+    d.tile_off = (int32_t)P.n_tiles;
+    d.item_off = (int32_t)P.n_items;
+    d.pix_off = (int32_t)P.n_pix;
+    P.n_tiles += (int64_t)d.tiles_x * d.tiles_y;
+    P.n_items += (int64_t)d.blocks_x * d.blocks_y;
+    P.n_pix += (int64_t)c.width * c.height;
+    P.views.push_back(d);
+    snprintf(buf, sizeof buf, "%dx%d,", c.width, c.height);
+    P.sig += buf;
+  }
+  return P;
+}
+
+// Work items (8x8 blocks) tile by tile, raster order inside a tile.
+std::vector<uint32_t> make_items(const Plan& P, int tile) {
+  std::vector<uint32_t> items;
+  items.reserve(P.n_items);
+  const int bpt = tile / kBlock;
+  for (size_t v = 0; v < P.views.size(); ++v) {
+    const ViewDesc& d = P.views[v];
+    for (int ty = 0; ty < d.tiles_y; ++ty)
+      for (int tx = 0; tx < d.tiles_x; ++tx)
+        for (int j = 0; j < bpt; ++j)
+          for (int i = 0; i < bpt; ++i) {
+            const int bx = tx * bpt + i, by = ty * bpt + j;
+            if (bx < d.blocks_x && by < d.blocks_y)
+              items.push_back((uint32_t)bx | ((uint32_t)by << 8) | ((uint32_t)v << 16));
+          }
+  }
+  return items;
+}
+
+Settings dev_settings(const lgs_settings* st, int tile_shift) {
+  Settings s;
+  s.z_near = st->z_near; s.eps2d = st->eps2d; s.fov_clamp = st->fov_clamp;
+  s.alpha_max = st->alpha_max; s.alpha_min = st->alpha_min; s.T_eps = st->T_eps;
+  s.cutoff2 = st->cutoff2; s.tile = st->tile; s.tile_shift = tile_shift;
+  return s;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// device buffers of one forward(+backward): an eager state or a graph
+// ---------------------------------------------------------------------------
+struct Work {
+  lgs_context* ctx = nullptr;
+  std::vector<void*> bufs;
+  lgs_settings st{};
+  Plan plan;
+  int64_t n = 0, n_rid = 0;
+  int npad_shift = 0, app_bf16 = 0;
+  int64_t cap_pairs = 0, cap_slots = 0;
+  lgs_counts counts{};
+  ViewDesc* d_views = nullptr;
+  ViewImages *d_out = nullptr, *d_up = nullptr, *d_tgt = nullptr;
+  float* d_lossw = nullptr;
+  GeomRec* geom = nullptr;
+  uint32_t *cnt_t = nullptr, *cnt_b = nullptr, *cidx = nullptr, *slot_base = nullptr;
+  uint32_t *ent = nullptr, *ent_a = nullptr, *ent_b = nullptr, *srid = nullptr;
+  uint32_t *off_t = nullptr, *slot_off = nullptr;
+  uint64_t *dkey = nullptr, *dk0 = nullptr, *dk1 = nullptr;
+  void* app = nullptr;
+  Counters* counters = nullptr;
+  int32_t* last_idx = nullptr;
+  float* T_state = nullptr;
+  void *scan_tmp = nullptr, *radix_small = nullptr, *radix_big = nullptr;
+  uint32_t *k0 = nullptr, *v0 = nullptr, *k1 = nullptr, *v1 = nullptr, *pkeys = nullptr, *pvals = nullptr;
+  uint2* ranges = nullptr;
+  const uint32_t* items_static = nullptr;
+  uint32_t *ik_a = nullptr, *ii_a = nullptr, *ik_b = nullptr, *ii_b = nullptr;
+  void* radix_items = nullptr;
+  const uint32_t* items = nullptr;
+  float* partials = nullptr;
+  uint8_t* mask = nullptr;
+  float* grad2d = nullptr;
+  void* ttmp = nullptr;
+  bool bwd_alloc = false;
+};
+
+namespace {
+
+void* w_alloc(Work* W, size_t bytes, bool& ok) {
+  void* p = pool_alloc(W->ctx, bytes);
+  if (!p) ok = false;
+  else W->bufs.push_back(p);
+  return p;
+}
+
+void w_release(Work* W) {
+  for (void* p : W->bufs) pool_free(W->ctx, p);
+  W->bufs.clear();
+}
+
+uint32_t* get_items(lgs_context* ctx, const Plan& P, int tile) {
+  auto it = ctx->items_cache.find(P.sig);
+  if (it != ctx->items_cache.end()) return it->second.first;
+  std::vector<uint32_t> items = make_items(P, tile);
+  uint32_t* d = nullptr;
+  if (hipMalloc(&d, std::max<size_t>(4, items.size() * 4)) != hipSuccess) return nullptr;
+  if (!items.empty() && hipMemcpy(d, items.data(), items.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+    hipFree(d);
+    return nullptr;
+  }
+  ctx->items_cache[P.sig] = {d, (int64_t)items.size()};
+  return d;
+}
+
+lgs_status w_init(Work* W, lgs_context* ctx, const lgs_settings* st, const lgs_gaussians* g, int32_t n_views,
+                  const lgs_camera* cams) {
+  W->ctx = ctx;
+  W->st = *st;
+  W->plan = make_plan(st, n_views, cams);
+  W->n = g->n;
+  W->app_bf16 = g->appearance_dtype == LGS_BF16;
+  W->npad_shift = (int)ceil_log2((uint64_t)std::max<int64_t>(g->n, 1));
+  W->n_rid = (int64_t)n_views << W->npad_shift;
+  if (W->n_rid > ((int64_t)1 << 32)) return fail(ctx, LGS_ERR_UNSUPPORTED, "n_views * 2^ceil(log2 n) exceeds 2^32");
+  if (W->plan.n_items > ((int64_t)1 << 31)) return fail(ctx, LGS_ERR_UNSUPPORTED, "too many pixels");
+  return LGS_OK;
+}
+
+// buffers whose size does not depend on the pair count
+lgs_status w_alloc_front(Work* W) {
+  bool ok = true;
+  const int V = (int)W->plan.views.size();
+  const int64_t n_rid = W->n_rid, npix = std::max<int64_t>(W->plan.n_pix, 1);
+  W->d_views = (ViewDesc*)w_alloc(W, sizeof(ViewDesc) * V, ok);
+  W->d_out = (ViewImages*)w_alloc(W, sizeof(ViewImages) * V, ok);
+  W->d_up = (ViewImages*)w_alloc(W, sizeof(ViewImages) * V, ok);
+  W->d_tgt = (ViewImages*)w_alloc(W, sizeof(ViewImages) * V, ok);
+  W->d_lossw = (float*)w_alloc(W, 16, ok);
+  W->geom = (GeomRec*)w_alloc(W, sizeof(GeomRec) * n_rid, ok);
+  W->cnt_t = (uint32_t*)w_alloc(W, 4 * n_rid, ok);
+  W->cnt_b = (uint32_t*)w_alloc(W, 4 * n_rid, ok);
+  W->cidx = (uint32_t*)w_alloc(W, 4 * n_rid, ok);
+  W->slot_base = (uint32_t*)w_alloc(W, 4 * n_rid, ok);
+  W->ent = (uint32_t*)w_alloc(W, 4 * n_rid, ok);
+  W->ent_a = (uint32_t*)w_alloc(W, 4 * n_rid, ok);
+  W->ent_b = (uint32_t*)w_alloc(W, 4 * n_rid, ok);
+  W->off_t = (uint32_t*)w_alloc(W, 4 * n_rid, ok);
+  W->slot_off = (uint32_t*)w_alloc(W, 4 * n_rid, ok);
+  W->dkey = (uint64_t*)w_alloc(W, 8 * n_rid, ok);
+  W->dk0 = (uint64_t*)w_alloc(W, 8 * n_rid, ok);
+  W->dk1 = (uint64_t*)w_alloc(W, 8 * n_rid, ok);
+  W->app = w_alloc(W, (size_t)std::max<int64_t>(W->n, 1) * (W->app_bf16 ? 40 : 80), ok);
+  W->counters = (Counters*)w_alloc(W, sizeof(Counters), ok);
+  W->last_idx = (int32_t*)w_alloc(W, 4 * npix, ok);
+  W->T_state = (float*)w_alloc(W, 4 * npix, ok);
+  W->scan_tmp = w_alloc(W, scan_temp_bytes(n_rid), ok);
+  W->radix_small = w_alloc(W, radix_temp_bytes(n_rid), ok);
+  W->ranges = (uint2*)w_alloc(W, 8 * std::max<int64_t>(W->plan.n_tiles, 1), ok);
+  const int64_t ni = std::max<int64_t>(W->plan.n_items, 1);
+  W->ik_a = (uint32_t*)w_alloc(W, 4 * ni, ok);
+  W->ii_a = (uint32_t*)w_alloc(W, 4 * ni, ok);
+  W->ik_b = (uint32_t*)w_alloc(W, 4 * ni, ok);
+  W->ii_b = (uint32_t*)w_alloc(W, 4 * ni, ok);
+  W->radix_items = w_alloc(W, radix_temp_bytes(ni), ok);
+  W->items_static = get_items(W->ctx, W->plan, W->st.tile);
+  if (!ok || !W->items_static) return fail(W->ctx, LGS_ERR_HIP, "device allocation failed");
+  return LGS_OK;
+}
+
+lgs_status w_alloc_pairs(Work* W, int64_t cap_pairs, int64_t cap_slots) {
+  bool ok = true;
+  W->cap_pairs = cap_pairs;
+  W->cap_slots = cap_slots;
+  const int64_t pa = std::max<int64_t>(cap_pairs, 1);
+  W->k0 = (uint32_t*)w_alloc(W, 4 * pa, ok);
+  W->v0 = (uint32_t*)w_alloc(W, 4 * pa, ok);
+  W->k1 = (uint32_t*)w_alloc(W, 4 * pa, ok);
+  W->v1 = (uint32_t*)w_alloc(W, 4 * pa, ok);
+  W->radix_big = w_alloc(W, radix_temp_bytes(pa), ok);
+  if (!ok) return fail(W->ctx, LGS_ERR_HIP, "device allocation failed (pairs)");
+  return LGS_OK;
+}
+
+lgs_status w_alloc_bwd(Work* W) {
+  if (W->bwd_alloc) return LGS_OK;
+  bool ok = true;
+  const int64_t S = std::max<int64_t>(W->cap_slots, 1);
+  W->partials = (float*)w_alloc(W, sizeof(float) * kPartials * S, ok);
+  W->mask = (uint8_t*)w_alloc(W, S + 8, ok);
+  W->grad2d = (float*)w_alloc(W, sizeof(float) * kPartials * std::max<int64_t>(W->n_rid, 1), ok);
+  W->ttmp = w_alloc(W, twist_temp_bytes(W->n, (int)W->plan.views.size()), ok);
+  if (!ok) return fail(W->ctx, LGS_ERR_HIP, "device allocation failed (backward)");
+  W->bwd_alloc = true;
+  return LGS_OK;
+}
+
+lgs_status w_upload(Work* W, const lgs_images* out, hipStream_t stream) {
+  const int V = (int)W->plan.views.size();
+  std::vector<ViewImages> himg(V);
+  for (int v = 0; v < V; ++v)
+    himg[v] = ViewImages{out[v].rgb, out[v].depth, out[v].feat, out[v].final_T, out[v].n_contrib};
+  HIP_TRY(W->ctx, hipMemcpyAsync(W->d_views, W->plan.views.data(), sizeof(ViewDesc) * V, hipMemcpyHostToDevice, stream));
+  HIP_TRY(W->ctx, hipMemcpyAsync(W->d_out, himg.data(), sizeof(ViewImages) * V, hipMemcpyHostToDevice, stream));
+  HIP_TRY(W->ctx, hipStreamSynchronize(stream));   // host vectors go out of scope
+  return LGS_OK;
+}
+
+// projection .. slot bases: everything up to the pair / slot counts
+void enqueue_front(Work* W, const lgs_gaussians* g, hipStream_t s) {
+  const Settings ds = dev_settings(&W->st, W->plan.tile_shift);
+  const int V = (int)W->plan.views.size();
+  const int64_t n_rid = W->n_rid;
+  launch_reset_counters(W->counters, s);
+  launch_project(ds, W->d_views, V, g->means, g->log_scales, g->quats, g->opacity_logits, g->rgb, g->feat,
+                 W->app_bf16, W->n, W->npad_shift, W->geom, W->cnt_t, W->cnt_b, W->dkey, W->app, s);
+  launch_scan(SCAN_FLAG_NONZERO, W->cnt_t, nullptr, W->cidx, &W->counters->n_visible, nullptr, n_rid,
+              W->scan_tmp, s);
+  // the compaction writes ent (kept, index order) and a copy that the depth sort permutes
+  launch_compact(W->cnt_t, W->cidx, W->dkey, n_rid, W->ent, W->dk0, s);
+  launch_compact(W->cnt_t, W->cidx, W->dkey, n_rid, W->ent_a, W->dk0, s);
+  bool alt = false;
+  radix_sort_u64(W->dk0, W->ent_a, W->dk1, W->ent_b, &W->counters->n_visible, n_rid, 0, 48, W->radix_small, s,
+                 &alt);
+  W->srid = alt ? W->ent_b : W->ent_a;
+  launch_scan(SCAN_GATHER, W->cnt_t, W->srid, W->off_t, &W->counters->n_pairs, &W->counters->n_visible, n_rid,
+              W->scan_tmp, s);
+  launch_scan(SCAN_GATHER, W->cnt_b, W->ent, W->slot_off, &W->counters->n_slots, &W->counters->n_visible, n_rid,
+              W->scan_tmp, s);
+  launch_slot_bases(W->ent, W->slot_off, W->counters, n_rid, W->slot_base, s);
+}
+
+// emission, tile sort, tile ranges, work order (capacity-bounded)
+void enqueue_pairs(Work* W, hipStream_t s) {
+  const Plan& P = W->plan;
+  launch_set_overflow(W->counters, (uint64_t)W->cap_pairs, (uint64_t)W->cap_slots, s);
+  launch_fill_u32((uint32_t*)W->ranges, 0u, 2 * P.n_tiles, s);
+  launch_emit(W->geom, W->d_views, W->srid, W->off_t, W->counters, W->cap_pairs, W->cap_pairs, W->npad_shift,
+              P.tile_shift, W->k0, W->v0, s);
+  const int tile_bits = std::max<int>(1, (int)ceil_log2((uint64_t)P.n_tiles));
+  bool alt = false;
+  radix_sort_u32(W->k0, W->v0, W->k1, W->v1, &W->counters->n_pairs_eff, std::max<int64_t>(W->cap_pairs, 1), 0,
+                 tile_bits, W->radix_big, s, &alt);
+  W->pkeys = alt ? W->k1 : W->k0;
+  W->pvals = alt ? W->v1 : W->v0;
+  launch_tile_ranges(W->pkeys, W->counters, W->cap_pairs, W->ranges, s);
+  if (W->st.order == 1)
+    W->items = launch_order_items(W->d_views, W->ranges, P.tile_shift, W->items_static, P.n_items, W->ik_a,
+                                  W->ii_a, W->ik_b, W->ii_b, W->radix_items, s);
+  else
+    W->items = W->items_static;
+}
+
+void enqueue_raster_fwd(Work* W, hipStream_t s) {
+  const Settings ds = dev_settings(&W->st, W->plan.tile_shift);
+  launch_raster_fwd(ds, W->d_views, W->d_out, W->ranges, W->pvals, W->geom, W->app, W->app_bf16,
+                    (uint32_t)((1ull << W->npad_shift) - 1), W->items, W->plan.n_items, W->counters, W->st.chunk,
+                    W->last_idx, W->T_state, s);
+}
+
+// fused: upstream = dL1/dY from (d_out, d_tgt, d_lossw); else from d_up
+void enqueue_backward(Work* W, const lgs_gaussians* g, const lgs_grads* gr, bool fused, hipStream_t s,
+                      hipEvent_t mid_event = nullptr, hipEvent_t end_event = nullptr) {
+  const Settings ds = dev_settings(&W->st, W->plan.tile_shift);
+  const int V = (int)W->plan.views.size();
+  launch_fill_u8(W->mask, 0, &W->counters->n_slots_eff, std::max<int64_t>(W->cap_slots, 1), s);
+  launch_fill_u32(&W->counters->work_next_b, 0u, 1, s);
+  launch_fill_u32((uint32_t*)&W->counters->bwd_evals, 0u, 4, s);   // bwd_evals, bwd_contrib
+  launch_raster_bwd(ds, W->d_views, W->d_up, fused ? W->d_out : nullptr, fused ? W->d_tgt : nullptr,
+                    fused ? W->d_lossw : nullptr, W->ranges, W->pvals, W->geom, W->app, W->app_bf16,
+                    (uint32_t)((1ull << W->npad_shift) - 1), W->items, W->plan.n_items, W->counters, W->st.chunk,
+                    W->last_idx, W->T_state, W->slot_base, W->partials, W->mask, s);
+  if (mid_event) hipEventRecord(mid_event, s);
+  launch_seg_reduce(W->ent, W->slot_base, W->cnt_b, W->partials, W->mask, W->counters, W->n_rid, W->grad2d, s);
+  launch_project_bwd(ds, W->d_views, V, g->means, g->log_scales, g->quats, g->opacity_logits, W->n,
+                     W->npad_shift, W->counters, W->cnt_t, W->cidx, W->grad2d, gr->means, gr->log_scales,
+                     gr->quats, gr->opacity_logits, gr->rgb, gr->feat, gr->twist, W->ttmp, s);
+  if (end_event) hipEventRecord(end_event, s);
+}
+
+lgs_status read_counts(Work* W, hipStream_t s, Counters* hc) {
+  HIP_TRY(W->ctx, hipMemcpyAsync(hc, W->counters, sizeof(Counters), hipMemcpyDeviceToHost, s));
+  HIP_TRY(W->ctx, hipStreamSynchronize(s));
+  W->counts.n_visible = hc->n_visible;
+  W->counts.n_pairs = hc->n_pairs;
+  W->counts.n_slots = hc->n_slots;
+  W->counts.n_tiles = W->plan.n_tiles;
+  W->counts.n_items = W->plan.n_items;
+  W->counts.fwd_evals = (int64_t)hc->fwd_evals;
+  W->counts.fwd_contrib = (int64_t)hc->fwd_contrib;
+  W->counts.bwd_evals = (int64_t)hc->bwd_evals;
+  W->counts.bwd_contrib = (int64_t)hc->bwd_contrib;
+  return LGS_OK;
+}
+
+lgs_status check_grads(lgs_context* ctx, const lgs_gaussians* g, const lgs_grads* grads) {
+  if (!grads) return fail(ctx, LGS_ERR_INVALID_ARG, "grads is NULL");
+  if (g->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits ||
+                   !grads->rgb || !grads->feat))
+    return fail(ctx, LGS_ERR_INVALID_ARG, "NULL gradient plane");
+  return LGS_OK;
+}
+
+}  // namespace
+
+struct lgs_fwd_state {
+  Work W;
+};
+
+struct lgs_graph {
+  Work W;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t cap_stream = nullptr;
+  hipStream_t last_stream = nullptr;
+  lgs_gaussians g{};
+  lgs_grads grads{};
+  hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  bool profile = false;
+};
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* lgs_status_string(lgs_status s) {
+  switch (s) {
+    case LGS_OK: return "LGS_OK";
+    case LGS_ERR_INVALID_ARG: return "LGS_ERR_INVALID_ARG";
+    case LGS_ERR_HIP: return "LGS_ERR_HIP";
+    case LGS_ERR_CAPACITY: return "LGS_ERR_CAPACITY";
+    case LGS_ERR_UNSUPPORTED: return "LGS_ERR_UNSUPPORTED";
+    case LGS_ERR_STATE: return "LGS_ERR_STATE";
+  }
+  return "LGS_ERR_UNKNOWN";
+}
+
+const char* lgs_last_error(const lgs_context* ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
+
+lgs_settings lgs_default_settings(void) {
+  lgs_settings s;
+  s.z_near = 0.2f; s.eps2d = 0.3f; s.fov_clamp = 1.3f; s.alpha_max = 0.99f;
+  s.alpha_min = 1.0f / 255.0f; s.T_eps = 1e-4f; s.cutoff2 = 9.0f;
+  s.tile = 16; s.chunk = 4; s.order = 0; s.profile = 0;
+  return s;
+}
+
+lgs_status lgs_context_create(int hip_device, lgs_context** out) {
+  if (!out) return LGS_ERR_INVALID_ARG;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return LGS_ERR_HIP;
+  if (hip_device < 0 || hip_device >= count) return LGS_ERR_INVALID_ARG;
+  if (hipSetDevice(hip_device) != hipSuccess) return LGS_ERR_HIP;
+  lgs_context* c = new lgs_context();
+  c->device = hip_device;
+  *out = c;
+  return LGS_OK;
+}
+
+void lgs_context_destroy(lgs_context* ctx) {
+  if (!ctx) return;
+  hipSetDevice(ctx->device);
+  hipDeviceSynchronize();
+  for (auto& kv : ctx->free_blocks) hipFree(kv.second);
+  for (auto& kv : ctx->live) hipFree(kv.first);
+  for (auto& kv : ctx->items_cache) hipFree(kv.second.first);
+  delete ctx;
+}
+
+lgs_status lgs_state_counts(const lgs_fwd_state* s, lgs_counts* out) {
+  if (!s || !out) return LGS_ERR_INVALID_ARG;
+  lgs_fwd_state* S = const_cast<lgs_fwd_state*>(s);
+  hipSetDevice(S->W.ctx->device);
+  hipDeviceSynchronize();
+  Counters hc;
+  lgs_status rc = read_counts(&S->W, nullptr, &hc);
+  if (rc != LGS_OK) return rc;
+  *out = S->W.counts;
+  return LGS_OK;
+}
+
+lgs_status lgs_state_release(lgs_context* ctx, lgs_fwd_state* s) {
+  if (!ctx || !s) return LGS_ERR_INVALID_ARG;
+  if (s->W.ctx != ctx) return fail(ctx, LGS_ERR_STATE, "state belongs to another context");
+  hipSetDevice(ctx->device);
+  hipDeviceSynchronize();   // queued work may still use the buffers
+  w_release(&s->W);
+  delete s;
+  return LGS_OK;
+}
+
+lgs_status lgs_forward(lgs_context* ctx, const lgs_settings* st, const lgs_gaussians* g, int32_t n_views,
+                       const lgs_camera* cams, const lgs_images* out, lgs_fwd_state** state_out,
+                       hipStream_t stream) {
+  if (!ctx) return LGS_ERR_INVALID_ARG;
+  ctx->err.clear();
+  if (!state_out) return fail(ctx, LGS_ERR_INVALID_ARG, "state_out is NULL");
+  *state_out = nullptr;
+  lgs_status rc;
+  if ((rc = check_settings(ctx, st)) != LGS_OK) return rc;
+  if ((rc = check_gaussians(ctx, g)) != LGS_OK) return rc;
+  if ((rc = check_cams(ctx, n_views, cams)) != LGS_OK) return rc;
+  if ((rc = check_images(ctx, n_views, out, true, "out")) != LGS_OK) return rc;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  lgs_fwd_state* S = new lgs_fwd_state();
+  Work* W = &S->W;
+  auto bail = [&](lgs_status e) {
+    w_release(W);
+    delete S;
+    return e;
+  };
+  if ((rc = w_init(W, ctx, st, g, n_views, cams)) != LGS_OK) return bail(rc);
+  if ((rc = w_alloc_front(W)) != LGS_OK) return bail(rc);
+  if ((rc = w_upload(W, out, stream)) != LGS_OK) return bail(rc);
+  enqueue_front(W, g, stream);
+  if (hipGetLastError() != hipSuccess) return bail(fail(ctx, LGS_ERR_HIP, "kernel launch failed"));
+  Counters hc;
+  if ((rc = read_counts(W, stream, &hc)) != LGS_OK) return bail(rc);
+  if ((rc = w_alloc_pairs(W, hc.n_pairs, hc.n_slots)) != LGS_OK) return bail(rc);
+  enqueue_pairs(W, stream);
+  enqueue_raster_fwd(W, stream);
+  if (hipGetLastError() != hipSuccess) return bail(fail(ctx, LGS_ERR_HIP, "kernel launch failed"));
+  *state_out = S;
+  return LGS_OK;
+}
+
+lgs_status lgs_backward(lgs_context* ctx, const lgs_fwd_state* Sc, const lgs_gaussians* g,
+                        const lgs_images* grad_out, lgs_grads* grads, hipStream_t stream) {
+  if (!ctx) return LGS_ERR_INVALID_ARG;
+  ctx->err.clear();
+  if (!Sc) return fail(ctx, LGS_ERR_INVALID_ARG, "state is NULL");
+  lgs_fwd_state* S = const_cast<lgs_fwd_state*>(Sc);
+  Work* W = &S->W;
+  if (W->ctx != ctx) return fail(ctx, LGS_ERR_STATE, "state belongs to another context");
+  lgs_status rc;
+  if ((rc = check_gaussians(ctx, g)) != LGS_OK) return rc;
+  if (g->n != W->n) return fail(ctx, LGS_ERR_INVALID_ARG, "n differs from the forward's");
+  const int V = (int)W->plan.views.size();
+  if ((rc = check_images(ctx, V, grad_out, false, "grad_out")) != LGS_OK) return rc;
+  if ((rc = check_grads(ctx, g, grads)) != LGS_OK) return rc;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  if ((rc = w_alloc_bwd(W)) != LGS_OK) return rc;
+  std::vector<ViewImages> hup(V);
+  for (int v = 0; v < V; ++v)
+    hup[v] = ViewImages{grad_out[v].rgb, grad_out[v].depth, grad_out[v].feat, grad_out[v].final_T, nullptr};
+  HIP_TRY(ctx, hipMemcpyAsync(W->d_up, hup.data(), sizeof(ViewImages) * V, hipMemcpyHostToDevice, stream));
+  enqueue_backward(W, g, grads, false, stream);
+  HIP_TRY(ctx, hipGetLastError());
+  Counters hc;   // synchronises: hup goes out of scope
+  return read_counts(W, stream, &hc);
+}
+
+// ---------------------------------------------------------------------------
+// whole-step graph
+// ---------------------------------------------------------------------------
+lgs_status lgs_graph_create(lgs_context* ctx, const lgs_settings* st, const lgs_gaussians* g, int32_t n_views,
+                            const lgs_camera* cams, const lgs_images* targets, const float loss_w[3],
+                            const lgs_images* out, const lgs_grads* grads, int64_t pair_capacity,
+                            hipStream_t stream, lgs_graph** graph_out) {
+  if (!ctx) return LGS_ERR_INVALID_ARG;
+  ctx->err.clear();
+  if (!graph_out) return fail(ctx, LGS_ERR_INVALID_ARG, "graph_out is NULL");
+  *graph_out = nullptr;
+  lgs_status rc;
+  if ((rc = check_settings(ctx, st)) != LGS_OK) return rc;
+  if ((rc = check_gaussians(ctx, g)) != LGS_OK) return rc;
+  if ((rc = check_cams(ctx, n_views, cams)) != LGS_OK) return rc;
+  if ((rc = check_images(ctx, n_views, out, true, "out")) != LGS_OK) return rc;
+  if ((rc = check_images(ctx, n_views, targets, false, "targets")) != LGS_OK) return rc;
+  if (!loss_w) return fail(ctx, LGS_ERR_INVALID_ARG, "loss_w is NULL");
+  if ((rc = check_grads(ctx, g, grads)) != LGS_OK) return rc;
+  if (pair_capacity < 0) return fail(ctx, LGS_ERR_INVALID_ARG, "pair_capacity < 0");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  // measure the workload once (eager) to size the pair and slot buffers
+  lgs_fwd_state* probe = nullptr;
+  if ((rc = lgs_forward(ctx, st, g, n_views, cams, out, &probe, stream)) != LGS_OK) return rc;
+  const lgs_counts pc = probe->W.counts;
+  lgs_state_release(ctx, probe);
+  int64_t capP, capS;
+  const double sp = pc.n_pairs > 0 ? (double)pc.n_slots / (double)pc.n_pairs : 1.0;
+  if (pair_capacity > 0) {
+    capP = pair_capacity;
+    capS = (int64_t)ceil((double)pair_capacity * std::max(1.0, sp) * 1.25) + 4096;
+  } else {
+    capP = (int64_t)ceil(1.5 * (double)pc.n_pairs) + 4096;
+    capS = (int64_t)ceil(1.5 * (double)pc.n_slots) + 4096;
+  }
+  if (capP > 0xFFFFFFFFll || capS > 0xFFFFFFFFll) return fail(ctx, LGS_ERR_UNSUPPORTED, "capacity exceeds 2^32");
+  lgs_graph* G = new lgs_graph();
+  Work* W = &G->W;
+  G->g = *g;
+  G->grads = *grads;
+  auto bail = [&](lgs_status e) {
+    if (G->exec) hipGraphExecDestroy(G->exec);
+    if (G->graph) hipGraphDestroy(G->graph);
+    if (G->cap_stream) hipStreamDestroy(G->cap_stream);
+    for (int i = 0; i < 6; ++i)
+      if (G->ev[i]) hipEventDestroy(G->ev[i]);
+    w_release(W);
+    delete G;
+    return e;
+  };
+  if ((rc = w_init(W, ctx, st, g, n_views, cams)) != LGS_OK) return bail(rc);
+  if ((rc = w_alloc_front(W)) != LGS_OK) return bail(rc);
+  if ((rc = w_alloc_pairs(W, capP, capS)) != LGS_OK) return bail(rc);
+  if ((rc = w_alloc_bwd(W)) != LGS_OK) return bail(rc);
+  if ((rc = w_upload(W, out, stream)) != LGS_OK) return bail(rc);
+  {
+    std::vector<ViewImages> ht(n_views);
+    for (int v = 0; v < n_views; ++v)
+      ht[v] = ViewImages{targets[v].rgb, targets[v].depth, targets[v].feat, nullptr, nullptr};
+    float lw[4] = {loss_w[0], loss_w[1], loss_w[2], 0.f};
+    if (hipMemcpy(W->d_tgt, ht.data(), sizeof(ViewImages) * n_views, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(W->d_lossw, lw, sizeof lw, hipMemcpyHostToDevice) != hipSuccess)
+      return bail(fail(ctx, LGS_ERR_HIP, "upload failed"));
+  }
+  if (hipStreamCreateWithFlags(&G->cap_stream, hipStreamNonBlocking) != hipSuccess)
+    return bail(fail(ctx, LGS_ERR_HIP, "stream creation failed"));
+  if (st->profile)
+    for (int i = 0; i < 6; ++i)
+      if (hipEventCreate(&G->ev[i]) != hipSuccess) return bail(fail(ctx, LGS_ERR_HIP, "event creation failed"));
+  if (hipStreamBeginCapture(G->cap_stream, hipStreamCaptureModeRelaxed) != hipSuccess)
+    return bail(fail(ctx, LGS_ERR_HIP, "hipStreamBeginCapture failed"));
+  G->profile = st->profile != 0;
+  auto mark = [&](int i) {
+    if (G->profile) hipEventRecord(G->ev[i], G->cap_stream);
+  };
+  mark(0);
+  enqueue_front(W, &G->g, G->cap_stream);
+  mark(1);
+  enqueue_pairs(W, G->cap_stream);
+  mark(2);
+  enqueue_raster_fwd(W, G->cap_stream);
+  mark(3);
+  enqueue_backward(W, &G->g, &G->grads, true, G->cap_stream, G->profile ? G->ev[4] : nullptr,
+                   G->profile ? G->ev[5] : nullptr);
+  hipError_t e = hipStreamEndCapture(G->cap_stream, &G->graph);
+  if (e != hipSuccess) return bail(fail(ctx, LGS_ERR_HIP, std::string("capture failed: ") + hipGetErrorString(e)));
+  e = hipGraphInstantiate(&G->exec, G->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess)
+    return bail(fail(ctx, LGS_ERR_HIP, std::string("instantiate failed: ") + hipGetErrorString(e)));
+  W->counts = pc;
+  *graph_out = G;
+  return LGS_OK;
+}
+
+lgs_status lgs_graph_launch(lgs_graph* G, hipStream_t stream) {
+  if (!G) return LGS_ERR_INVALID_ARG;
+  HIP_TRY(G->W.ctx, hipSetDevice(G->W.ctx->device));
+  HIP_TRY(G->W.ctx, hipGraphLaunch(G->exec, stream));
+  G->last_stream = stream;
+  return LGS_OK;
+}
+
+lgs_status lgs_graph_status(lgs_graph* G) {
+  if (!G) return LGS_ERR_INVALID_ARG;
+  HIP_TRY(G->W.ctx, hipSetDevice(G->W.ctx->device));
+  Counters hc;
+  lgs_status rc = read_counts(&G->W, G->last_stream, &hc);
+  if (rc != LGS_OK) return rc;
+  if (hc.overflow) return fail(G->W.ctx, LGS_ERR_CAPACITY, "pair or slot capacity exceeded; re-create the graph");
+  return LGS_OK;
+}
+
+lgs_status lgs_graph_counts(lgs_graph* G, lgs_counts* out) {
+  if (!G || !out) return LGS_ERR_INVALID_ARG;
+  HIP_TRY(G->W.ctx, hipSetDevice(G->W.ctx->device));
+  Counters hc;
+  lgs_status rc = read_counts(&G->W, G->last_stream, &hc);
+  if (rc != LGS_OK) return rc;
+  *out = G->W.counts;
+  return LGS_OK;
+}
+
+lgs_status lgs_graph_stage_ms(lgs_graph* G, float ms[5]) {
+  if (!G || !ms) return LGS_ERR_INVALID_ARG;
+  if (!G->profile) return fail(G->W.ctx, LGS_ERR_STATE, "graph was created without settings.profile");
+  HIP_TRY(G->W.ctx, hipSetDevice(G->W.ctx->device));
+  HIP_TRY(G->W.ctx, hipEventSynchronize(G->ev[5]));
+  for (int i = 0; i < 5; ++i) HIP_TRY(G->W.ctx, hipEventElapsedTime(&ms[i], G->ev[i], G->ev[i + 1]));
+  return LGS_OK;
+}
+
+void lgs_graph_destroy(lgs_graph* G) {
+  if (!G) return;
+  hipSetDevice(G->W.ctx->device);
+  hipDeviceSynchronize();
+  if (G->exec) hipGraphExecDestroy(G->exec);
+  if (G->graph) hipGraphDestroy(G->graph);
+  if (G->cap_stream) hipStreamDestroy(G->cap_stream);
+  for (int i = 0; i < 6; ++i)
+    if (G->ev[i]) hipEventDestroy(G->ev[i]);
+  w_release(&G->W);
+  delete G;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner
+// ---------------------------------------------------------------------------
+static std::string tune_key(const lgs_gaussians* g, int32_t n_views, const lgs_camera* cams) {
+  char buf[96];
+  snprintf(buf, sizeof buf, "n%lld_%s_v%d", (long long)g->n, g->appearance_dtype == LGS_BF16 ? "bf16" : "f32",
+           n_views);
+  std::string k = buf;
+  for (int v = 0; v < n_views; ++v) {
+    snprintf(buf, sizeof buf, "_%dx%d", cams[v].width, cams[v].height);
+    k += buf;
+  }
+  return k;
+}
+
+static bool tune_cache_read(const char* path, const std::string& key, lgs_settings* s) {
+  FILE* f = fopen(path, "r");
+  if (!f) return false;
+  char line[1024];
+  bool found = false;
+  while (fgets(line, sizeof line, f)) {
+    char k[900];
+    int tile, chunk, order;
+    if (sscanf(line, " \"%899[^\"]\": {\"tile\": %d, \"chunk\": %d, \"order\": %d}", k, &tile, &chunk, &order) == 4 &&
+        key == k) {
+      s->tile = tile; s->chunk = chunk; s->order = order;
+      found = true;
+    }
+  }
+  fclose(f);
+  return found;
+}
+
+static void tune_cache_write(const char* path, const std::string& key, const lgs_settings& s) {
+  std::vector<std::string> lines;
+  if (FILE* f = fopen(path, "r")) {
+    char line[1024];
+    while (fgets(line, sizeof line, f)) {
+      char k[900];
+      std::string L(line);
+      if (sscanf(line, " \"%899[^\"]\":", k) == 1 && key != k) {
+        while (!L.empty() && (L.back() == '\n' || L.back() == ',')) L.pop_back();
+        lines.push_back(L);
+      }
+    }
+    fclose(f);
+  }
+  char buf[1024];
+  snprintf(buf, sizeof buf, "  \"%s\": {\"tile\": %d, \"chunk\": %d, \"order\": %d}", key.c_str(), s.tile,
+           s.chunk, s.order);
+  lines.push_back(buf);
+  FILE* f = fopen(path, "w");
+  if (!f) return;
+  fprintf(f, "{\n");
+  for (size_t i = 0; i < lines.size(); ++i) fprintf(f, "%s%s\n", lines[i].c_str(), i + 1 < lines.size() ? "," : "");
+  fprintf(f, "}\n");
+  fclose(f);
+}
+
+lgs_status lgs_autotune(lgs_context* ctx, const lgs_settings* st, const lgs_gaussians* g, int32_t n_views,
+                        const lgs_camera* cams, const lgs_images* targets, const float loss_w[3],
+                        const lgs_images* out, const lgs_grads* grads, int64_t pair_capacity, hipStream_t stream,
+                        const char* cache_path, lgs_settings* best_out) {
+  if (!ctx) return LGS_ERR_INVALID_ARG;
+  ctx->err.clear();
+  if (!best_out) return fail(ctx, LGS_ERR_INVALID_ARG, "best_out is NULL");
+  lgs_status rc;
+  if ((rc = check_settings(ctx, st)) != LGS_OK) return rc;
+  if ((rc = check_gaussians(ctx, g)) != LGS_OK) return rc;
+  if ((rc = check_cams(ctx, n_views, cams)) != LGS_OK) return rc;
+  const std::string key = tune_key(g, n_views, cams);
+  *best_out = *st;
+  if (cache_path && tune_cache_read(cache_path, key, best_out)) return LGS_OK;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  hipEvent_t e0, e1;
+  HIP_TRY(ctx, hipEventCreate(&e0));
+  HIP_TRY(ctx, hipEventCreate(&e1));
+  float best_ms = 1e30f;
+  const int tiles[3] = {8, 16, 32}, chunks[3] = {1, 2, 4}, orders[2] = {0, 1};
+  for (int ti = 0; ti < 3; ++ti)
+    for (int ci = 0; ci < 3; ++ci)
+      for (int oi = 0; oi < 2; ++oi) {
+        lgs_settings s = *st;
+        s.tile = tiles[ti]; s.chunk = chunks[ci]; s.order = orders[oi]; s.profile = 0;
+        lgs_graph* G = nullptr;
+        rc = lgs_graph_create(ctx, &s, g, n_views, cams, targets, loss_w, out, grads, pair_capacity, stream, &G);
+        if (rc != LGS_OK) continue;
+        for (int w = 0; w < 3; ++w) lgs_graph_launch(G, stream);
+        const int reps = 10;
+        hipEventRecord(e0, stream);
+        for (int r = 0; r < reps; ++r) lgs_graph_launch(G, stream);
+        hipEventRecord(e1, stream);
+        hipEventSynchronize(e1);
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        const bool ok = lgs_graph_status(G) == LGS_OK;
+        lgs_graph_destroy(G);
+        if (ok && ms / reps < best_ms) {
+          best_ms = ms / reps;
+          *best_out = s;
+        }
+      }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (best_ms >= 1e29f) return fail(ctx, LGS_ERR_HIP, "no setting ran");
+  if (cache_path) tune_cache_write(cache_path, key, *best_out);
+  return LGS_OK;
+}
+
+}  // extern "C"
