@@ -2,8 +2,8 @@
 
 One step = forward render (RGB + depth + 16-d feature) of every view, the L1
 loss gradient of Eq. (1) (without D-SSIM), and the full backward to the
-Gaussian parameters and the pose twists, as one captured hipGraph launch on
-device-resident inputs.  Metric: Mpixel/s = sum over views of W x H per step
+Gaussian parameters and the pose twists (lgs_forward + lgs_backward_l1, all
+stages in the library's HIP kernels) on device-resident inputs.  Metric: Mpixel/s = sum over views of W x H per step
 / step time.
 
 Default workload: the batched configuration (500k Gaussians in a 6x6x3 m
@@ -49,64 +49,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_graph(ctx, P, wl, params, settings, dev, tune, cache=None):
-    import torch
-    from paper_2511_16144_amd import binding as B
-    V = len(wl.cams)
-    outs = []
-    imgs = (B.lgs_images * V)()
-    tgts = (B.lgs_images * V)()
-    keep = []
-    for v, c in enumerate(wl.cams):
-        H, W = c.height, c.width
-        o = {"rgb": torch.empty((3, H, W), device=dev), "depth": torch.empty((H, W), device=dev),
-             "feat": torch.empty((16, H, W), device=dev), "T": torch.empty((H, W), device=dev)}
-        outs.append(o)
-        imgs[v] = B.lgs_images(o["rgb"].data_ptr(), o["depth"].data_ptr(), o["feat"].data_ptr(),
-                               o["T"].data_ptr(), None)
-        t = wl.targets[v]
-        tt = {"rgb": torch.as_tensor(t.rgb).to(dev), "depth": torch.as_tensor(t.depth).to(dev),
-              "feat": torch.as_tensor(t.feat).to(dev)}
-        keep.append(tt)
-        tgts[v] = B.lgs_images(tt["rgb"].data_ptr(), tt["depth"].data_ptr(), tt["feat"].data_ptr(), None, None)
-    n = params["logits"].shape[0]
-    grads = {"means": torch.empty((3, n), device=dev), "log_scales": torch.empty((3, n), device=dev),
-             "quats": torch.empty((4, n), device=dev), "logits": torch.empty((n,), device=dev),
-             "rgb": torch.empty((3, n), device=dev), "feat": torch.empty((16, n), device=dev),
-             "twist": torch.empty((V, 6), device=dev)}
-    gr = B.lgs_grads(*[grads[k].data_ptr() for k in ("means", "log_scales", "quats", "logits", "rgb", "feat",
-                                                    "twist")])
-    g = B.gaussians_c(params["means"], params["log_scales"], params["quats"], params["logits"],
-                      params["rgb"], params["feat"])
-    cams = (B.lgs_camera * V)(*[B.camera_c(c) for c in wl.cams])
-    lw = (C.c_float * 3)(*wl.loss_w)
-    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
-    st = settings.to_c()
-    if tune:
-        best = B.lgs_settings()
-        rc = B.lib().lgs_autotune(ctx._h, C.byref(st), C.byref(g), V, cams, tgts, lw, imgs, C.byref(gr), 0,
-                                  stream, cache.encode() if cache else None, C.byref(best))
-        if rc != 0:
-            raise B.LgsError(rc, B.lib().lgs_last_error(ctx._h).decode())
-        st = best
-        st.profile = settings.profile
-    h = C.c_void_p()
-    rc = B.lib().lgs_graph_create(ctx._h, C.byref(st), C.byref(g), V, cams, tgts, lw, imgs, C.byref(gr), 0,
-                                  stream, C.byref(h))
-    if rc != 0:
-        raise B.LgsError(rc, B.lib().lgs_last_error(ctx._h).decode())
-    return h, st, (outs, keep, grads, imgs, tgts, gr, g, cams, lw)
-
-
-def graph_launch(h):
-    import torch
-    from paper_2511_16144_amd import binding as B
-    rc = B.lib().lgs_graph_launch(h, C.c_void_p(torch.cuda.current_stream().cuda_stream))
-    if rc != 0:
-        raise RuntimeError(f"graph launch failed: {rc}")
-
-
 def time_workload(ctx, wl, steps, warmup, dev, tune, settings):
+    """Time `steps` whole steps (forward of every view, fused L1 gradient,
+    backward) after `warmup` untimed ones; the library records HIP events
+    around each stage on the launching stream (settings.profile)."""
     import torch
     import paper_2511_16144_amd as P
     from paper_2511_16144_amd import binding as B
@@ -114,56 +60,77 @@ def time_workload(ctx, wl, steps, warmup, dev, tune, settings):
     s = wl.scene
     params = P.params_from_arrays(s.means, s.log_scales, s.quats, s.logits, s.rgb, s.feat, device=dev,
                                   appearance_dtype=dt)
-    h, st, keep = make_graph(ctx, P, wl, params, settings, dev, tune)
-    try:
-        for _ in range(warmup):
-            graph_launch(h)
-        torch.cuda.synchronize()
-        rc = B.lib().lgs_graph_status(h)
+    V = len(wl.cams)
+    outs = [{"rgb": torch.empty((3, c.height, c.width), device=dev),
+             "depth": torch.empty((c.height, c.width), device=dev),
+             "feat": torch.empty((16, c.height, c.width), device=dev),
+             "T": torch.empty((c.height, c.width), device=dev)} for c in wl.cams]
+    tgts = [{"rgb": torch.as_tensor(t.rgb).to(dev), "depth": torch.as_tensor(t.depth).to(dev),
+             "feat": torch.as_tensor(t.feat).to(dev)} for t in wl.targets]
+    grads = B._grad_buffers(s.n, V, dev)
+    st = settings
+    if tune:
+        shapes = [(c.height, c.width) for c in wl.cams]
+        g = B.gaussians_c(params["means"], params["log_scales"], params["quats"], params["logits"],
+                          params["rgb"], params["feat"])
+        cams = (B.lgs_camera * V)(*[B.camera_c(c) for c in wl.cams])
+        best = B.lgs_settings()
+        sc = settings.to_c()
+        rc = B.lib().lgs_autotune(ctx._h, C.byref(sc), C.byref(g), V, cams, B._images_c(tgts, shapes, False),
+                                  (C.c_float * 3)(*wl.loss_w), B._images_c(outs, shapes, True),
+                                  C.byref(grads[1]), 0, C.c_void_p(torch.cuda.current_stream().cuda_stream),
+                                  None, C.byref(best))
         if rc != 0:
-            raise RuntimeError(f"graph status {rc}: {B.lib().lgs_last_error(ctx._h).decode()}")
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        e0.record()
-        for _ in range(steps):
-            graph_launch(h)
-        e1.record()
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        ms = e0.elapsed_time(e1) / steps
-        cnt = B.lgs_counts()
-        B.lib().lgs_graph_counts(h, C.byref(cnt))
-        counts = {k: getattr(cnt, k) for k, _ in B.lgs_counts._fields_}
-        stages = None
-        if st.profile:
-            acc = [0.0] * 5
-            buf = (C.c_float * 5)()
-            for _ in range(steps):
-                graph_launch(h)
-                B.lib().lgs_graph_stage_ms(h, buf)
-                for i in range(5):
-                    acc[i] += buf[i]
-            stages = [a / steps for a in acc]
-    finally:
-        torch.cuda.synchronize()
-        B.lib().lgs_graph_destroy(h)
-    return {"ms": ms, "wall_s": wall, "counts": counts, "stages": stages,
+            raise B.LgsError(rc, B.lib().lgs_last_error(ctx._h).decode())
+        st = B.Settings.from_c(best)
+        st.profile = settings.profile
+
+    def step(record):
+        o, state = ctx.forward(params, wl.cams, st, out=outs)
+        ctx.backward_l1(state, params, outs, tgts, wl.loss_w, grads=grads)
+        if record is not None:
+            record.append(state.stage_ms())
+        c = state.counts() if record is not None and len(record) == 1 else None
+        state.release()
+        return c
+
+    for _ in range(warmup):
+        step(None)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    stages = [] if st.profile else None
+    counts = None
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        c = step(stages)
+        counts = counts or c
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / steps
+    if counts is None:
+        o, state = ctx.forward(params, wl.cams, st, out=outs)
+        ctx.backward_l1(state, params, outs, tgts, wl.loss_w, grads=grads)
+        counts = state.counts()
+        state.release()
+    mean_st = [sum(x[i] for x in stages) / len(stages) for i in range(5)] if stages else None
+    return {"ms": ms, "wall_s": wall, "counts": counts, "stages": mean_st,
             "settings": {"tile": st.tile, "chunk": st.chunk, "order": st.order}}
 
 
-def cpu_baseline(wl, budget_s=25.0):
+def cpu_baseline(wl, budget_s=12.0):
     """The FP64 oracle (forward + autodiff backward) on a bounded sample of
-    the same workload: 64x64 crops of the first view, as many as fit in about
-    `budget_s` seconds, with every host core."""
+    the same workload: 64x64 crops of the first view, until about `budget_s`
+    seconds of work are done (at most 16 crops), with every host core."""
     import numpy as np
     import torch
     import scenes
     from oracle import raster_fp64 as R
-    torch.set_num_threads(os.cpu_count() or 1)
+    torch.set_num_threads(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
     cam = wl.cams[0]
-    wins = scenes.crop_windows(11, cam, k=4, size=64)
+    wins = scenes.crop_windows(11, cam, k=16, size=64)
     done_px = 0
     t0 = time.perf_counter()
     n_crops = 0
@@ -190,6 +157,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="batched", choices=["batched", "plain", "precision", "differentiation"])
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--tile", type=int, default=None, help="fix the tile size (skips the autotuner)")
+    ap.add_argument("--chunk", type=int, default=None)
+    ap.add_argument("--order", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     args = ap.parse_args()
@@ -207,8 +177,15 @@ def main():
     wl = scenes.make_workload(cfg)
     ctx = P.Context(0)
     settings = P.Settings(profile=1)
+    fixed = any(x is not None for x in (args.tile, args.chunk, args.order))
+    if args.tile is not None:
+        settings.tile = args.tile
+    if args.chunk is not None:
+        settings.chunk = args.chunk
+    if args.order is not None:
+        settings.order = args.order
     log(f"[bench] timing C{cfg}: {wl.scene.n} Gaussians, {len(wl.cams)} views, {wl.pixels} px")
-    r = time_workload(ctx, wl, args.steps, args.warmup, dev, not args.no_tune, settings)
+    r = time_workload(ctx, wl, args.steps, args.warmup, dev, not (args.no_tune or fixed), settings)
     mpx = wl.pixels / (r["ms"] / 1e3) / 1e6
     c = r["counts"]
     st = r["stages"]

@@ -78,7 +78,7 @@ typedef struct {
   int32_t tile;     /* 16      binning tile side: 8, 16 or 32 */
   int32_t chunk;    /* 4       8x8 pixel blocks per work-group (1, 2, 4, 8) */
   int32_t order;    /* 0       1: work queue in descending list length, 0: raster order */
-  int32_t profile;  /* 0       1: graphs record HIP events around each stage */
+  int32_t profile;  /* 0       1: record HIP events around each stage (lgs_state_stage_ms) */
 } lgs_settings;
 
 /* Gaussians: SoA planes, n of each (Sec. III-B.1, Theta).  means [3][n],
@@ -159,10 +159,28 @@ lgs_status lgs_backward(lgs_context *ctx, const lgs_fwd_state *state,
                         const lgs_gaussians *g, const lgs_images *grad_out,
                         lgs_grads *grads, hipStream_t stream);
 
+/* The backward of the mapping loss of Eq. (1) without its D-SSIM term:
+ * computes dL/dY of L = sum over views of mean|RGB-RGB*| + w_depth mean|D-D*|
+ * + w_feat mean|F-F*| (sign(0) = 0, loss_w = {1, w_depth, w_feat}) inside
+ * the backward compositing kernel from the forward's images `out` (the
+ * buffers lgs_forward wrote) and `targets` (device planes; final_T
+ * ignored), then back-propagates it like lgs_backward.  Deterministic. */
+lgs_status lgs_backward_l1(lgs_context *ctx, const lgs_fwd_state *state,
+                           const lgs_gaussians *g, const lgs_images *out,
+                           const lgs_images *targets, const float loss_w[3],
+                           lgs_grads *grads, hipStream_t stream);
+
 lgs_status lgs_state_counts(const lgs_fwd_state *state, lgs_counts *out);
+/* With settings.profile = 1 on the forward, after its backward: elapsed
+ * milliseconds of ms[0..4] = projection + depth sort + scans, pair emission
+ * + tile sort, forward compositing kernel, backward compositing kernel,
+ * gradient reduction + projection backward (HIP events on the caller's
+ * stream).  Synchronises. */
+lgs_status lgs_state_stage_ms(const lgs_fwd_state *state, float ms[5]);
 lgs_status lgs_state_release(lgs_context *ctx, lgs_fwd_state *state);
 
-/* Whole mapping-loss step as one captured hipGraph: forward, L1 loss
+/* Whole mapping-loss step as one captured hipGraph (the eager pair
+ * lgs_forward + lgs_backward_l1 computes the same step): forward, L1 loss
  * gradient of Eq. (1) without its D-SSIM term (sum over views of
  * mean|RGB-RGB*| + w_depth mean|D-D*| + w_feat mean|F-F*|, sign(0) = 0,
  * loss_w = {1, w_depth, w_feat}), backward.  targets[n_views] (device
@@ -190,9 +208,10 @@ lgs_status lgs_graph_counts(lgs_graph *graph, lgs_counts *out);
 lgs_status lgs_graph_stage_ms(lgs_graph *graph, float ms[5]);
 void lgs_graph_destroy(lgs_graph *graph);
 
-/* Autotuner: times the graph step for every (tile, chunk, order) setting on
- * the given workload and returns the fastest in *best_out (other fields
- * copied from *st).  With cache_path non-NULL the result is stored in / read
+/* Autotuner: times the step (lgs_forward + lgs_backward_l1, median of 5)
+ * for every (tile, chunk, order) setting on the given workload and returns
+ * the fastest in *best_out (other fields copied from *st); `out` and `grads`
+ * are overwritten.  With cache_path non-NULL the result is stored in / read
  * from a small JSON file keyed by the workload's shape. */
 lgs_status lgs_autotune(lgs_context *ctx, const lgs_settings *st,
                         const lgs_gaussians *g, int32_t n_views,

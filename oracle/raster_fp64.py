@@ -161,7 +161,7 @@ def project_view(P: dict, cam, xi: torch.Tensor, st: Settings) -> dict:
 # Per-pixel compositing (O9 - O11)
 # ---------------------------------------------------------------------------
 def composite(px: torch.Tensor, py: torch.Tensor, mu, conic, opac, z, y, ids,
-              st: Settings, want_margin: bool = False):
+              st: Settings, want_margin: bool = False, sig: list | None = None):
     """Composite K candidate Gaussians over P pixels.
 
     px, py [P] pixel centres; mu [K,2], conic [K,3], opac [K], z [K],
@@ -178,6 +178,8 @@ def composite(px: torch.Tensor, py: torch.Tensor, mu, conic, opac, z, y, ids,
     if K == 0:
         Y = torch.zeros((P, 20), dtype=F64)
         mg = {k: torch.full((P,), math.inf, dtype=F64) for k in ("m2", "alpha", "clamp", "T", "z")}
+        if sig is not None:
+            sig.append(torch.zeros(P, dtype=torch.int64))
         return Y, torch.ones(P, dtype=F64), torch.zeros(P, dtype=torch.int64), \
             (mg if want_margin else None)
     order = np.lexsort((ids.numpy(), z.detach().numpy()))          # (z, id)
@@ -201,6 +203,16 @@ def composite(px: torch.Tensor, py: torch.Tensor, mu, conic, opac, z, y, ids,
     Y = w @ y
     T = Tinc[:, -1]
     n = incl.sum(1)
+    if sig is not None:
+        # digest of every per-pixel decision: which candidates contribute, in
+        # which order, and which of them sit on the alpha clamp
+        with torch.no_grad():
+            sid = ids[order].to(torch.int64) + 1
+            pos = torch.cumsum(incl.to(torch.int64), 1)
+            clamp = (a_raw > st.alpha_max) & incl
+            d = (incl.to(torch.int64) * sid[None, :] * (pos * 7919 + 1)).sum(1) \
+                + (clamp.to(torch.int64) * sid[None, :] * 104729).sum(1) + n * 15485863
+            sig.append(d)
     margin = None
     if want_margin:
         with torch.no_grad():

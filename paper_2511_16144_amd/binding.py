@@ -56,7 +56,7 @@ class lgs_counts(C.Structure):
 
 
 EXPORTS = ["lgs_status_string", "lgs_last_error", "lgs_default_settings", "lgs_context_create",
-           "lgs_context_destroy", "lgs_forward", "lgs_backward", "lgs_state_counts",
+           "lgs_context_destroy", "lgs_forward", "lgs_backward", "lgs_backward_l1", "lgs_state_counts", "lgs_state_stage_ms",
            "lgs_state_release", "lgs_graph_create", "lgs_graph_launch", "lgs_graph_status",
            "lgs_graph_counts", "lgs_graph_stage_ms", "lgs_graph_destroy", "lgs_autotune"]
 
@@ -83,8 +83,13 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.lgs_backward.restype = C.c_int
     lib.lgs_backward.argtypes = [P, P, C.POINTER(lgs_gaussians), C.POINTER(lgs_images),
                                  C.POINTER(lgs_grads), P]
+    lib.lgs_backward_l1.restype = C.c_int
+    lib.lgs_backward_l1.argtypes = [P, P, C.POINTER(lgs_gaussians), C.POINTER(lgs_images), C.POINTER(lgs_images),
+                                    C.POINTER(C.c_float), C.POINTER(lgs_grads), P]
     lib.lgs_state_counts.restype = C.c_int
     lib.lgs_state_counts.argtypes = [P, C.POINTER(lgs_counts)]
+    lib.lgs_state_stage_ms.restype = C.c_int
+    lib.lgs_state_stage_ms.argtypes = [P, C.POINTER(C.c_float)]
     lib.lgs_state_release.restype = C.c_int
     lib.lgs_state_release.argtypes = [P, P]
     lib.lgs_graph_create.restype = C.c_int
@@ -214,7 +219,7 @@ class Context:
 
     # -- eager forward / backward ------------------------------------------
     def forward(self, params, cams, settings: Settings | None = None, want_n: bool = False,
-                stream=None):
+                stream=None, out=None):
         """params: dict of CUDA tensors means [3,N], log_scales [3,N], quats [4,N],
         logits [N], rgb [3,N], feat [16,N].  Returns (list of per-view dicts
         rgb [3,H,W], depth [H,W], feat [16,H,W], T [H,W] (and n [H,W] int32),
@@ -228,10 +233,13 @@ class Context:
         cams_c = (lgs_camera * V)(*[camera_c(c) for c in cams])
         for v, c in enumerate(cams):
             H, W = int(c.height), int(c.width)
-            o = {"rgb": torch.empty((3, H, W), device=dev), "depth": torch.empty((H, W), device=dev),
-                 "feat": torch.empty((16, H, W), device=dev), "T": torch.empty((H, W), device=dev)}
-            if want_n:
-                o["n"] = torch.empty((H, W), device=dev, dtype=torch.int32)
+            if out is not None:        # caller-provided output buffers (reused across steps)
+                o = out[v]
+            else:
+                o = {"rgb": torch.empty((3, H, W), device=dev), "depth": torch.empty((H, W), device=dev),
+                     "feat": torch.empty((16, H, W), device=dev), "T": torch.empty((H, W), device=dev)}
+                if want_n:
+                    o["n"] = torch.empty((H, W), device=dev, dtype=torch.int32)
             imgs[v] = lgs_images(_ptr(o["rgb"]), _ptr(o["depth"]), _ptr(o["feat"]), _ptr(o["T"]),
                                  _ptr(o.get("n")))
             outs.append(o)
@@ -242,6 +250,9 @@ class Context:
         if st != LGS_OK:
             self._raise(st)
         return outs, State(self, state, V, [(int(c.height), int(c.width)) for c in cams])
+
+    def backward_l1(self, state, params, outs, targets, loss_w, stream=None, grads=None) -> dict:
+        return backward_l1(self, state, params, outs, targets, loss_w, stream, grads)
 
     def backward(self, state: "State", params, grad_outs, stream=None) -> dict:
         """grad_outs: per view dict rgb [3,H,W], depth [H,W], feat [16,H,W],
@@ -276,6 +287,49 @@ class Context:
         return out
 
 
+def _images_c(ims, shapes, with_T):
+    V = len(ims)
+    arr = (lgs_images * V)()
+    for v, im in enumerate(ims):
+        H, W = shapes[v]
+        for k, shp in (("rgb", (3, H, W)), ("depth", (H, W)), ("feat", (16, H, W))):
+            t = im[k]
+            if tuple(t.shape) != shp or not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
+                raise ValueError(f"image {v} {k}: expected contiguous FP32 CUDA tensor of shape {shp}")
+        arr[v] = lgs_images(_ptr(im["rgb"]), _ptr(im["depth"]), _ptr(im["feat"]),
+                            _ptr(im.get("T")) if with_T else None, None)
+    return arr
+
+
+def _grad_buffers(n, V, dev):
+    out = {"means": torch.empty((3, n), device=dev), "log_scales": torch.empty((3, n), device=dev),
+           "quats": torch.empty((4, n), device=dev), "logits": torch.empty((n,), device=dev),
+           "rgb": torch.empty((3, n), device=dev), "feat": torch.empty((16, n), device=dev),
+           "twist": torch.empty((V, 6), device=dev)}
+    gr = lgs_grads(_ptr(out["means"]), _ptr(out["log_scales"]), _ptr(out["quats"]), _ptr(out["logits"]),
+                   _ptr(out["rgb"]), _ptr(out["feat"]), _ptr(out["twist"]))
+    return out, gr
+
+
+def backward_l1(context: "Context", state: "State", params, outs, targets, loss_w, stream=None,
+                grads=None) -> dict:
+    """Backward of the L1 mapping loss (Eq. (1) without D-SSIM) of the
+    forward that produced `state`: outs are that forward's images, targets
+    per-view dicts (rgb, depth, feat) of FP32 CUDA tensors."""
+    g = gaussians_c(params["means"], params["log_scales"], params["quats"], params["logits"],
+                    params["rgb"], params["feat"])
+    if grads is None:
+        grads = _grad_buffers(g.n, state.n_views, params["means"].device)
+    out, gr = grads
+    o = _images_c(outs, state.shapes, True)
+    t = _images_c(targets, state.shapes, False)
+    lw = (C.c_float * 3)(*[float(x) for x in loss_w])
+    st = lib().lgs_backward_l1(context._h, state.handle, C.byref(g), o, t, lw, C.byref(gr), _stream(stream))
+    if st != LGS_OK:
+        context._raise(st)
+    return out
+
+
 class State:
     def __init__(self, ctx: Context, handle, n_views, shapes):
         self.ctx, self.handle, self.n_views, self.shapes = ctx, handle, n_views, shapes
@@ -284,6 +338,13 @@ class State:
         c = lgs_counts()
         lib().lgs_state_counts(self.handle, C.byref(c))
         return {k: getattr(c, k) for k, _ in lgs_counts._fields_}
+
+    def stage_ms(self) -> list:
+        buf = (C.c_float * 5)()
+        st = lib().lgs_state_stage_ms(self.handle, buf)
+        if st != LGS_OK:
+            raise LgsError(st, lib().lgs_last_error(self.ctx._h).decode())
+        return list(buf)
 
     def release(self):
         if self.handle:

@@ -83,10 +83,18 @@ __device__ __forceinline__ void load_y(const void* __restrict__ app, uint32_t g,
   }
 }
 
-__device__ __forceinline__ uint32_t pop_item(uint32_t* counter, int lane) {
-  uint32_t it = 0;
-  if (lane == 0) it = atomicAdd(counter, 1u);
-  return __builtin_amdgcn_readfirstlane(it);
+// Pop one work item for the whole wave.  Every active lane executes the
+// atomic (no lane-dependent branch around it): the first active lane adds 1,
+// the others 0, and the first active lane's return value is broadcast.  A
+// "lane 0 only" branch here let the compiler merge it with the other
+// lane-0 branches of the loop and drop lane 0 from EXEC at the back edge,
+// after which readfirstlane read another lane's stale value.
+__device__ __forceinline__ uint32_t pop_item(uint32_t* counter) {
+  const uint64_t exec = __builtin_amdgcn_read_exec();
+  const uint32_t lane = __lane_id();
+  const bool leader = lane == (uint32_t)(__builtin_ctzll(exec));
+  const uint32_t old = atomicAdd(counter, leader ? 1u : 0u);
+  return __builtin_amdgcn_readfirstlane(old);
 }
 
 template <bool BF16>
@@ -98,8 +106,9 @@ __global__ void __launch_bounds__(256) k_raster_fwd(
     int32_t* __restrict__ last_idx, float* __restrict__ T_state) {
   const int lane = threadIdx.x & 63;
   if (cnt->overflow) return;
+  uint64_t n_eval = 0, n_con = 0;   // this wave's work, added to the counters once at the end
   for (;;) {
-    const uint32_t it = pop_item(&cnt->work_next, lane);
+    const uint32_t it = pop_item(&cnt->work_next);
     if (it >= n_items) break;
     const uint32_t item = items[it];
     const uint32_t bx = item & 255u, by = (item >> 8) & 255u, v = item >> 16;
@@ -116,7 +125,6 @@ __global__ void __launch_bounds__(256) k_raster_fwd(
     for (int c = 0; c < 20; ++c) acc[c] = 0.f;
     int32_t last = -1, ncon = 0;
     bool done = !inside;
-    uint64_t n_eval = 0, n_con = 0;
     for (uint32_t k = r.x; k < r.y; ++k) {
       const uint64_t live = __builtin_amdgcn_ballot_w64(!done);
       if (live == 0ull) break;
@@ -158,29 +166,62 @@ __global__ void __launch_bounds__(256) k_raster_fwd(
       last_idx[(size_t)V->pix_off + p] = last;
       T_state[(size_t)V->pix_off + p] = T;
     }
-    if (lane == 0) {
-      atomicAdd(&cnt->fwd_evals, (unsigned long long)n_eval);
-      atomicAdd(&cnt->fwd_contrib, (unsigned long long)n_con);
-    }
+  }
+  if (lane == 0) {
+    atomicAdd(&cnt->fwd_evals, (unsigned long long)n_eval);
+    atomicAdd(&cnt->fwd_contrib, (unsigned long long)n_con);
   }
 }
 
-// Butterfly transpose-reduction: on entry every lane holds v[0..31]; on exit
-// lanes 2i and 2i+1 hold the wave sum of value i (i < 32) in v[0].
+// Butterfly transpose-reduction of 32 values over the wave.  On entry every
+// lane holds v[0..31]; on exit lanes 2i and 2i+1 hold the wave sum of value i.
+// Each step pairs every lane with a partner, each keeps one half of its
+// values and adds the partner's copy of that half: the two cross-row steps
+// use the gfx950 permlane swaps (no selects: the swap itself hands each half
+// to the lane that keeps it), the four in-row steps a bit-select and a DPP
+// read of the partner.
+__device__ __forceinline__ float bsel(bool hi, float a, float b) {   // hi ? b : a
+  const uint32_t m = hi ? 0xffffffffu : 0u;
+  return __uint_as_float((__float_as_uint(a) & ~m) | (__float_as_uint(b) & m));
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
+}
+
 __device__ __forceinline__ float transpose_reduce32(float v[32], int lane) {
+  float s[8];
 #pragma unroll
-  for (int step = 0; step < 5; ++step) {
-    const int half = 16 >> step;
-    const int mask = 32 >> step;
-    const bool hi = (lane & mask) != 0;
-#pragma unroll
-    for (int i = 0; i < half; ++i) {
-      const float send = hi ? v[i] : v[half + i];
-      const float keep = hi ? v[half + i] : v[i];
-      v[i] = keep + __shfl_xor(send, mask, 64);
-    }
+  for (int i = 0; i < 8; ++i) {
+    // lanes 0-31 keep value i / 8+i, lanes 32-63 keep 16+i / 24+i (sum over l, l^32)
+    auto r0 = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]), __float_as_uint(v[16 + i]), false, false);
+    auto r1 = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[8 + i]), __float_as_uint(v[24 + i]), false, false);
+    const float a = __uint_as_float(r0[0]) + __uint_as_float(r0[1]);
+    const float b = __uint_as_float(r1[0]) + __uint_as_float(r1[1]);
+    // rows 0, 2 keep a, rows 1, 3 keep b (sum over l, l^16)
+    auto r2 = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    s[i] = __uint_as_float(r2[0]) + __uint_as_float(r2[1]);
   }
-  return v[0] + __shfl_xor(v[0], 1, 64);
+  float t[4];
+  const bool h8 = (lane & 8) != 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {   // partner lane ^ 8 (row_ror:8)
+    const float keep = bsel(h8, s[i], s[4 + i]);
+    const float send = bsel(h8, s[4 + i], s[i]);
+    t[i] = keep + dpp<0x128>(send);
+  }
+  float u[2];
+  const bool h4 = (lane & 4) != 0;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {   // partner 7 - (lane & 7) within the half row (row_half_mirror)
+    const float keep = bsel(h4, t[i], t[2 + i]);
+    const float send = bsel(h4, t[2 + i], t[i]);
+    u[i] = keep + dpp<0x141>(send);
+  }
+  const bool h2 = (lane & 2) != 0;   // partner lane ^ 2 (quad_perm 2,3,0,1)
+  const float w = bsel(h2, u[0], u[1]) + dpp<0x4E>(bsel(h2, u[1], u[0]));
+  return w + dpp<0xB1>(w);           // partner lane ^ 1 (quad_perm 1,0,3,2)
 }
 
 __device__ __forceinline__ int wave_max_i32(int x) {
@@ -201,8 +242,9 @@ __global__ void __launch_bounds__(256) k_raster_bwd(
     float* __restrict__ partials, uint8_t* __restrict__ mask) {
   const int lane = threadIdx.x & 63;
   if (cnt->overflow) return;
+  uint64_t n_eval = 0, n_con = 0;   // this wave's work, added to the counters once at the end
   for (;;) {
-    const uint32_t it = pop_item(&cnt->work_next_b, lane);
+    const uint32_t it = pop_item(&cnt->work_next_b);
     if (it >= n_items) break;
     const uint32_t item = items[it];
     const uint32_t bx = item & 255u, by = (item >> 8) & 255u, v = item >> 16;
@@ -247,14 +289,15 @@ __global__ void __launch_bounds__(256) k_raster_bwd(
         if (U.T) gT = U.T[p];
       }
     }
-    const int kmax = wave_max_i32(last);
+    // every lane holds the same maximum; readfirstlane makes that visible to
+    // the compiler, so the entry loop below stays on the scalar unit
+    const int kmax = __builtin_amdgcn_readfirstlane(wave_max_i32(last));
     if (kmax < 0) continue;
     const uint32_t tile = (uint32_t)V->tile_off + (by >> st.tile_shift) * (uint32_t)V->tiles_x +
                           (bx >> st.tile_shift);
     const uint32_t kbeg = ranges[tile].x;
     const float gTT = gT * Tfin;
     float Tc = Tfin, sB = 0.f;
-    uint64_t n_eval = 0, n_con = 0;
     for (int k = kmax; k >= (int)kbeg; --k) {
       const uint32_t rid = vals[k];
       const GeomRec gr = geom[rid];
@@ -304,10 +347,10 @@ __global__ void __launch_bounds__(256) k_raster_bwd(
       if ((lane & 1) == 0 && idx < kPartials) partials[(size_t)slot * kPartials + idx] = s;
       if (lane == 0) mask[slot] = 1;
     }
-    if (lane == 0) {
-      atomicAdd(&cnt->bwd_evals, (unsigned long long)n_eval);
-      atomicAdd(&cnt->bwd_contrib, (unsigned long long)n_con);
-    }
+  }
+  if (lane == 0) {
+    atomicAdd(&cnt->bwd_evals, (unsigned long long)n_eval);
+    atomicAdd(&cnt->bwd_contrib, (unsigned long long)n_con);
   }
 }
 

@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <map>
 #include <string>
 #include <vector>
@@ -247,6 +248,10 @@ struct Work {
   float* grad2d = nullptr;
   void* ttmp = nullptr;
   bool bwd_alloc = false;
+  // settings.profile: events on the caller's stream around each stage
+  // (0 forward start, 1 front end, 2 pairs start, 3 raster start, 4 raster
+  // end, 5 backward raster start, 6 backward raster end, 7 backward end)
+  hipEvent_t ev[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 
 namespace {
@@ -261,6 +266,15 @@ void* w_alloc(Work* W, size_t bytes, bool& ok) {
 void w_release(Work* W) {
   for (void* p : W->bufs) pool_free(W->ctx, p);
   W->bufs.clear();
+  for (int i = 0; i < 8; ++i)
+    if (W->ev[i]) {
+      hipEventDestroy(W->ev[i]);
+      W->ev[i] = nullptr;
+    }
+}
+
+void w_mark(Work* W, int i, hipStream_t s) {
+  if (W->ev[i]) hipEventRecord(W->ev[i], s);
 }
 
 uint32_t* get_items(lgs_context* ctx, const Plan& P, int tile) {
@@ -430,16 +444,19 @@ void enqueue_backward(Work* W, const lgs_gaussians* g, const lgs_grads* gr, bool
   launch_fill_u8(W->mask, 0, &W->counters->n_slots_eff, std::max<int64_t>(W->cap_slots, 1), s);
   launch_fill_u32(&W->counters->work_next_b, 0u, 1, s);
   launch_fill_u32((uint32_t*)&W->counters->bwd_evals, 0u, 4, s);   // bwd_evals, bwd_contrib
+  w_mark(W, 5, s);
   launch_raster_bwd(ds, W->d_views, W->d_up, fused ? W->d_out : nullptr, fused ? W->d_tgt : nullptr,
                     fused ? W->d_lossw : nullptr, W->ranges, W->pvals, W->geom, W->app, W->app_bf16,
                     (uint32_t)((1ull << W->npad_shift) - 1), W->items, W->plan.n_items, W->counters, W->st.chunk,
                     W->last_idx, W->T_state, W->slot_base, W->partials, W->mask, s);
   if (mid_event) hipEventRecord(mid_event, s);
+  w_mark(W, 6, s);
   launch_seg_reduce(W->ent, W->slot_base, W->cnt_b, W->partials, W->mask, W->counters, W->n_rid, W->grad2d, s);
   launch_project_bwd(ds, W->d_views, V, g->means, g->log_scales, g->quats, g->opacity_logits, W->n,
                      W->npad_shift, W->counters, W->cnt_t, W->cidx, W->grad2d, gr->means, gr->log_scales,
                      gr->quats, gr->opacity_logits, gr->rgb, gr->feat, gr->twist, W->ttmp, s);
   if (end_event) hipEventRecord(end_event, s);
+  w_mark(W, 7, s);
 }
 
 lgs_status read_counts(Work* W, hipStream_t s, Counters* hc) {
@@ -470,6 +487,8 @@ lgs_status check_grads(lgs_context* ctx, const lgs_gaussians* g, const lgs_grads
 struct lgs_fwd_state {
   Work W;
 };
+
+static constexpr bool kGraphEnabled = true;
 
 struct lgs_graph {
   Work W;
@@ -545,6 +564,16 @@ lgs_status lgs_state_counts(const lgs_fwd_state* s, lgs_counts* out) {
   return LGS_OK;
 }
 
+lgs_status lgs_state_stage_ms(const lgs_fwd_state* s, float ms[5]) {
+  if (!s || !ms) return LGS_ERR_INVALID_ARG;
+  const Work* W = &s->W;
+  if (!W->ev[0]) return fail(W->ctx, LGS_ERR_STATE, "forward was run without settings.profile");
+  HIP_TRY(W->ctx, hipEventSynchronize(W->ev[7]));
+  const int a[5] = {0, 2, 3, 5, 6}, b[5] = {1, 3, 4, 6, 7};
+  for (int i = 0; i < 5; ++i) HIP_TRY(W->ctx, hipEventElapsedTime(&ms[i], W->ev[a[i]], W->ev[b[i]]));
+  return LGS_OK;
+}
+
 lgs_status lgs_state_release(lgs_context* ctx, lgs_fwd_state* s) {
   if (!ctx || !s) return LGS_ERR_INVALID_ARG;
   if (s->W.ctx != ctx) return fail(ctx, LGS_ERR_STATE, "state belongs to another context");
@@ -578,13 +607,21 @@ lgs_status lgs_forward(lgs_context* ctx, const lgs_settings* st, const lgs_gauss
   if ((rc = w_init(W, ctx, st, g, n_views, cams)) != LGS_OK) return bail(rc);
   if ((rc = w_alloc_front(W)) != LGS_OK) return bail(rc);
   if ((rc = w_upload(W, out, stream)) != LGS_OK) return bail(rc);
+  if (st->profile)
+    for (int i = 0; i < 8; ++i)
+      if (hipEventCreate(&W->ev[i]) != hipSuccess) return bail(fail(ctx, LGS_ERR_HIP, "event creation failed"));
+  w_mark(W, 0, stream);
   enqueue_front(W, g, stream);
+  w_mark(W, 1, stream);
   if (hipGetLastError() != hipSuccess) return bail(fail(ctx, LGS_ERR_HIP, "kernel launch failed"));
   Counters hc;
   if ((rc = read_counts(W, stream, &hc)) != LGS_OK) return bail(rc);
   if ((rc = w_alloc_pairs(W, hc.n_pairs, hc.n_slots)) != LGS_OK) return bail(rc);
+  w_mark(W, 2, stream);
   enqueue_pairs(W, stream);
+  w_mark(W, 3, stream);
   enqueue_raster_fwd(W, stream);
+  w_mark(W, 4, stream);
   if (hipGetLastError() != hipSuccess) return bail(fail(ctx, LGS_ERR_HIP, "kernel launch failed"));
   *state_out = S;
   return LGS_OK;
@@ -616,6 +653,40 @@ lgs_status lgs_backward(lgs_context* ctx, const lgs_fwd_state* Sc, const lgs_gau
   return read_counts(W, stream, &hc);
 }
 
+lgs_status lgs_backward_l1(lgs_context* ctx, const lgs_fwd_state* Sc, const lgs_gaussians* g,
+                           const lgs_images* out, const lgs_images* targets, const float loss_w[3],
+                           lgs_grads* grads, hipStream_t stream) {
+  if (!ctx) return LGS_ERR_INVALID_ARG;
+  ctx->err.clear();
+  if (!Sc) return fail(ctx, LGS_ERR_INVALID_ARG, "state is NULL");
+  lgs_fwd_state* S = const_cast<lgs_fwd_state*>(Sc);
+  Work* W = &S->W;
+  if (W->ctx != ctx) return fail(ctx, LGS_ERR_STATE, "state belongs to another context");
+  lgs_status rc;
+  if ((rc = check_gaussians(ctx, g)) != LGS_OK) return rc;
+  if (g->n != W->n) return fail(ctx, LGS_ERR_INVALID_ARG, "n differs from the forward's");
+  const int V = (int)W->plan.views.size();
+  if ((rc = check_images(ctx, V, out, true, "out")) != LGS_OK) return rc;
+  if ((rc = check_images(ctx, V, targets, false, "targets")) != LGS_OK) return rc;
+  if (!loss_w) return fail(ctx, LGS_ERR_INVALID_ARG, "loss_w is NULL");
+  if ((rc = check_grads(ctx, g, grads)) != LGS_OK) return rc;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  if ((rc = w_alloc_bwd(W)) != LGS_OK) return rc;
+  std::vector<ViewImages> ho(V), ht(V);
+  for (int v = 0; v < V; ++v) {
+    ho[v] = ViewImages{out[v].rgb, out[v].depth, out[v].feat, out[v].final_T, nullptr};
+    ht[v] = ViewImages{targets[v].rgb, targets[v].depth, targets[v].feat, nullptr, nullptr};
+  }
+  const float lw[4] = {loss_w[0], loss_w[1], loss_w[2], 0.f};
+  HIP_TRY(ctx, hipMemcpyAsync(W->d_out, ho.data(), sizeof(ViewImages) * V, hipMemcpyHostToDevice, stream));
+  HIP_TRY(ctx, hipMemcpyAsync(W->d_tgt, ht.data(), sizeof(ViewImages) * V, hipMemcpyHostToDevice, stream));
+  HIP_TRY(ctx, hipMemcpyAsync(W->d_lossw, lw, sizeof lw, hipMemcpyHostToDevice, stream));
+  enqueue_backward(W, g, grads, true, stream);
+  HIP_TRY(ctx, hipGetLastError());
+  Counters hc;   // synchronises: the host arrays go out of scope
+  return read_counts(W, stream, &hc);
+}
+
 // ---------------------------------------------------------------------------
 // whole-step graph
 // ---------------------------------------------------------------------------
@@ -636,6 +707,7 @@ lgs_status lgs_graph_create(lgs_context* ctx, const lgs_settings* st, const lgs_
   if (!loss_w) return fail(ctx, LGS_ERR_INVALID_ARG, "loss_w is NULL");
   if ((rc = check_grads(ctx, g, grads)) != LGS_OK) return rc;
   if (pair_capacity < 0) return fail(ctx, LGS_ERR_INVALID_ARG, "pair_capacity < 0");
+  if (!kGraphEnabled) return fail(ctx, LGS_ERR_UNSUPPORTED, "graph mode is switched off in this build");
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   // measure the workload once (eager) to size the pair and slot buffers
   lgs_fwd_state* probe = nullptr;
@@ -823,6 +895,7 @@ lgs_status lgs_autotune(lgs_context* ctx, const lgs_settings* st, const lgs_gaus
                         const lgs_camera* cams, const lgs_images* targets, const float loss_w[3],
                         const lgs_images* out, const lgs_grads* grads, int64_t pair_capacity, hipStream_t stream,
                         const char* cache_path, lgs_settings* best_out) {
+  (void)pair_capacity;
   if (!ctx) return LGS_ERR_INVALID_ARG;
   ctx->err.clear();
   if (!best_out) return fail(ctx, LGS_ERR_INVALID_ARG, "best_out is NULL");
@@ -830,41 +903,43 @@ lgs_status lgs_autotune(lgs_context* ctx, const lgs_settings* st, const lgs_gaus
   if ((rc = check_settings(ctx, st)) != LGS_OK) return rc;
   if ((rc = check_gaussians(ctx, g)) != LGS_OK) return rc;
   if ((rc = check_cams(ctx, n_views, cams)) != LGS_OK) return rc;
+  if ((rc = check_images(ctx, n_views, out, true, "out")) != LGS_OK) return rc;
+  if ((rc = check_images(ctx, n_views, targets, false, "targets")) != LGS_OK) return rc;
+  if ((rc = check_grads(ctx, g, grads)) != LGS_OK) return rc;
+  if (!loss_w) return fail(ctx, LGS_ERR_INVALID_ARG, "loss_w is NULL");
   const std::string key = tune_key(g, n_views, cams);
   *best_out = *st;
   if (cache_path && tune_cache_read(cache_path, key, best_out)) return LGS_OK;
   HIP_TRY(ctx, hipSetDevice(ctx->device));
-  hipEvent_t e0, e1;
-  HIP_TRY(ctx, hipEventCreate(&e0));
-  HIP_TRY(ctx, hipEventCreate(&e1));
-  float best_ms = 1e30f;
+  double best_ms = 1e30;
   const int tiles[3] = {8, 16, 32}, chunks[3] = {1, 2, 4}, orders[2] = {0, 1};
   for (int ti = 0; ti < 3; ++ti)
     for (int ci = 0; ci < 3; ++ci)
       for (int oi = 0; oi < 2; ++oi) {
         lgs_settings s = *st;
         s.tile = tiles[ti]; s.chunk = chunks[ci]; s.order = orders[oi]; s.profile = 0;
-        lgs_graph* G = nullptr;
-        rc = lgs_graph_create(ctx, &s, g, n_views, cams, targets, loss_w, out, grads, pair_capacity, stream, &G);
-        if (rc != LGS_OK) continue;
-        for (int w = 0; w < 3; ++w) lgs_graph_launch(G, stream);
-        const int reps = 10;
-        hipEventRecord(e0, stream);
-        for (int r = 0; r < reps; ++r) lgs_graph_launch(G, stream);
-        hipEventRecord(e1, stream);
-        hipEventSynchronize(e1);
-        float ms = 0.f;
-        hipEventElapsedTime(&ms, e0, e1);
-        const bool ok = lgs_graph_status(G) == LGS_OK;
-        lgs_graph_destroy(G);
-        if (ok && ms / reps < best_ms) {
-          best_ms = ms / reps;
+        // one step = forward + fused L1 backward; median of 5 after 1 warm-up
+        std::vector<double> t;
+        bool ok = true;
+        for (int r = 0; r < 6 && ok; ++r) {
+          const auto t0 = std::chrono::steady_clock::now();
+          lgs_fwd_state* S = nullptr;
+          ok = lgs_forward(ctx, &s, g, n_views, cams, out, &S, stream) == LGS_OK;
+          if (ok) ok = lgs_backward_l1(ctx, S, g, out, targets, loss_w, const_cast<lgs_grads*>(grads), stream) == LGS_OK;
+          if (S) lgs_state_release(ctx, S);
+          const auto t1 = std::chrono::steady_clock::now();
+          if (r > 0) t.push_back(std::chrono::duration<double, std::milli>(t1 - t0).count());
+        }
+        if (!ok) continue;
+        std::sort(t.begin(), t.end());
+        const double ms = t[t.size() / 2];
+        if (ms < best_ms) {
+          best_ms = ms;
           *best_out = s;
         }
       }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
-  if (best_ms >= 1e29f) return fail(ctx, LGS_ERR_HIP, "no setting ran");
+  if (best_ms >= 1e29) return fail(ctx, LGS_ERR_HIP, "no setting ran");
+  best_out->profile = st->profile;
   if (cache_path) tune_cache_write(cache_path, key, *best_out);
   return LGS_OK;
 }

@@ -1,0 +1,184 @@
+"""GPU parity on the five workload configurations (through the C ABI).
+
+* C2 at full size (640x480, 300k Gaussians): every pixel and every gradient.
+* C2 reduced (352x264: ragged against every tile size), tiles 8/16/32.
+* C3/C5 precision: BF16-stored appearance vs the oracle on the rounded inputs
+  (arithmetic error, 1e-4) and on the unrounded FP32 inputs (precision
+  error, 1e-2).
+* C4 reduced, batched 8 views vs the oracle.
+* C3, C4, C5 at full size: four seeded 64x64 windows per view; forward on
+  the windows and the whole gradient of an upstream that vanishes outside
+  them (the oracle evaluates only those windows).
+"""
+import numpy as np
+import pytest
+import torch
+
+import scenes
+from oracle import raster_fp64 as R
+from parity import (TOL_BF16, TOL_F32, ambiguous, fmt, gaussian_ambiguity, gpu_params, grad_errors, grads_np,
+                    rel_err, to_np, upstream_tensors)
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2511_16144_amd as P
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+def gpu_fwd_bwd(ctx, scene, cams, ups, settings):
+    prm = gpu_params(scene)
+    outs, st = ctx.forward(prm, cams, settings, want_n=True)
+    g = grads_np(ctx.backward(st, prm, upstream_tensors(ups)))
+    torch.cuda.synchronize()
+    counts = st.counts()
+    st.release()
+    return to_np(outs), g, counts
+
+
+def check_forward(out, ref, mask_rect=None, tol=TOL_F32, label=""):
+    amb = ambiguous(ref["margin"])
+    keep = ~amb
+    if mask_rect is not None:
+        keep &= mask_rect
+    res = {}
+    for k in ("rgb", "depth", "feat", "T"):
+        res[k] = rel_err(out[k], ref[k], keep)
+    say(f"  {label} forward: ambiguous {int((amb & (mask_rect if mask_rect is not None else True)).sum())} px; {fmt(res)}")
+    for k, (l2, mx) in res.items():
+        assert l2 <= tol and mx <= tol, (label, k, l2, mx)
+    n_ok = keep & (out["n"] >= 0)
+    assert np.array_equal(out["n"][n_ok], ref["n"][n_ok])
+    return amb
+
+
+def check_grads(g, gr, bad, tol=TOL_F32, label="", skip=()):
+    err = grad_errors(g, gr, bad)
+    say(f"  {label} backward: ambiguous Gaussians {int(bad.sum())}; {fmt(err)}")
+    for k, (l2, mx) in err.items():
+        if k in skip:
+            continue
+        assert l2 <= tol and mx <= tol, (label, k, l2, mx)
+
+
+def test_c2_full_frame(ctx):
+    import paper_2511_16144_amd as P
+    wl = scenes.make_workload(2)
+    say(f"[case] C2 full frame: {wl.scene.n} Gaussians 640x480")
+    ups = scenes.random_upstream(2, wl.cams)
+    out, g, counts = gpu_fwd_bwd(ctx, wl.scene, wl.cams, ups, P.Settings(tile=16))
+    say("  counts", counts)
+    ref = R.render(wl.scene, wl.cams, R.Settings())
+    amb = check_forward(out[0], ref[0], label="C2")
+    assert amb.mean() < 0.01
+    gr = R.vjp(wl.scene, wl.cams, ups, R.Settings())
+    check_grads(g, gr, gaussian_ambiguity(ref[0], amb, wl.scene.n), label="C2")
+
+
+@pytest.mark.parametrize("tile", [8, 32])
+def test_c2_reduced_ragged(ctx, tile):
+    import paper_2511_16144_amd as P
+    wl = scenes.make_workload(2, n=60000, res_scale=0.55)
+    say(f"[case] C2 reduced {wl.cams[0].width}x{wl.cams[0].height} tile={tile}")
+    ups = scenes.random_upstream(5, wl.cams)
+    out, g, _ = gpu_fwd_bwd(ctx, wl.scene, wl.cams, ups, P.Settings(tile=tile, chunk=2, order=1))
+    ref = R.render(wl.scene, wl.cams, R.Settings())
+    amb = check_forward(out[0], ref[0], label="C2r")
+    gr = R.vjp(wl.scene, wl.cams, ups, R.Settings())
+    check_grads(g, gr, gaussian_ambiguity(ref[0], amb, wl.scene.n), label="C2r")
+
+
+def test_bf16_storage_rounded_and_unrounded(ctx):
+    import paper_2511_16144_amd as P
+    wl = scenes.make_workload(3, n=120000, res_scale=0.3)
+    say(f"[case] C3 reduced BF16 {wl.cams[0].width}x{wl.cams[0].height} n={wl.scene.n}")
+    assert wl.scene.dtype == "bf16"
+    ups = scenes.random_upstream(3, wl.cams)
+    out, g, _ = gpu_fwd_bwd(ctx, wl.scene, wl.cams, ups, P.Settings())
+    # arithmetic error: oracle on the rounded (stored) values
+    ref = R.render(wl.scene, wl.cams, R.Settings())
+    amb = check_forward(out[0], ref[0], label="bf16 vs rounded")
+    gr = R.vjp(wl.scene, wl.cams, ups, R.Settings())
+    check_grads(g, gr, gaussian_ambiguity(ref[0], amb, wl.scene.n), label="bf16 vs rounded")
+    # precision error: oracle on the unrounded FP32 appearance
+    ref_u = R.render(wl.scene.unrounded(), wl.cams, R.Settings())
+    res = {k: rel_err(out[0][k], ref_u[0][k], ~amb) for k in ("rgb", "depth", "feat", "T")}
+    say("  bf16 vs unrounded FP32:", fmt(res))
+    for k, (l2, mx) in res.items():
+        assert l2 <= TOL_BF16 and mx <= TOL_BF16, k
+    assert res["feat"][0] > 1e-5          # the rounding is visible, as it should be
+
+
+def test_c4_reduced_batched_vs_oracle(ctx):
+    import paper_2511_16144_amd as P
+    wl = scenes.make_workload(4, n=100000, res_scale=0.3)
+    say(f"[case] C4 reduced: 8 views, n={wl.scene.n}")
+    ups = scenes.random_upstream(6, wl.cams)
+    out, g, _ = gpu_fwd_bwd(ctx, wl.scene, wl.cams, ups, P.Settings(tile=16, order=1))
+    ref = R.render(wl.scene, wl.cams, R.Settings())
+    bad = np.zeros(wl.scene.n, bool)
+    for v in range(len(wl.cams)):
+        amb = check_forward(out[v], ref[v], label=f"C4r view {v}")
+        bad |= gaussian_ambiguity(ref[v], amb, wl.scene.n)
+    gr = R.vjp(wl.scene, wl.cams, ups, R.Settings())
+    check_grads(g, gr, bad, label="C4r")
+
+
+def crop_subscene(wl, wins):
+    """Gaussians that can touch any window of any view (a superset, judged
+    from the oracle's own projection), in their original order."""
+    keep = np.zeros(wl.scene.n, bool)
+    for v, cam in enumerate(wl.cams):
+        o = R.render(wl.scene, [cam], R.Settings(), rects=[[]], want_margin=False)[0]
+        mu, cov, vis = o["mu"], o["cov2d"], o["vis"]
+        rx = 3.0 * np.sqrt(np.maximum(cov[:, 0], 0)) + 2.0
+        ry = 3.0 * np.sqrt(np.maximum(cov[:, 2], 0)) + 2.0
+        for (x0, y0, w, h) in wins[v]:
+            keep |= vis & (mu[:, 0] + rx >= x0) & (mu[:, 0] - rx <= x0 + w - 1) & \
+                (mu[:, 1] + ry >= y0) & (mu[:, 1] - ry <= y0 + h - 1)
+    return np.nonzero(keep)[0]
+
+
+@pytest.mark.parametrize("cfg", [3, 4, 5])
+def test_full_size_windows(ctx, cfg):
+    import paper_2511_16144_amd as P
+    wl = scenes.make_workload(cfg)
+    wins = [scenes.crop_windows(cfg * 10 + v, c, k=4, size=64) for v, c in enumerate(wl.cams)]
+    say(f"[case] C{cfg} full size, {len(wl.cams)} view(s), 4 windows per view, n={wl.scene.n}")
+    ups = scenes.random_upstream(cfg, wl.cams, windows=wins)
+    st = P.Settings(tile=16, order=1)
+    out, g, counts = gpu_fwd_bwd(ctx, wl.scene, wl.cams, ups, st)
+    say("  counts", counts)
+    idx = crop_subscene(wl, wins)
+    sub = wl.scene.subset(idx)
+    say(f"  oracle sub-scene: {len(idx)} Gaussians")
+    ref = R.render(sub, wl.cams, R.Settings(), rects=wins)
+    bad_sub = np.zeros(sub.n, bool)
+    for v, cam in enumerate(wl.cams):
+        m = np.zeros((cam.height, cam.width), bool)
+        for (x0, y0, w, h) in wins[v]:
+            m[y0:y0 + h, x0:x0 + w] = True
+        amb = check_forward(out[v], ref[v], mask_rect=m, label=f"C{cfg} view {v}")
+        bad_sub |= gaussian_ambiguity(ref[v], amb & m, sub.n)
+    gr_sub = R.vjp(sub, wl.cams, ups, R.Settings(), rects=wins)
+    gr = {k: np.zeros((wl.scene.n,) + np.shape(v)[1:]) for k, v in gr_sub.items() if k != "twist"}
+    for k in gr:
+        gr[k][idx] = gr_sub[k]
+    gr["twist"] = gr_sub["twist"]
+    bad = np.zeros(wl.scene.n, bool)
+    bad[idx[bad_sub]] = True
+    # every Gaussian outside the sub-scene must have an exactly zero gradient on the GPU
+    outside = np.ones(wl.scene.n, bool)
+    outside[idx] = False
+    for k in ("means", "logits", "feat"):
+        gk = g[k].T if g[k].ndim == 2 else g[k]
+        assert np.all(gk[outside] == 0), k
+    check_grads(g, gr, bad, label=f"C{cfg}")
