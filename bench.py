@@ -120,6 +120,88 @@ def time_workload(ctx, wl, steps, warmup, dev, tune, settings):
             "settings": {"tile": st.tile, "chunk": st.chunk, "order": st.order}}
 
 
+def time_workload_graph(ctx, wl, steps, warmup, dev, tune, settings):
+    """Same step as `time_workload`, captured once as a hipGraph by the
+    library (lgs_graph_create) and replayed: one launch per step.  Stage times
+    come from HIP events captured in the graph."""
+    import torch
+    import paper_2511_16144_amd as P
+    from paper_2511_16144_amd import binding as B
+    dt = torch.bfloat16 if wl.scene.dtype == "bf16" else torch.float32
+    s = wl.scene
+    params = P.params_from_arrays(s.means, s.log_scales, s.quats, s.logits, s.rgb, s.feat, device=dev,
+                                  appearance_dtype=dt)
+    V = len(wl.cams)
+    shapes = [(c.height, c.width) for c in wl.cams]
+    outs = [{"rgb": torch.empty((3, c.height, c.width), device=dev),
+             "depth": torch.empty((c.height, c.width), device=dev),
+             "feat": torch.empty((16, c.height, c.width), device=dev),
+             "T": torch.empty((c.height, c.width), device=dev)} for c in wl.cams]
+    tgts = [{"rgb": torch.as_tensor(t.rgb).to(dev), "depth": torch.as_tensor(t.depth).to(dev),
+             "feat": torch.as_tensor(t.feat).to(dev)} for t in wl.targets]
+    grads = B._grad_buffers(s.n, V, dev)
+    g = B.gaussians_c(params["means"], params["log_scales"], params["quats"], params["logits"],
+                      params["rgb"], params["feat"])
+    cams = (B.lgs_camera * V)(*[B.camera_c(c) for c in wl.cams])
+    im, ti = B._images_c(outs, shapes, True), B._images_c(tgts, shapes, False)
+    lw = (C.c_float * 3)(*wl.loss_w)
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    st = settings.to_c()
+    if tune:
+        best = B.lgs_settings()
+        rc = B.lib().lgs_autotune(ctx._h, C.byref(st), C.byref(g), V, cams, ti, lw, im, C.byref(grads[1]), 0,
+                                  stream, None, C.byref(best))
+        if rc != 0:
+            raise B.LgsError(rc, B.lib().lgs_last_error(ctx._h).decode())
+        st = best
+        st.profile = settings.profile
+    h = C.c_void_p()
+    rc = B.lib().lgs_graph_create(ctx._h, C.byref(st), C.byref(g), V, cams, ti, lw, im, C.byref(grads[1]), 0,
+                                  stream, C.byref(h))
+    if rc != 0:
+        raise B.LgsError(rc, B.lib().lgs_last_error(ctx._h).decode())
+
+    def launch():
+        rc = B.lib().lgs_graph_launch(h, C.c_void_p(torch.cuda.current_stream().cuda_stream))
+        if rc != 0:
+            raise RuntimeError(f"graph launch failed: {rc}")
+    try:
+        for _ in range(warmup):
+            launch()
+        torch.cuda.synchronize()
+        if B.lib().lgs_graph_status(h) != 0:
+            raise RuntimeError(B.lib().lgs_last_error(ctx._h).decode())
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record()
+        for _ in range(steps):
+            launch()
+        e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = e0.elapsed_time(e1) / steps
+        cnt = B.lgs_counts()
+        B.lib().lgs_graph_counts(h, C.byref(cnt))
+        counts = {k: getattr(cnt, k) for k, _ in B.lgs_counts._fields_}
+        stages = None
+        if st.profile:     # the captured events: one readout per replay, K more replays
+            acc = [0.0] * 5
+            buf = (C.c_float * 5)()
+            for _ in range(steps):
+                launch()
+                B.lib().lgs_graph_stage_ms(h, buf)
+                for i in range(5):
+                    acc[i] += buf[i]
+            stages = [x / steps for x in acc]
+    finally:
+        torch.cuda.synchronize()
+        B.lib().lgs_graph_destroy(h)
+    return {"ms": ms, "wall_s": wall, "counts": counts, "stages": stages,
+            "settings": {"tile": st.tile, "chunk": st.chunk, "order": st.order}}
+
+
 def cpu_baseline(wl, budget_s=12.0):
     """The FP64 oracle (forward + autodiff backward) on a bounded sample of
     the same workload: 64x64 crops of the first view, until about `budget_s`
@@ -157,6 +239,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="batched", choices=["batched", "plain", "precision", "differentiation"])
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--mode", default="eager", choices=["eager", "graph"],
+                    help="eager: lgs_forward + lgs_backward_l1 per step; graph: one captured launch per step")
     ap.add_argument("--tile", type=int, default=None, help="fix the tile size (skips the autotuner)")
     ap.add_argument("--chunk", type=int, default=None)
     ap.add_argument("--order", type=int, default=None)
@@ -185,7 +269,8 @@ def main():
     if args.order is not None:
         settings.order = args.order
     log(f"[bench] timing C{cfg}: {wl.scene.n} Gaussians, {len(wl.cams)} views, {wl.pixels} px")
-    r = time_workload(ctx, wl, args.steps, args.warmup, dev, not (args.no_tune or fixed), settings)
+    timer = time_workload_graph if args.mode == "graph" else time_workload
+    r = timer(ctx, wl, args.steps, args.warmup, dev, not (args.no_tune or fixed), settings)
     mpx = wl.pixels / (r["ms"] / 1e3) / 1e6
     c = r["counts"]
     st = r["stages"]
@@ -209,7 +294,8 @@ def main():
            "data": "synthetic (seeded room-surface scenes shaped like indoor RGB-D keyframes)",
            "config": {"workload": wl.name, "gaussians": wl.scene.n,
                       "views": [f"{cc.width}x{cc.height}" for cc in wl.cams],
-                      "appearance_storage": wl.scene.dtype, "loss_w": list(wl.loss_w), **r["settings"],
+                      "appearance_storage": wl.scene.dtype, "loss_w": list(wl.loss_w), "mode": args.mode,
+                      **r["settings"],
                       "parallelism": "single GPU"},
            "roofline": roof, "stages_ms": stages,
            "forward_compositing": {"TFLOP/s": fwd_tf, "frac": fwd_tf / PEAK_FP32_TFLOPS if fwd_tf else None},
@@ -217,7 +303,7 @@ def main():
     if not args.no_plain and cfg != 2:
         log("[bench] timing the plain FP32 single-view form (C2)")
         wl2 = scenes.make_workload(2)
-        r2 = time_workload(ctx, wl2, args.steps, args.warmup, dev, not args.no_tune, P.Settings())
+        r2 = timer(ctx, wl2, args.steps, args.warmup, dev, not args.no_tune, P.Settings())
         out["plain_fp32"] = {"workload": wl2.name, "Mpixel/s": round(wl2.pixels / (r2["ms"] / 1e3) / 1e6, 3),
                              "ms_per_step": round(r2["ms"], 4), **r2["settings"]}
         out["batched_bf16_over_plain_fp32"] = round(mpx / out["plain_fp32"]["Mpixel/s"], 3)
