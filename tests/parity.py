@@ -28,6 +28,18 @@ TOL_F32 = 1e-4     # FP32 path vs FP64 oracle on the same inputs
 TOL_BF16 = 1e-2    # BF16-stored appearance vs the oracle on unrounded inputs
 
 
+def mask_upstream(ups, ambs):
+    """Zero the upstream gradient at ambiguous pixels (per view), so the
+    gradient comparison can include every Gaussian: a pixel with zero upstream
+    contributes nothing to any gradient, whichever branch it took."""
+    out = []
+    for u, a in zip(ups, ambs):
+        u = np.array(u, np.float32, copy=True)
+        u[:, a] = 0.0
+        out.append(u)
+    return out
+
+
 def ambiguous(margin: dict) -> np.ndarray:
     m = np.zeros_like(margin["m2"], dtype=bool)
     for k, thr in AMBIG.items():
