@@ -246,6 +246,9 @@ def main():
     ap.add_argument("--order", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB device-to-device three times: a kernel of known HBM traffic "
+                         "against which rocprofv3 FETCH_SIZE / WRITE_SIZE counts are scaled")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only: this build has no multi-GPU path (asked for --gpus {args.gpus})",
@@ -259,6 +262,15 @@ def main():
     cfg = {"batched": 4, "plain": 2, "precision": 3, "differentiation": 5}[args.workload]
     log(f"[bench] building workload C{cfg}")
     wl = scenes.make_workload(cfg)
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.rand(n, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] copy calibration: {args.copy_calibration} MiB read + {args.copy_calibration} MiB written, x3")
+        del a, b
     ctx = P.Context(0)
     settings = P.Settings(profile=1)
     fixed = any(x is not None for x in (args.tile, args.chunk, args.order))
@@ -274,6 +286,15 @@ def main():
     mpx = wl.pixels / (r["ms"] / 1e3) / 1e6
     c = r["counts"]
     st = r["stages"]
+    if args.mode == "graph":
+        # per-stage times come from the eager form of the same step with the
+        # same settings: HIP events on the launching stream around each kernel
+        fixed_st = P.Settings(profile=1, **r["settings"])
+        re = time_workload(ctx, wl, args.steps, args.warmup, dev, False, fixed_st)
+        st = re["stages"]
+        c = re["counts"]
+    if st and min(st) <= 0.0:
+        st = None
     names = ["project+depth sort+scans", "pair emission+tile sort", "forward compositing",
              "backward compositing", "gradient reduction+projection backward"]
     stages = {n: round(v, 4) for n, v in zip(names, st)} if st else None
@@ -288,6 +309,7 @@ def main():
             "flops_per_unit": {"eval": FLOPS_EVAL, "contrib": FLOPS_BWD_CONTRIB}}
     fwd_fl = FLOPS_EVAL * c["fwd_evals"] + FLOPS_FWD_CONTRIB * c["fwd_contrib"]
     fwd_tf = fwd_fl / (st[2] / 1e3) / 1e12 if st else None
+    eager_ms = re["ms"] if args.mode == "graph" else None
     out = {"metric": METRIC, "value": round(mpx, 3), "unit": "Mpixel/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(r["ms"], 4), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32",
@@ -300,6 +322,8 @@ def main():
            "roofline": roof, "stages_ms": stages,
            "forward_compositing": {"TFLOP/s": fwd_tf, "frac": fwd_tf / PEAK_FP32_TFLOPS if fwd_tf else None},
            "counts": c}
+    if eager_ms is not None:
+        out["eager_ms_per_step"] = round(eager_ms, 4)
     if not args.no_plain and cfg != 2:
         log("[bench] timing the plain FP32 single-view form (C2)")
         wl2 = scenes.make_workload(2)
