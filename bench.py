@@ -122,8 +122,7 @@ def time_workload(ctx, wl, steps, warmup, dev, tune, settings):
 
 def time_workload_graph(ctx, wl, steps, warmup, dev, tune, settings):
     """Same step as `time_workload`, captured once as a hipGraph by the
-    library (lgs_graph_create) and replayed: one launch per step.  Stage times
-    come from HIP events captured in the graph."""
+    library (lgs_graph_create) and replayed: one launch per step."""
     import torch
     import paper_2511_16144_amd as P
     from paper_2511_16144_amd import binding as B
@@ -154,7 +153,7 @@ def time_workload_graph(ctx, wl, steps, warmup, dev, tune, settings):
         if rc != 0:
             raise B.LgsError(rc, B.lib().lgs_last_error(ctx._h).decode())
         st = best
-        st.profile = settings.profile
+    st.profile = 0     # one graph for the whole step; stage times come from the eager form
     h = C.c_void_p()
     rc = B.lib().lgs_graph_create(ctx._h, C.byref(st), C.byref(g), V, cams, ti, lw, im, C.byref(grads[1]), 0,
                                   stream, C.byref(h))
@@ -186,15 +185,6 @@ def time_workload_graph(ctx, wl, steps, warmup, dev, tune, settings):
         B.lib().lgs_graph_counts(h, C.byref(cnt))
         counts = {k: getattr(cnt, k) for k, _ in B.lgs_counts._fields_}
         stages = None
-        if st.profile:     # the captured events: one readout per replay, K more replays
-            acc = [0.0] * 5
-            buf = (C.c_float * 5)()
-            for _ in range(steps):
-                launch()
-                B.lib().lgs_graph_stage_ms(h, buf)
-                for i in range(5):
-                    acc[i] += buf[i]
-            stages = [x / steps for x in acc]
     finally:
         torch.cuda.synchronize()
         B.lib().lgs_graph_destroy(h)

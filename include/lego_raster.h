@@ -201,10 +201,13 @@ lgs_status lgs_graph_launch(lgs_graph *graph, hipStream_t stream);
 lgs_status lgs_graph_status(lgs_graph *graph);
 /* Work counts of the graph's last launch (synchronises with it). */
 lgs_status lgs_graph_counts(lgs_graph *graph, lgs_counts *out);
-/* With settings.profile = 1: elapsed milliseconds of the last launch's
- * stages, ms[0..4] = projection + depth sort + scans, pair emission + tile
- * sort, forward compositing, backward compositing (with the fused L1
- * gradient), gradient reduction + projection backward.  Synchronises. */
+/* With settings.profile = 1 at creation, the step is captured as five
+ * graphs, one per stage, which lgs_graph_launch launches back to back with
+ * HIP events recorded between them on the launching stream (same results as
+ * the one-graph form).  Elapsed milliseconds of the last launch's stages,
+ * ms[0..4] = projection + depth sort + scans, pair emission + tile sort,
+ * forward compositing, backward compositing (with the fused L1 gradient),
+ * gradient reduction + projection backward.  Synchronises. */
 lgs_status lgs_graph_stage_ms(lgs_graph *graph, float ms[5]);
 void lgs_graph_destroy(lgs_graph *graph);
 

@@ -11,12 +11,16 @@
 //   Y += alpha T [r, g, b, z, f0..f15]; T = T'.
 //
 // Execution.  One wave64 renders one 8x8 pixel block (one pixel per lane)
-// and walks the list of the binning tile that holds the block.  Everything a
-// list entry carries is wave-uniform, so it is fetched with scalar loads into
-// SGPRs and used directly as VALU operands: no LDS staging and no per-lane
-// gathers.  An entry whose pixel box misses the block is skipped on the
-// scalar unit; the wave leaves the list as soon as a ballot shows every lane
-// finished.  Waves pop blocks from a device work counter (persistent grid).
+// and walks the list of the binning tile that holds the block, 64 entries at
+// a time: each lane loads one entry's geometry record with a vector load and
+// tests whether the entry's ellipse can reach the block at all (cull_hit); a
+// ballot gives the mask of entries to evaluate.  The wave then visits those
+// entries in list order.  What an entry carries is wave-uniform: its fields
+// are broadcast to SGPRs (v_readlane from the lane that loaded it, or a
+// scalar load) and used directly as VALU operands, so no LDS staging and no
+// per-lane gathers are needed.  The wave leaves the list as soon as a ballot
+// shows every lane finished.  Waves pop blocks from a device work counter
+// (persistent grid).
 //
 // Backward.  Each wave restarts from the last contributor of its pixels and
 // walks the list backwards, recovering T before each entry as T / (1 - alpha)
@@ -57,6 +61,39 @@ __device__ __forceinline__ Eval eval_entry(float dx, float dy, float qa, float q
 
 __device__ __forceinline__ bool block_in_bbox(uint32_t bb, uint32_t bx, uint32_t by) {
   return bx >= (bb & 255u) && bx <= ((bb >> 8) & 255u) && by >= ((bb >> 16) & 255u) && by <= (bb >> 24);
+}
+
+// Can the entry's ellipse reach the 8x8 block (bx, by) at all?  The minimum
+// of the quadratic form over the block's pixel rectangle is 0 when the
+// rectangle holds the centre, else the smallest of the four edge minima (a
+// clamped 1-D minimiser per edge).  The entry is skipped only when that
+// minimum exceeds the per-pixel cut min(cutoff2, 2 ln(o / alpha_min)) by a
+// margin that covers the FP32 rounding of both this test and the per-pixel
+// evaluation (whose error grows with (qa + qc) |d|^2), so the test never
+// drops an entry that eval_entry would accept at some pixel of the block.
+__device__ __forceinline__ bool cull_hit(const GeomRec& g, uint32_t bx, uint32_t by, float cutoff2,
+                                         float alpha_min) {
+  const int bx0 = (int)(g.bbox & 255u), by0 = (int)((g.bbox >> 16) & 255u);
+  const float x0 = (float)(8 * ((int)bx - bx0)) - g.mx, x1 = x0 + 7.f;
+  const float y0 = (float)(8 * ((int)by - by0)) - g.my, y1 = y0 + 7.f;
+  float m = 0.f;
+  if (!(x0 <= 0.f && x1 >= 0.f && y0 <= 0.f && y1 >= 0.f)) {
+    const float ia = -g.qb2 / (2.f * g.qa), ic = -g.qb2 / (2.f * g.qc);
+    auto qf = [&](float dx, float dy) { return g.qa * dx * dx + g.qb2 * dx * dy + g.qc * dy * dy; };
+    const float e0 = qf(x0, fminf(fmaxf(ic * x0, y0), y1));
+    const float e1 = qf(x1, fminf(fmaxf(ic * x1, y0), y1));
+    const float e2 = qf(fminf(fmaxf(ia * y0, x0), x1), y0);
+    const float e3 = qf(fminf(fmaxf(ia * y1, x0), x1), y1);
+    m = fminf(fminf(e0, e1), fminf(e2, e3));
+  }
+  const float r2 = fminf(cutoff2, 1.3862943611198906f * (__builtin_amdgcn_logf(g.o) -
+                                                          __builtin_amdgcn_logf(alpha_min)));
+  const float d2 = fmaxf(x0 * x0, x1 * x1) + fmaxf(y0 * y0, y1 * y1);
+  return m <= r2 * 1.0001f + 1e-3f + 4e-6f * (g.qa + g.qc) * d2;
+}
+
+__device__ __forceinline__ float bcast(float x, uint32_t j) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), j));
 }
 
 // Appearance of a Gaussian as the 20-vector [r, g, b, (z), f0..f15]; slot 3
@@ -125,33 +162,52 @@ __global__ void __launch_bounds__(256) k_raster_fwd(
     for (int c = 0; c < 20; ++c) acc[c] = 0.f;
     int32_t last = -1, ncon = 0;
     bool done = !inside;
-    for (uint32_t k = r.x; k < r.y; ++k) {
-      const uint64_t live = __builtin_amdgcn_ballot_w64(!done);
-      if (live == 0ull) break;
-      const uint32_t rid = vals[k];
-      const GeomRec gr = geom[rid];
-      if (!block_in_bbox(gr.bbox, bx, by)) continue;
-      n_eval += (uint64_t)__popcll(live);
-      const float dx = (float)(px - 8 * (int)(gr.bbox & 255u)) - gr.mx;
-      const float dy = (float)(py - 8 * (int)((gr.bbox >> 16) & 255u)) - gr.my;
-      const Eval e = eval_entry(dx, dy, gr.qa, gr.qb2, gr.qc, gr.o, st.cutoff2, st.alpha_max, st.alpha_min);
-      bool con = !done && e.pass;
-      const float Tn = T * (1.f - e.alpha);
-      const bool term = con && (Tn < st.T_eps);
-      done = done || term;
-      con = con && !term;
-      const uint64_t cmask = __builtin_amdgcn_ballot_w64(con);
-      if (cmask == 0ull) continue;
-      n_con += (uint64_t)__popcll(cmask);
-      float y[20];
-      load_y<BF16>(app, rid & npad_mask, y);
-      y[3] = gr.z;
-      const float w = con ? e.alpha * T : 0.f;
+    bool finished = __builtin_amdgcn_ballot_w64(!done) == 0ull;
+    for (uint32_t base = r.x; base < r.y && !finished; base += 64) {
+      // lane l loads entry base + l and decides whether the wave visits it
+      const uint32_t kl = base + (uint32_t)lane;
+      uint32_t rid_l = 0;
+      GeomRec g_l{};
+      bool hit = false;
+      if (kl < r.y) {
+        rid_l = vals[kl];
+        g_l = geom[rid_l];
+        hit = block_in_bbox(g_l.bbox, bx, by) && cull_hit(g_l, bx, by, st.cutoff2, st.alpha_min);
+      }
+      uint64_t hm = __builtin_amdgcn_ballot_w64(hit);
+      while (hm) {
+        const uint32_t j = (uint32_t)__builtin_ctzll(hm);
+        hm &= hm - 1ull;
+        const uint32_t rid = __builtin_amdgcn_readlane(rid_l, j);
+        const uint32_t bb = __builtin_amdgcn_readlane(g_l.bbox, j);
+        n_eval += (uint64_t)__popcll(__builtin_amdgcn_ballot_w64(!done));
+        const float dx = (float)(px - 8 * (int)(bb & 255u)) - bcast(g_l.mx, j);
+        const float dy = (float)(py - 8 * (int)((bb >> 16) & 255u)) - bcast(g_l.my, j);
+        const Eval e = eval_entry(dx, dy, bcast(g_l.qa, j), bcast(g_l.qb2, j), bcast(g_l.qc, j),
+                                  bcast(g_l.o, j), st.cutoff2, st.alpha_max, st.alpha_min);
+        bool con = !done && e.pass;
+        const float Tn = T * (1.f - e.alpha);
+        const bool term = con && (Tn < st.T_eps);
+        done = done || term;
+        con = con && !term;
+        const uint64_t cmask = __builtin_amdgcn_ballot_w64(con);
+        if (cmask != 0ull) {
+          n_con += (uint64_t)__popcll(cmask);
+          float y[20];
+          load_y<BF16>(app, rid & npad_mask, y);
+          y[3] = bcast(g_l.z, j);
+          const float w = con ? e.alpha * T : 0.f;
 #pragma unroll
-      for (int c = 0; c < 20; ++c) acc[c] = __builtin_fmaf(w, y[c], acc[c]);
-      T = con ? Tn : T;
-      last = con ? (int32_t)k : last;
-      ncon += con ? 1 : 0;
+          for (int c = 0; c < 20; ++c) acc[c] = __builtin_fmaf(w, y[c], acc[c]);
+          T = con ? Tn : T;
+          last = con ? (int32_t)(base + j) : last;
+          ncon += con ? 1 : 0;
+        }
+        if (__builtin_amdgcn_ballot_w64(!done) == 0ull) {
+          finished = true;
+          break;
+        }
+      }
     }
     if (inside) {
       const ViewImages o = out[v];
@@ -298,54 +354,69 @@ __global__ void __launch_bounds__(256) k_raster_bwd(
     const uint32_t kbeg = ranges[tile].x;
     const float gTT = gT * Tfin;
     float Tc = Tfin, sB = 0.f;
-    for (int k = kmax; k >= (int)kbeg; --k) {
-      const uint32_t rid = vals[k];
-      const GeomRec gr = geom[rid];
-      if (!block_in_bbox(gr.bbox, bx, by)) continue;
-      n_eval += (uint64_t)__popcll(__builtin_amdgcn_ballot_w64(k <= last));
-      const int bx0 = (int)(gr.bbox & 255u), by0 = (int)((gr.bbox >> 16) & 255u);
-      const float dx = (float)(px - 8 * bx0) - gr.mx;
-      const float dy = (float)(py - 8 * by0) - gr.my;
-      const Eval e = eval_entry(dx, dy, gr.qa, gr.qb2, gr.qc, gr.o, st.cutoff2, st.alpha_max, st.alpha_min);
-      const bool con = (k <= last) && e.pass;
-      const uint64_t cmask = __builtin_amdgcn_ballot_w64(con);
-      if (cmask == 0ull) continue;
-      n_con += (uint64_t)__popcll(cmask);
-      float y[20];
-      load_y<BF16>(app, rid & npad_mask, y);
-      y[3] = gr.z;
-      float vv[32];
-      {
-        const float rinv = __builtin_amdgcn_rcpf(1.f - e.alpha);
-        const float Tp = Tc * rinv;
-        const float w = e.alpha * Tp;
-        float gy = 0.f;
-#pragma unroll
-        for (int c = 0; c < 20; ++c) gy = __builtin_fmaf(g[c], y[c], gy);
-        const float dal = Tp * gy - (sB + gTT) * rinv;
-        const float wc = con ? w : 0.f;
-        sB = con ? __builtin_fmaf(w, gy, sB) : sB;
-        Tc = con ? Tp : Tc;
-        const float dgeo = (con && !(e.araw > st.alpha_max)) ? dal : 0.f;
-        const float dm2 = dgeo * (-0.5f * e.alpha);
-        vv[0] = -dm2 * (2.f * gr.qa * dx + gr.qb2 * dy);
-        vv[1] = -dm2 * (gr.qb2 * dx + 2.f * gr.qc * dy);
-        vv[2] = dm2 * dx * dx;
-        vv[3] = dm2 * 2.f * dx * dy;
-        vv[4] = dm2 * dy * dy;
-        vv[5] = dgeo * e.G;
-#pragma unroll
-        for (int c = 0; c < 20; ++c) vv[6 + c] = wc * g[c];
-#pragma unroll
-        for (int c = 26; c < 32; ++c) vv[c] = 0.f;
+    for (int top = kmax; top >= (int)kbeg; top -= 64) {
+      // lane l loads entry top - l (the list backwards) and decides whether
+      // the wave visits it
+      const int kl = top - lane;
+      uint32_t rid_l = 0;
+      bool hit = false;
+      if (kl >= (int)kbeg) {
+        rid_l = vals[kl];
+        const GeomRec g_l = geom[rid_l];
+        hit = block_in_bbox(g_l.bbox, bx, by) && cull_hit(g_l, bx, by, st.cutoff2, st.alpha_min);
       }
-      const float s = transpose_reduce32(vv, lane);
-      const uint32_t bb = gr.bbox;
-      const uint32_t bw = ((bb >> 8) & 255u) - (bb & 255u) + 1u;
-      const uint32_t slot = slot_base[rid] + (by - (uint32_t)by0) * bw + (bx - (uint32_t)bx0);
-      const int idx = lane >> 1;
-      if ((lane & 1) == 0 && idx < kPartials) partials[(size_t)slot * kPartials + idx] = s;
-      if (lane == 0) mask[slot] = 1;
+      uint64_t hm = __builtin_amdgcn_ballot_w64(hit);
+      while (hm) {
+        const uint32_t j = (uint32_t)__builtin_ctzll(hm);
+        hm &= hm - 1ull;
+        const int k = top - (int)j;
+        const uint32_t rid = __builtin_amdgcn_readlane(rid_l, j);
+        const GeomRec gr = geom[rid];
+        n_eval += (uint64_t)__popcll(__builtin_amdgcn_ballot_w64(k <= last));
+        const int bx0 = (int)(gr.bbox & 255u), by0 = (int)((gr.bbox >> 16) & 255u);
+        const float dx = (float)(px - 8 * bx0) - gr.mx;
+        const float dy = (float)(py - 8 * by0) - gr.my;
+        const Eval e = eval_entry(dx, dy, gr.qa, gr.qb2, gr.qc, gr.o, st.cutoff2, st.alpha_max, st.alpha_min);
+        const bool con = (k <= last) && e.pass;
+        const uint64_t cmask = __builtin_amdgcn_ballot_w64(con);
+        if (cmask == 0ull) continue;
+        n_con += (uint64_t)__popcll(cmask);
+        float y[20];
+        load_y<BF16>(app, rid & npad_mask, y);
+        y[3] = gr.z;
+        float vv[32];
+        {
+          const float rinv = __builtin_amdgcn_rcpf(1.f - e.alpha);
+          const float Tp = Tc * rinv;
+          const float w = e.alpha * Tp;
+          float gy = 0.f;
+#pragma unroll
+          for (int c = 0; c < 20; ++c) gy = __builtin_fmaf(g[c], y[c], gy);
+          const float dal = Tp * gy - (sB + gTT) * rinv;
+          const float wc = con ? w : 0.f;
+          sB = con ? __builtin_fmaf(w, gy, sB) : sB;
+          Tc = con ? Tp : Tc;
+          const float dgeo = (con && !(e.araw > st.alpha_max)) ? dal : 0.f;
+          const float dm2 = dgeo * (-0.5f * e.alpha);
+          vv[0] = -dm2 * (2.f * gr.qa * dx + gr.qb2 * dy);
+          vv[1] = -dm2 * (gr.qb2 * dx + 2.f * gr.qc * dy);
+          vv[2] = dm2 * dx * dx;
+          vv[3] = dm2 * 2.f * dx * dy;
+          vv[4] = dm2 * dy * dy;
+          vv[5] = dgeo * e.G;
+#pragma unroll
+          for (int c = 0; c < 20; ++c) vv[6 + c] = wc * g[c];
+#pragma unroll
+          for (int c = 26; c < 32; ++c) vv[c] = 0.f;
+        }
+        const float s = transpose_reduce32(vv, lane);
+        const uint32_t bb = gr.bbox;
+        const uint32_t bw = ((bb >> 8) & 255u) - (bb & 255u) + 1u;
+        const uint32_t slot = slot_base[rid] + (by - (uint32_t)by0) * bw + (bx - (uint32_t)bx0);
+        const int idx = lane >> 1;
+        if ((lane & 1) == 0 && idx < kPartials) partials[(size_t)slot * kPartials + idx] = s;
+        if (lane == 0) mask[slot] = 1;
+      }
     }
   }
   if (lane == 0) {

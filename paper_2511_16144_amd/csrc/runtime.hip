@@ -437,10 +437,8 @@ void enqueue_raster_fwd(Work* W, hipStream_t s) {
 }
 
 // fused: upstream = dL1/dY from (d_out, d_tgt, d_lossw); else from d_up
-void enqueue_backward(Work* W, const lgs_gaussians* g, const lgs_grads* gr, bool fused, hipStream_t s,
-                      hipEvent_t mid_event = nullptr, hipEvent_t end_event = nullptr) {
+void enqueue_backward_raster(Work* W, bool fused, hipStream_t s) {
   const Settings ds = dev_settings(&W->st, W->plan.tile_shift);
-  const int V = (int)W->plan.views.size();
   launch_fill_u8(W->mask, 0, &W->counters->n_slots_eff, std::max<int64_t>(W->cap_slots, 1), s);
   launch_fill_u32(&W->counters->work_next_b, 0u, 1, s);
   launch_fill_u32((uint32_t*)&W->counters->bwd_evals, 0u, 4, s);   // bwd_evals, bwd_contrib
@@ -449,14 +447,22 @@ void enqueue_backward(Work* W, const lgs_gaussians* g, const lgs_grads* gr, bool
                     fused ? W->d_lossw : nullptr, W->ranges, W->pvals, W->geom, W->app, W->app_bf16,
                     (uint32_t)((1ull << W->npad_shift) - 1), W->items, W->plan.n_items, W->counters, W->st.chunk,
                     W->last_idx, W->T_state, W->slot_base, W->partials, W->mask, s);
-  if (mid_event) hipEventRecord(mid_event, s);
   w_mark(W, 6, s);
+}
+
+void enqueue_backward_reduce(Work* W, const lgs_gaussians* g, const lgs_grads* gr, hipStream_t s) {
+  const Settings ds = dev_settings(&W->st, W->plan.tile_shift);
+  const int V = (int)W->plan.views.size();
   launch_seg_reduce(W->ent, W->slot_base, W->cnt_b, W->partials, W->mask, W->counters, W->n_rid, W->grad2d, s);
   launch_project_bwd(ds, W->d_views, V, g->means, g->log_scales, g->quats, g->opacity_logits, W->n,
                      W->npad_shift, W->counters, W->cnt_t, W->cidx, W->grad2d, gr->means, gr->log_scales,
                      gr->quats, gr->opacity_logits, gr->rgb, gr->feat, gr->twist, W->ttmp, s);
-  if (end_event) hipEventRecord(end_event, s);
   w_mark(W, 7, s);
+}
+
+void enqueue_backward(Work* W, const lgs_gaussians* g, const lgs_grads* gr, bool fused, hipStream_t s) {
+  enqueue_backward_raster(W, fused, s);
+  enqueue_backward_reduce(W, g, gr, s);
 }
 
 lgs_status read_counts(Work* W, hipStream_t s, Counters* hc) {
@@ -492,8 +498,13 @@ static constexpr bool kGraphEnabled = true;
 
 struct lgs_graph {
   Work W;
-  hipGraph_t graph = nullptr;
+  hipGraph_t graph = nullptr;        // the whole step (settings.profile = 0)
   hipGraphExec_t exec = nullptr;
+  // settings.profile = 1: the five stages captured as five graphs, launched
+  // back to back with events recorded between them on the launching stream
+  // (events recorded inside a captured graph cannot be timed)
+  hipGraph_t sgraph[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  hipGraphExec_t sexec[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   hipStream_t cap_stream = nullptr;
   hipStream_t last_stream = nullptr;
   lgs_gaussians g{};
@@ -597,6 +608,7 @@ lgs_status lgs_forward(lgs_context* ctx, const lgs_settings* st, const lgs_gauss
   if ((rc = check_cams(ctx, n_views, cams)) != LGS_OK) return rc;
   if ((rc = check_images(ctx, n_views, out, true, "out")) != LGS_OK) return rc;
   HIP_TRY(ctx, hipSetDevice(ctx->device));
+  (void)hipGetLastError();   // launch checks below see only this call's errors
   lgs_fwd_state* S = new lgs_fwd_state();
   Work* W = &S->W;
   auto bail = [&](lgs_status e) {
@@ -642,6 +654,7 @@ lgs_status lgs_backward(lgs_context* ctx, const lgs_fwd_state* Sc, const lgs_gau
   if ((rc = check_images(ctx, V, grad_out, false, "grad_out")) != LGS_OK) return rc;
   if ((rc = check_grads(ctx, g, grads)) != LGS_OK) return rc;
   HIP_TRY(ctx, hipSetDevice(ctx->device));
+  (void)hipGetLastError();   // launch checks below see only this call's errors
   if ((rc = w_alloc_bwd(W)) != LGS_OK) return rc;
   std::vector<ViewImages> hup(V);
   for (int v = 0; v < V; ++v)
@@ -671,6 +684,7 @@ lgs_status lgs_backward_l1(lgs_context* ctx, const lgs_fwd_state* Sc, const lgs_
   if (!loss_w) return fail(ctx, LGS_ERR_INVALID_ARG, "loss_w is NULL");
   if ((rc = check_grads(ctx, g, grads)) != LGS_OK) return rc;
   HIP_TRY(ctx, hipSetDevice(ctx->device));
+  (void)hipGetLastError();   // launch checks below see only this call's errors
   if ((rc = w_alloc_bwd(W)) != LGS_OK) return rc;
   std::vector<ViewImages> ho(V), ht(V);
   for (int v = 0; v < V; ++v) {
@@ -709,6 +723,7 @@ lgs_status lgs_graph_create(lgs_context* ctx, const lgs_settings* st, const lgs_
   if (pair_capacity < 0) return fail(ctx, LGS_ERR_INVALID_ARG, "pair_capacity < 0");
   if (!kGraphEnabled) return fail(ctx, LGS_ERR_UNSUPPORTED, "graph mode is switched off in this build");
   HIP_TRY(ctx, hipSetDevice(ctx->device));
+  (void)hipGetLastError();   // launch checks below see only this call's errors
   // measure the workload once (eager) to size the pair and slot buffers
   lgs_fwd_state* probe = nullptr;
   if ((rc = lgs_forward(ctx, st, g, n_views, cams, out, &probe, stream)) != LGS_OK) return rc;
@@ -731,6 +746,10 @@ lgs_status lgs_graph_create(lgs_context* ctx, const lgs_settings* st, const lgs_
   auto bail = [&](lgs_status e) {
     if (G->exec) hipGraphExecDestroy(G->exec);
     if (G->graph) hipGraphDestroy(G->graph);
+    for (int i = 0; i < 5; ++i) {
+      if (G->sexec[i]) hipGraphExecDestroy(G->sexec[i]);
+      if (G->sgraph[i]) hipGraphDestroy(G->sgraph[i]);
+    }
     if (G->cap_stream) hipStreamDestroy(G->cap_stream);
     for (int i = 0; i < 6; ++i)
       if (G->ev[i]) hipEventDestroy(G->ev[i]);
@@ -757,26 +776,32 @@ lgs_status lgs_graph_create(lgs_context* ctx, const lgs_settings* st, const lgs_
   if (st->profile)
     for (int i = 0; i < 6; ++i)
       if (hipEventCreate(&G->ev[i]) != hipSuccess) return bail(fail(ctx, LGS_ERR_HIP, "event creation failed"));
-  if (hipStreamBeginCapture(G->cap_stream, hipStreamCaptureModeRelaxed) != hipSuccess)
-    return bail(fail(ctx, LGS_ERR_HIP, "hipStreamBeginCapture failed"));
   G->profile = st->profile != 0;
-  auto mark = [&](int i) {
-    if (G->profile) hipEventRecord(G->ev[i], G->cap_stream);
+  auto stage = [&](int i) {
+    switch (i) {
+      case 0: enqueue_front(W, &G->g, G->cap_stream); break;
+      case 1: enqueue_pairs(W, G->cap_stream); break;
+      case 2: enqueue_raster_fwd(W, G->cap_stream); break;
+      case 3: enqueue_backward_raster(W, true, G->cap_stream); break;
+      default: enqueue_backward_reduce(W, &G->g, &G->grads, G->cap_stream); break;
+    }
   };
-  mark(0);
-  enqueue_front(W, &G->g, G->cap_stream);
-  mark(1);
-  enqueue_pairs(W, G->cap_stream);
-  mark(2);
-  enqueue_raster_fwd(W, G->cap_stream);
-  mark(3);
-  enqueue_backward(W, &G->g, &G->grads, true, G->cap_stream, G->profile ? G->ev[4] : nullptr,
-                   G->profile ? G->ev[5] : nullptr);
-  hipError_t e = hipStreamEndCapture(G->cap_stream, &G->graph);
-  if (e != hipSuccess) return bail(fail(ctx, LGS_ERR_HIP, std::string("capture failed: ") + hipGetErrorString(e)));
-  e = hipGraphInstantiate(&G->exec, G->graph, nullptr, nullptr, 0);
-  if (e != hipSuccess)
-    return bail(fail(ctx, LGS_ERR_HIP, std::string("instantiate failed: ") + hipGetErrorString(e)));
+  auto capture = [&](int first, int last, hipGraph_t* gr, hipGraphExec_t* ex) -> lgs_status {
+    if (hipStreamBeginCapture(G->cap_stream, hipStreamCaptureModeRelaxed) != hipSuccess)
+      return fail(ctx, LGS_ERR_HIP, "hipStreamBeginCapture failed");
+    for (int i = first; i <= last; ++i) stage(i);
+    hipError_t e = hipStreamEndCapture(G->cap_stream, gr);
+    if (e != hipSuccess) return fail(ctx, LGS_ERR_HIP, std::string("capture failed: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(ex, *gr, nullptr, nullptr, 0);
+    if (e != hipSuccess) return fail(ctx, LGS_ERR_HIP, std::string("instantiate failed: ") + hipGetErrorString(e));
+    return LGS_OK;
+  };
+  if (G->profile) {
+    for (int i = 0; i < 5; ++i)
+      if ((rc = capture(i, i, &G->sgraph[i], &G->sexec[i])) != LGS_OK) return bail(rc);
+  } else if ((rc = capture(0, 4, &G->graph, &G->exec)) != LGS_OK) {
+    return bail(rc);
+  }
   W->counts = pc;
   *graph_out = G;
   return LGS_OK;
@@ -785,7 +810,15 @@ lgs_status lgs_graph_create(lgs_context* ctx, const lgs_settings* st, const lgs_
 lgs_status lgs_graph_launch(lgs_graph* G, hipStream_t stream) {
   if (!G) return LGS_ERR_INVALID_ARG;
   HIP_TRY(G->W.ctx, hipSetDevice(G->W.ctx->device));
-  HIP_TRY(G->W.ctx, hipGraphLaunch(G->exec, stream));
+  if (G->profile) {
+    for (int i = 0; i < 5; ++i) {
+      HIP_TRY(G->W.ctx, hipEventRecord(G->ev[i], stream));
+      HIP_TRY(G->W.ctx, hipGraphLaunch(G->sexec[i], stream));
+    }
+    HIP_TRY(G->W.ctx, hipEventRecord(G->ev[5], stream));
+  } else {
+    HIP_TRY(G->W.ctx, hipGraphLaunch(G->exec, stream));
+  }
   G->last_stream = stream;
   return LGS_OK;
 }
@@ -911,6 +944,7 @@ lgs_status lgs_autotune(lgs_context* ctx, const lgs_settings* st, const lgs_gaus
   *best_out = *st;
   if (cache_path && tune_cache_read(cache_path, key, best_out)) return LGS_OK;
   HIP_TRY(ctx, hipSetDevice(ctx->device));
+  (void)hipGetLastError();   // launch checks below see only this call's errors
   double best_ms = 1e30;
   const int tiles[3] = {8, 16, 32}, chunks[3] = {1, 2, 4}, orders[2] = {0, 1};
   for (int ti = 0; ti < 3; ++ti)

@@ -293,3 +293,40 @@ def test_eager_autotune_and_cache(ctx, tmp_path):
     rc = B.lib().lgs_autotune(ctx._h, C.byref(st), C.byref(g), V, cams, ti, lw, im, C.byref(gr), 0, s,
                               cache.encode(), C.byref(best2))
     assert rc == 0 and (best2.tile, best2.chunk, best2.order) == (best.tile, best.chunk, best.order)
+
+
+def test_profiled_graph_and_stage_times(ctx):
+    """settings.profile = 1: the graph launches its five stages as five
+    graphs with events between them; results equal the one-graph form bitwise
+    and every stage time is positive.  The eager stage times too, also after
+    a graph has been used and destroyed (no stale error leaks into it)."""
+    import paper_2511_16144_amd as P
+    from paper_2511_16144_amd import binding as B
+    wl = scenes.make_workload(1)
+    say("[case] C1 profiled graph vs one-graph form, stage times")
+    snaps = []
+    for prof in (0, 1):
+        run = GraphRun(ctx, wl, P.Settings(tile=16, profile=prof))
+        assert run.rc == 0, P.lib().lgs_last_error(ctx._h).decode()
+        for _ in range(2):
+            run.launch()
+        assert run.status() == 0
+        snaps.append(run.snapshot())
+        if prof:
+            ms = (C.c_float * 5)()
+            assert B.lib().lgs_graph_stage_ms(run.h, ms) == 0
+            say("  graph stage ms", list(ms))
+            assert all(x > 0 for x in ms)
+        run.destroy()
+    for a, b in zip(snaps[0][0], snaps[1][0]):
+        for k in a:
+            assert np.array_equal(a[k], b[k]), k
+    for k in snaps[0][1]:
+        assert np.array_equal(snaps[0][1][k], snaps[1][1][k]), k
+    prm = gpu_params(wl.scene)
+    outs, state = ctx.forward(prm, wl.cams, P.Settings(tile=16, profile=1))
+    ctx.backward(state, prm, upstream_tensors(scenes.random_upstream(1, wl.cams)))
+    ms = state.stage_ms()
+    state.release()
+    say("  eager stage ms", ms)
+    assert all(x > 0 for x in ms)
