@@ -229,7 +229,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="batched", choices=["batched", "plain", "precision", "differentiation"])
     ap.add_argument("--no-tune", action="store_true")
-    ap.add_argument("--mode", default="eager", choices=["eager", "graph"],
+    ap.add_argument("--mode", default="graph", choices=["eager", "graph"],
                     help="eager: lgs_forward + lgs_backward_l1 per step; graph: one captured launch per step")
     ap.add_argument("--tile", type=int, default=None, help="fix the tile size (skips the autotuner)")
     ap.add_argument("--chunk", type=int, default=None)
@@ -257,7 +257,7 @@ def main():
         a = torch.rand(n, device=dev)
         b = torch.empty_like(a)
         for _ in range(3):
-            b.copy_(a)
+            torch.mul(a, 2.0, out=b)      # one elementwise kernel: reads a, writes b
         torch.cuda.synchronize()
         log(f"[bench] copy calibration: {args.copy_calibration} MiB read + {args.copy_calibration} MiB written, x3")
         del a, b

@@ -137,9 +137,8 @@ void launch_raster_bwd(const Settings& st, const ViewDesc* views, const ViewImag
                        float* partials, uint8_t* mask, hipStream_t s);
 
 // gradient reduction and projection backward
-void launch_seg_reduce(const uint32_t* ent, const uint32_t* slot_base, const uint32_t* cnt_b,
-                       const float* partials, const uint8_t* mask, const Counters* cnt,
-                       int64_t grid_max, float* grad2d, hipStream_t s);
+void launch_seg_reduce(const uint32_t* slot_off, const float* partials, const uint8_t* mask,
+                       const Counters* cnt, int64_t n_max, float* grad2d, hipStream_t s);
 size_t twist_temp_bytes(int64_t n, int n_views);
 void launch_project_bwd(const Settings& st, const ViewDesc* views, int n_views,
                         const float* means, const float* log_scales, const float* quats,

@@ -386,13 +386,21 @@ __global__ void __launch_bounds__(256) k_project_bwd(
   for (int k = 0; k < 16; ++k) g_feat[k * n + g] = gy[4 + k];
 }
 
-__global__ void __launch_bounds__(64) k_twist_final(const double* __restrict__ part, int n_blocks,
-                                                   int n_views, float* __restrict__ twist) {
-  const int idx = blockIdx.x * 64 + threadIdx.x;
-  if (idx >= n_views * 6) return;
+// twist[v][k] = sum over the projection-backward blocks of their partial sums;
+// one workgroup per (view, component), fixed summation order.
+__global__ void __launch_bounds__(256) k_twist_final(const double* __restrict__ part, int n_blocks,
+                                                    int n_views, float* __restrict__ twist) {
+  __shared__ double red[256];
+  const int idx = blockIdx.x;   // v * 6 + k
   double s = 0.0;
-  for (int b = 0; b < n_blocks; ++b) s += part[(size_t)b * n_views * 6 + idx];
-  twist[idx] = (float)s;
+  for (int b = threadIdx.x; b < n_blocks; b += 256) s += part[(size_t)b * n_views * 6 + idx];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) twist[idx] = (float)red[0];
 }
 
 }  // namespace
@@ -428,8 +436,8 @@ void launch_project_bwd(const Settings& st, const ViewDesc* views, int n_views, 
                        log_scales, quats, logits, n, npad_shift, cnt, cnt_t, cidx, grad2d, g_means, g_ls,
                        g_q, g_logit, g_rgb, g_feat, (double*)temp);
   if (twist)   // with no Gaussian block the sum is empty and the kernel writes zeros
-    hipLaunchKernelGGL(k_twist_final, dim3((n_views * 6 + 63) / 64), dim3(64), 0, s,
-                       (const double*)temp, blocks, n_views, twist);
+    hipLaunchKernelGGL(k_twist_final, dim3(n_views * 6), dim3(256), 0, s, (const double*)temp, blocks,
+                       n_views, twist);
 }
 
 }  // namespace lgs

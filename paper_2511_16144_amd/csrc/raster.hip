@@ -96,6 +96,33 @@ __device__ __forceinline__ float bcast(float x, uint32_t j) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), j));
 }
 
+// Appearance record words of Gaussian g (10 words in BF16 storage, 20 in
+// FP32) and their unpacking into the 20-vector [r, g, b, (z), f0..f15]; slot
+// 3 is filled by the caller with the view's depth.
+template <bool BF16>
+__device__ __forceinline__ void load_app_words(const void* __restrict__ app, uint32_t g, uint32_t w[20]) {
+  const uint32_t* a = (const uint32_t*)app + (size_t)g * (BF16 ? 10 : 20);
+#pragma unroll
+  for (int k = 0; k < (BF16 ? 10 : 20); ++k) w[k] = a[k];
+}
+
+template <bool BF16>
+__device__ __forceinline__ void y_from_words(const uint32_t u[20], float y[20]) {
+  if (BF16) {
+    y[0] = __uint_as_float(u[0] << 16);
+    y[1] = __uint_as_float(u[0] & 0xffff0000u);
+    y[2] = __uint_as_float(u[1] << 16);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      y[4 + 2 * k] = __uint_as_float(u[2 + k] << 16);
+      y[5 + 2 * k] = __uint_as_float(u[2 + k] & 0xffff0000u);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 20; ++k) y[k] = __uint_as_float(u[k]);
+  }
+}
+
 // Appearance of a Gaussian as the 20-vector [r, g, b, (z), f0..f15]; slot 3
 // is filled by the caller with the view's depth.
 template <bool BF16>
@@ -175,10 +202,13 @@ __global__ void __launch_bounds__(256) k_raster_fwd(
         hit = block_in_bbox(g_l.bbox, bx, by) && cull_hit(g_l, bx, by, st.cutoff2, st.alpha_min);
       }
       uint64_t hm = __builtin_amdgcn_ballot_w64(hit);
+      // the appearance of the entry to visit next is requested at the end of
+      // the current one, so its latency overlaps that entry's evaluation
+      uint32_t j = hm ? (uint32_t)__builtin_ctzll(hm) : 0u;
+      uint32_t aw[20];
+      if (hm) load_app_words<BF16>(app, __builtin_amdgcn_readlane(rid_l, j) & npad_mask, aw);
       while (hm) {
-        const uint32_t j = (uint32_t)__builtin_ctzll(hm);
         hm &= hm - 1ull;
-        const uint32_t rid = __builtin_amdgcn_readlane(rid_l, j);
         const uint32_t bb = __builtin_amdgcn_readlane(g_l.bbox, j);
         n_eval += (uint64_t)__popcll(__builtin_amdgcn_ballot_w64(!done));
         const float dx = (float)(px - 8 * (int)(bb & 255u)) - bcast(g_l.mx, j);
@@ -194,7 +224,7 @@ __global__ void __launch_bounds__(256) k_raster_fwd(
         if (cmask != 0ull) {
           n_con += (uint64_t)__popcll(cmask);
           float y[20];
-          load_y<BF16>(app, rid & npad_mask, y);
+          y_from_words<BF16>(aw, y);
           y[3] = bcast(g_l.z, j);
           const float w = con ? e.alpha * T : 0.f;
 #pragma unroll
@@ -206,6 +236,10 @@ __global__ void __launch_bounds__(256) k_raster_fwd(
         if (__builtin_amdgcn_ballot_w64(!done) == 0ull) {
           finished = true;
           break;
+        }
+        if (hm) {
+          j = (uint32_t)__builtin_ctzll(hm);
+          load_app_words<BF16>(app, __builtin_amdgcn_readlane(rid_l, j) & npad_mask, aw);
         }
       }
     }
@@ -425,32 +459,39 @@ __global__ void __launch_bounds__(256) k_raster_bwd(
   }
 }
 
-// One wave per visible (view, Gaussian): sum its valid slots, fixed order.
-__global__ void __launch_bounds__(256) k_seg_reduce(const uint32_t* __restrict__ ent,
-                                                    const uint32_t* __restrict__ slot_base,
-                                                    const uint32_t* __restrict__ cnt_b,
+// Per-Gaussian sum of the backward's partials.  Visible (view, Gaussian) c
+// owns the slot range [slot_off[c], slot_off[c + 1]) (the last one ends at
+// n_slots); a slot holds a partial only where the backward set its mask byte.
+// Waves loop over c (grid-stride, persistent grid); lane l sums slots
+// base + l, base + l + 64, ... in order, then the wave sums its lanes with the
+// butterfly transpose-reduction: a fixed order, so results are deterministic.
+__global__ void __launch_bounds__(256) k_seg_reduce(const uint32_t* __restrict__ slot_off,
                                                     const float* __restrict__ partials,
                                                     const uint8_t* __restrict__ mask,
                                                     const Counters* __restrict__ cnt,
                                                     float* __restrict__ grad2d) {
   const int lane = threadIdx.x & 63;
-  const int64_t c = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (cnt->overflow || c >= (int64_t)cnt->n_visible) return;
-  const uint32_t rid = ent[c];
-  const uint32_t base = slot_base[rid], nb = cnt_b[rid];
-  float vv[32];
+  if (cnt->overflow) return;
+  const uint32_t nv = cnt->n_visible, ns = cnt->n_slots;
+  const uint32_t n_waves = (gridDim.x * blockDim.x) >> 6;
+  const uint32_t w0 = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  for (uint32_t c = w0; c < nv; c += n_waves) {
+    const uint32_t base = slot_off[c];
+    const uint32_t end = c + 1 < nv ? slot_off[c + 1] : ns;
+    float vv[32];
 #pragma unroll
-  for (int i = 0; i < 32; ++i) vv[i] = 0.f;
-  for (uint32_t s = lane; s < nb; s += 64) {
-    if (mask[base + s]) {
-      const float* pp = partials + (size_t)(base + s) * kPartials;
+    for (int i = 0; i < 32; ++i) vv[i] = 0.f;
+    for (uint32_t sl = base + (uint32_t)lane; sl < end; sl += 64) {
+      if (mask[sl]) {
+        const float* pp = partials + (size_t)sl * kPartials;
 #pragma unroll
-      for (int i = 0; i < kPartials; ++i) vv[i] += pp[i];
+        for (int i = 0; i < kPartials; ++i) vv[i] += pp[i];
+      }
     }
+    const float tot = transpose_reduce32(vv, lane);
+    const int idx = lane >> 1;
+    if ((lane & 1) == 0 && idx < kPartials) grad2d[(size_t)c * kPartials + idx] = tot;
   }
-  const float tot = transpose_reduce32(vv, lane);
-  const int idx = lane >> 1;
-  if ((lane & 1) == 0 && idx < kPartials) grad2d[c * kPartials + idx] = tot;
 }
 
 }  // namespace
@@ -530,12 +571,17 @@ void launch_raster_bwd(const Settings& st, const ViewDesc* views, const ViewImag
   }
 }
 
-void launch_seg_reduce(const uint32_t* ent, const uint32_t* slot_base, const uint32_t* cnt_b,
-                       const float* partials, const uint8_t* mask, const Counters* cnt, int64_t grid_max,
-                       float* grad2d, hipStream_t s) {
-  if (grid_max <= 0) return;
-  hipLaunchKernelGGL(k_seg_reduce, dim3((unsigned)((grid_max + 3) / 4)), dim3(256), 0, s, ent, slot_base,
-                     cnt_b, partials, mask, cnt, grad2d);
+void launch_seg_reduce(const uint32_t* slot_off, const float* partials, const uint8_t* mask,
+                       const Counters* cnt, int64_t n_max, float* grad2d, hipStream_t s) {
+  if (n_max <= 0) return;
+  int dev = 0, cus = 256, occ = 1;
+  hipGetDevice(&dev);
+  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_seg_reduce, 256, 0);
+  int64_t grid = (int64_t)cus * (occ > 0 ? occ : 1);
+  const int64_t need = (n_max + 3) / 4;
+  if (grid > need) grid = need;
+  hipLaunchKernelGGL(k_seg_reduce, dim3((unsigned)grid), dim3(256), 0, s, slot_off, partials, mask, cnt, grad2d);
 }
 
 }  // namespace lgs

@@ -453,7 +453,7 @@ void enqueue_backward_raster(Work* W, bool fused, hipStream_t s) {
 void enqueue_backward_reduce(Work* W, const lgs_gaussians* g, const lgs_grads* gr, hipStream_t s) {
   const Settings ds = dev_settings(&W->st, W->plan.tile_shift);
   const int V = (int)W->plan.views.size();
-  launch_seg_reduce(W->ent, W->slot_base, W->cnt_b, W->partials, W->mask, W->counters, W->n_rid, W->grad2d, s);
+  launch_seg_reduce(W->slot_off, W->partials, W->mask, W->counters, W->n_rid, W->grad2d, s);
   launch_project_bwd(ds, W->d_views, V, g->means, g->log_scales, g->quats, g->opacity_logits, W->n,
                      W->npad_shift, W->counters, W->cnt_t, W->cidx, W->grad2d, gr->means, gr->log_scales,
                      gr->quats, gr->opacity_logits, gr->rgb, gr->feat, gr->twist, W->ttmp, s);
