@@ -45,6 +45,28 @@ FLOPS_FWD_CONTRIB = 44
 FLOPS_BWD_CONTRIB = 111
 
 
+def measured_traffic(kernel, settings, workload):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (two rocprofv3 passes, FETCH_SIZE then WRITE_SIZE, scaled against a kernel
+    of known traffic), or None when the kernel sources changed since, or the
+    settings / workload differ from the profiled ones."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic_compositing_batched_c4.md")
+    if not os.path.exists(path) or workload != "batched" or \
+            (settings.get("tile"), settings.get("chunk"), settings.get("order")) != (32, 2, 1):
+        return None
+    src = os.path.join(ROOT, "paper_2511_16144_amd", "csrc")
+    h = hashlib.sha256(open(os.path.join(src, "raster.hip"), "rb").read() +
+                       open(os.path.join(src, "lgs_internal.h"), "rb").read()).hexdigest()
+    for line in open(path):
+        f = line.split()
+        if len(f) == 4 and f[0] == "traffic" and f[1] == kernel:
+            kv = dict(x.split("=", 1) for x in f[2:])
+            if kv.get("source_sha256") == h:
+                return float(kv["bytes_per_launch"])
+    return None
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -195,14 +217,14 @@ def time_workload_graph(ctx, wl, steps, warmup, dev, tune, settings):
 def cpu_baseline(wl, budget_s=12.0):
     """The FP64 oracle (forward + autodiff backward) on a bounded sample of
     the same workload: 64x64 crops of the first view, until about `budget_s`
-    seconds of work are done (at most 16 crops), with every host core."""
+    seconds of work are done (at most 64 crops), with every host core."""
     import numpy as np
     import torch
     import scenes
     from oracle import raster_fp64 as R
     torch.set_num_threads(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
     cam = wl.cams[0]
-    wins = scenes.crop_windows(11, cam, k=16, size=64)
+    wins = scenes.crop_windows(11, cam, k=64, size=64)
     done_px = 0
     t0 = time.perf_counter()
     n_crops = 0
@@ -293,7 +315,8 @@ def main():
     kms = st[3] if st else None
     achieved = fl / (kms / 1e3) / 1e12 if kms else None
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-            "frac": (achieved / PEAK_FP32_TFLOPS) if achieved else None, "traffic": None,
+            "frac": (achieved / PEAK_FP32_TFLOPS) if achieved else None,
+            "traffic": measured_traffic("k_raster_bwd", r["settings"], args.workload),
             "kernel": "k_raster_bwd", "kernel_ms": kms,
             "units": {"bwd_evals": c["bwd_evals"], "bwd_contrib": c["bwd_contrib"]},
             "flops_per_unit": {"eval": FLOPS_EVAL, "contrib": FLOPS_BWD_CONTRIB}}
