@@ -247,13 +247,13 @@ __global__ void __launch_bounds__(256) k_item_keys(const ViewDesc* __restrict__ 
   const uint32_t t = (uint32_t)V.tile_off + (by >> tile_shift) * (uint32_t)V.tiles_x + (bx >> tile_shift);
   const uint2 r = ranges[t];
   const uint32_t len = r.y - r.x;
-  keys[i] = 65535u - (len < 65535u ? len : 65535u);   // ascending key = descending length
+  // grouped by queue, then descending length (ascending key; lengths clamp at 8191)
+  keys[i] = (tile_queue(t) << 13) | (8191u - (len < 8191u ? len : 8191u));
   vals[i] = it;
 }
 
-__global__ void k_reset_counters(Counters* cnt) {
-  static_assert(sizeof(Counters) / 4 <= 64, "one wave clears the counters");
-  if (threadIdx.x < sizeof(Counters) / 4) ((uint32_t*)cnt)[threadIdx.x] = 0u;
+__global__ void __launch_bounds__(256) k_reset_counters(Counters* cnt) {
+  for (uint32_t i = threadIdx.x; i < sizeof(Counters) / 4; i += 256) ((uint32_t*)cnt)[i] = 0u;
 }
 
 __global__ void __launch_bounds__(256) k_slot_bases(const uint32_t* __restrict__ ent,
@@ -335,7 +335,7 @@ uint32_t* launch_order_items(const ViewDesc* views, const uint2* ranges, int til
 }
 
 void launch_reset_counters(Counters* cnt, hipStream_t s) {
-  hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, cnt);
+  hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(256), 0, s, cnt);
 }
 
 void launch_slot_bases(const uint32_t* ent, const uint32_t* slot_off, const Counters* cnt,

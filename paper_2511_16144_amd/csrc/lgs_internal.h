@@ -52,19 +52,37 @@ struct Settings {
 
 // Device-resident counters of one forward (written by kernels, read by
 // kernels; the host reads n_pairs in eager mode).
-struct Counters {
+// Work items of the compositing kernels are split into kQueues queues, one
+// per XCD (the GPU dispatches workgroup i to XCD i mod 8): all blocks of a
+// binning tile go to the same queue, so the tile's list is fetched into one
+// XCD's L2 and reused there by the blocks that walk it.
+#ifndef LGS_XCD_QUEUES
+#define LGS_XCD_QUEUES 1
+#endif
+constexpr int kQueues = 8;
+
+constexpr int kLineWords = 32;   // one 128-byte line per queue counter
+
+struct __attribute__((aligned(128))) Counters {
   uint32_t n_visible;   // M
   uint32_t n_pairs;     // P
   uint32_t n_slots;     // S
   uint32_t overflow;    // set when P exceeds the pair capacity
-  uint32_t work_next;   // persistent-kernel work counter (forward)
-  uint32_t work_next_b; // persistent-kernel work counter (backward)
   uint32_t n_pairs_eff; // n_pairs, or 0 after an overflow
   uint32_t n_slots_eff; // n_slots, or 0 after an overflow
-  // work actually done by the compositing kernels (one atomic per work item):
+  uint32_t pad0, pad1;
+  // work actually done by the compositing kernels (one atomic per wave):
   // (pixel, entry) evaluations and contributions, forward and backward
   unsigned long long fwd_evals, fwd_contrib, bwd_evals, bwd_contrib;
+  uint32_t pad2[16];
+  // persistent-kernel work counters, queue q at word q * kLineWords, each on
+  // its own line so that the queues' atomics do not serialise on one address
+  uint32_t work_q[kQueues * kLineWords];    // forward
+  uint32_t work_qb[kQueues * kLineWords];   // backward
 };
+
+// Queue of the items of binning tile t (global tile index).
+__host__ __device__ inline uint32_t tile_queue(uint32_t t) { return LGS_XCD_QUEUES ? (t % kQueues) : 0u; }
 
 // ---------------------------------------------------------------------------
 // launchers (each defined next to its kernels)
@@ -126,15 +144,15 @@ uint32_t* launch_order_items(const ViewDesc* views, const uint2* ranges, int til
 void launch_raster_fwd(const Settings& st, const ViewDesc* views, const ViewImages* out,
                        const uint2* ranges, const uint32_t* vals, const GeomRec* geom,
                        const void* app, int app_bf16, uint32_t npad_mask,
-                       const uint32_t* items, int64_t n_items, Counters* cnt, int waves_per_group,
-                       int32_t* last_idx, float* T_state, hipStream_t s);
+                       const uint32_t* items, const uint32_t* qoff, int64_t n_items, Counters* cnt,
+                       int waves_per_group, int32_t* last_idx, float* T_state, hipStream_t s);
 void launch_raster_bwd(const Settings& st, const ViewDesc* views, const ViewImages* upstream,
                        const ViewImages* fwd_out, const ViewImages* targets, const float* loss_w,
                        const uint2* ranges, const uint32_t* vals, const GeomRec* geom,
                        const void* app, int app_bf16, uint32_t npad_mask,
-                       const uint32_t* items, int64_t n_items, Counters* cnt, int waves_per_group,
-                       const int32_t* last_idx, const float* T_state, const uint32_t* slot_base,
-                       float* partials, uint8_t* mask, hipStream_t s);
+                       const uint32_t* items, const uint32_t* qoff, int64_t n_items, Counters* cnt,
+                       int waves_per_group, const int32_t* last_idx, const float* T_state,
+                       const uint32_t* slot_base, float* partials, uint8_t* mask, hipStream_t s);
 
 // gradient reduction and projection backward
 void launch_seg_reduce(const uint32_t* slot_off, const float* partials, const uint8_t* mask,

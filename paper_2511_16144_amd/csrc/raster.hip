@@ -161,18 +161,28 @@ __device__ __forceinline__ uint32_t pop_item(uint32_t* counter) {
   return __builtin_amdgcn_readfirstlane(old);
 }
 
+// Next work item of the calling wave from the queue of its XCD (workgroup
+// index mod kQueues), or n_items once that queue is empty.  Wave-uniform.
+__device__ __forceinline__ uint32_t next_item(uint32_t* ctr, const uint32_t* __restrict__ qoff, uint32_t q,
+                                              uint32_t n_items) {
+  const uint32_t k = pop_item(&ctr[q * kLineWords]);
+  const uint32_t b = qoff[q], e = qoff[q + 1];
+  return k < e - b ? b + k : n_items;
+}
+
 template <bool BF16>
 __global__ void __launch_bounds__(256) k_raster_fwd(
     Settings st, const ViewDesc* __restrict__ views, const ViewImages* __restrict__ out,
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ vals,
     const GeomRec* __restrict__ geom, const void* __restrict__ app, uint32_t npad_mask,
-    const uint32_t* __restrict__ items, uint32_t n_items, Counters* __restrict__ cnt,
-    int32_t* __restrict__ last_idx, float* __restrict__ T_state) {
+    const uint32_t* __restrict__ items, const uint32_t* __restrict__ qoff, uint32_t n_items,
+    Counters* __restrict__ cnt, int32_t* __restrict__ last_idx, float* __restrict__ T_state) {
   const int lane = threadIdx.x & 63;
   if (cnt->overflow) return;
   uint64_t n_eval = 0, n_con = 0;   // this wave's work, added to the counters once at the end
+  const uint32_t q = blockIdx.x % (uint32_t)kQueues;
   for (;;) {
-    const uint32_t it = pop_item(&cnt->work_next);
+    const uint32_t it = next_item(cnt->work_q, qoff, q, n_items);
     if (it >= n_items) break;
     const uint32_t item = items[it];
     const uint32_t bx = item & 255u, by = (item >> 8) & 255u, v = item >> 16;
@@ -327,14 +337,16 @@ __global__ void __launch_bounds__(256) k_raster_bwd(
     const float* __restrict__ loss_w, const uint2* __restrict__ ranges,
     const uint32_t* __restrict__ vals, const GeomRec* __restrict__ geom,
     const void* __restrict__ app, uint32_t npad_mask, const uint32_t* __restrict__ items,
-    uint32_t n_items, Counters* __restrict__ cnt, const int32_t* __restrict__ last_idx,
+    const uint32_t* __restrict__ qoff, uint32_t n_items, Counters* __restrict__ cnt,
+    const int32_t* __restrict__ last_idx,
     const float* __restrict__ T_state, const uint32_t* __restrict__ slot_base,
     float* __restrict__ partials, uint8_t* __restrict__ mask) {
   const int lane = threadIdx.x & 63;
   if (cnt->overflow) return;
   uint64_t n_eval = 0, n_con = 0;   // this wave's work, added to the counters once at the end
+  const uint32_t q = blockIdx.x % (uint32_t)kQueues;
   for (;;) {
-    const uint32_t it = pop_item(&cnt->work_next_b);
+    const uint32_t it = next_item(cnt->work_qb, qoff, q, n_items);
     if (it >= n_items) break;
     const uint32_t item = items[it];
     const uint32_t bx = item & 255u, by = (item >> 8) & 255u, v = item >> 16;
@@ -498,8 +510,8 @@ __global__ void __launch_bounds__(256) k_seg_reduce(const uint32_t* __restrict__
 
 void launch_raster_fwd(const Settings& st, const ViewDesc* views, const ViewImages* out, const uint2* ranges,
                        const uint32_t* vals, const GeomRec* geom, const void* app, int app_bf16,
-                       uint32_t npad_mask, const uint32_t* items, int64_t n_items, Counters* cnt,
-                       int waves_per_group, int32_t* last_idx, float* T_state, hipStream_t s) {
+                       uint32_t npad_mask, const uint32_t* items, const uint32_t* qoff, int64_t n_items,
+                       Counters* cnt, int waves_per_group, int32_t* last_idx, float* T_state, hipStream_t s) {
   if (n_items <= 0) return;
   const int threads = 64 * waves_per_group;
   int dev = 0, cus = 256;
@@ -513,20 +525,23 @@ void launch_raster_fwd(const Settings& st, const ViewDesc* views, const ViewImag
   int64_t grid = (int64_t)cus * (occ > 0 ? occ : 1);
   const int64_t need = (n_items + waves_per_group - 1) / waves_per_group;
   if (grid > need) grid = need;
+  if (grid < kQueues) grid = kQueues;   // every queue needs a workgroup (index mod kQueues) to drain it
   if (app_bf16)
     hipLaunchKernelGGL(k_raster_fwd<true>, dim3((unsigned)grid), dim3(threads), 0, s, st, views, out,
-                       ranges, vals, geom, app, npad_mask, items, (uint32_t)n_items, cnt, last_idx, T_state);
+                       ranges, vals, geom, app, npad_mask, items, qoff, (uint32_t)n_items, cnt, last_idx,
+                       T_state);
   else
     hipLaunchKernelGGL(k_raster_fwd<false>, dim3((unsigned)grid), dim3(threads), 0, s, st, views, out,
-                       ranges, vals, geom, app, npad_mask, items, (uint32_t)n_items, cnt, last_idx, T_state);
+                       ranges, vals, geom, app, npad_mask, items, qoff, (uint32_t)n_items, cnt, last_idx,
+                       T_state);
 }
 
 template <bool BF16, bool FUSED>
 static void launch_bwd_t(const Settings& st, const ViewDesc* views, const ViewImages* upstream,
                          const ViewImages* fwd_out, const ViewImages* targets, const float* loss_w,
                          const uint2* ranges, const uint32_t* vals, const GeomRec* geom, const void* app,
-                         uint32_t npad_mask, const uint32_t* items, int64_t n_items, Counters* cnt,
-                         int waves_per_group, const int32_t* last_idx, const float* T_state,
+                         uint32_t npad_mask, const uint32_t* items, const uint32_t* qoff, int64_t n_items,
+                         Counters* cnt, int waves_per_group, const int32_t* last_idx, const float* T_state,
                          const uint32_t* slot_base, float* partials, uint8_t* mask, hipStream_t s) {
   const int threads = 64 * waves_per_group;
   int dev = 0, cus = 256;
@@ -537,36 +552,38 @@ static void launch_bwd_t(const Settings& st, const ViewDesc* views, const ViewIm
   int64_t grid = (int64_t)cus * (occ > 0 ? occ : 1);
   const int64_t need = (n_items + waves_per_group - 1) / waves_per_group;
   if (grid > need) grid = need;
+  if (grid < kQueues) grid = kQueues;   // every queue needs a workgroup (index mod kQueues) to drain it
   hipLaunchKernelGGL((k_raster_bwd<BF16, FUSED>), dim3((unsigned)grid), dim3(threads), 0, s, st, views,
-                     upstream, fwd_out, targets, loss_w, ranges, vals, geom, app, npad_mask, items,
+                     upstream, fwd_out, targets, loss_w, ranges, vals, geom, app, npad_mask, items, qoff,
                      (uint32_t)n_items, cnt, last_idx, T_state, slot_base, partials, mask);
 }
 
 void launch_raster_bwd(const Settings& st, const ViewDesc* views, const ViewImages* upstream,
                        const ViewImages* fwd_out, const ViewImages* targets, const float* loss_w,
                        const uint2* ranges, const uint32_t* vals, const GeomRec* geom, const void* app,
-                       int app_bf16, uint32_t npad_mask, const uint32_t* items, int64_t n_items,
-                       Counters* cnt, int waves_per_group, const int32_t* last_idx, const float* T_state,
-                       const uint32_t* slot_base, float* partials, uint8_t* mask, hipStream_t s) {
+                       int app_bf16, uint32_t npad_mask, const uint32_t* items, const uint32_t* qoff,
+                       int64_t n_items, Counters* cnt, int waves_per_group, const int32_t* last_idx,
+                       const float* T_state, const uint32_t* slot_base, float* partials, uint8_t* mask,
+                       hipStream_t s) {
   if (n_items <= 0) return;
   const bool fused = targets != nullptr;
   if (app_bf16) {
     if (fused)
       launch_bwd_t<true, true>(st, views, upstream, fwd_out, targets, loss_w, ranges, vals, geom, app,
-                               npad_mask, items, n_items, cnt, waves_per_group, last_idx, T_state,
+                               npad_mask, items, qoff, n_items, cnt, waves_per_group, last_idx, T_state,
                                slot_base, partials, mask, s);
     else
       launch_bwd_t<true, false>(st, views, upstream, fwd_out, targets, loss_w, ranges, vals, geom, app,
-                                npad_mask, items, n_items, cnt, waves_per_group, last_idx, T_state,
+                                npad_mask, items, qoff, n_items, cnt, waves_per_group, last_idx, T_state,
                                 slot_base, partials, mask, s);
   } else {
     if (fused)
       launch_bwd_t<false, true>(st, views, upstream, fwd_out, targets, loss_w, ranges, vals, geom, app,
-                                npad_mask, items, n_items, cnt, waves_per_group, last_idx, T_state,
+                                npad_mask, items, qoff, n_items, cnt, waves_per_group, last_idx, T_state,
                                 slot_base, partials, mask, s);
     else
       launch_bwd_t<false, false>(st, views, upstream, fwd_out, targets, loss_w, ranges, vals, geom, app,
-                                 npad_mask, items, n_items, cnt, waves_per_group, last_idx, T_state,
+                                 npad_mask, items, qoff, n_items, cnt, waves_per_group, last_idx, T_state,
                                  slot_base, partials, mask, s);
   }
 }

@@ -12,6 +12,7 @@
 #include <chrono>
 #include <map>
 #include <string>
+#include <cstddef>
 #include <vector>
 
 using namespace lgs;
@@ -183,24 +184,37 @@ Plan make_plan(const lgs_settings* st, int32_t n_views, const lgs_camera* cams) 
   return P;
 }
 
-// Work items (8x8 blocks) tile by tile, raster order inside a tile.
+// Work items (8x8 blocks) grouped by queue (tile_queue of the block's tile),
+// tile by tile inside a queue, raster order inside a tile; the kQueues + 1
+// queue offsets follow the items.
 std::vector<uint32_t> make_items(const Plan& P, int tile) {
-  std::vector<uint32_t> items;
-  items.reserve(P.n_items);
+  std::vector<std::vector<uint32_t>> qs(kQueues);
   const int bpt = tile / kBlock;
   for (size_t v = 0; v < P.views.size(); ++v) {
     const ViewDesc& d = P.views[v];
     for (int ty = 0; ty < d.tiles_y; ++ty)
-      for (int tx = 0; tx < d.tiles_x; ++tx)
+      for (int tx = 0; tx < d.tiles_x; ++tx) {
+        auto& q = qs[tile_queue((uint32_t)(d.tile_off + ty * d.tiles_x + tx))];
         for (int j = 0; j < bpt; ++j)
           for (int i = 0; i < bpt; ++i) {
             const int bx = tx * bpt + i, by = ty * bpt + j;
             if (bx < d.blocks_x && by < d.blocks_y)
-              items.push_back((uint32_t)bx | ((uint32_t)by << 8) | ((uint32_t)v << 16));
+              q.push_back((uint32_t)bx | ((uint32_t)by << 8) | ((uint32_t)v << 16));
           }
+      }
   }
+  std::vector<uint32_t> items;
+  items.reserve(P.n_items + kQueues + 1);
+  std::vector<uint32_t> off(kQueues + 1, 0u);
+  for (int q = 0; q < kQueues; ++q) {
+    off[q] = (uint32_t)items.size();
+    items.insert(items.end(), qs[q].begin(), qs[q].end());
+  }
+  off[kQueues] = (uint32_t)items.size();
+  items.insert(items.end(), off.begin(), off.end());
   return items;
 }
+
 
 Settings dev_settings(const lgs_settings* st, int tile_shift) {
   Settings s;
@@ -432,7 +446,8 @@ void enqueue_pairs(Work* W, hipStream_t s) {
 void enqueue_raster_fwd(Work* W, hipStream_t s) {
   const Settings ds = dev_settings(&W->st, W->plan.tile_shift);
   launch_raster_fwd(ds, W->d_views, W->d_out, W->ranges, W->pvals, W->geom, W->app, W->app_bf16,
-                    (uint32_t)((1ull << W->npad_shift) - 1), W->items, W->plan.n_items, W->counters, W->st.chunk,
+                    (uint32_t)((1ull << W->npad_shift) - 1), W->items, W->items_static + W->plan.n_items,
+                    W->plan.n_items, W->counters, W->st.chunk,
                     W->last_idx, W->T_state, s);
 }
 
@@ -440,12 +455,13 @@ void enqueue_raster_fwd(Work* W, hipStream_t s) {
 void enqueue_backward_raster(Work* W, bool fused, hipStream_t s) {
   const Settings ds = dev_settings(&W->st, W->plan.tile_shift);
   launch_fill_u8(W->mask, 0, &W->counters->n_slots_eff, std::max<int64_t>(W->cap_slots, 1), s);
-  launch_fill_u32(&W->counters->work_next_b, 0u, 1, s);
+  launch_fill_u32(W->counters->work_qb, 0u, kQueues * kLineWords, s);
   launch_fill_u32((uint32_t*)&W->counters->bwd_evals, 0u, 4, s);   // bwd_evals, bwd_contrib
   w_mark(W, 5, s);
   launch_raster_bwd(ds, W->d_views, W->d_up, fused ? W->d_out : nullptr, fused ? W->d_tgt : nullptr,
                     fused ? W->d_lossw : nullptr, W->ranges, W->pvals, W->geom, W->app, W->app_bf16,
-                    (uint32_t)((1ull << W->npad_shift) - 1), W->items, W->plan.n_items, W->counters, W->st.chunk,
+                    (uint32_t)((1ull << W->npad_shift) - 1), W->items, W->items_static + W->plan.n_items,
+                    W->plan.n_items, W->counters, W->st.chunk,
                     W->last_idx, W->T_state, W->slot_base, W->partials, W->mask, s);
   w_mark(W, 6, s);
 }
@@ -466,7 +482,7 @@ void enqueue_backward(Work* W, const lgs_gaussians* g, const lgs_grads* gr, bool
 }
 
 lgs_status read_counts(Work* W, hipStream_t s, Counters* hc) {
-  HIP_TRY(W->ctx, hipMemcpyAsync(hc, W->counters, sizeof(Counters), hipMemcpyDeviceToHost, s));
+  HIP_TRY(W->ctx, hipMemcpyAsync(hc, W->counters, offsetof(Counters, pad2), hipMemcpyDeviceToHost, s));
   HIP_TRY(W->ctx, hipStreamSynchronize(s));
   W->counts.n_visible = hc->n_visible;
   W->counts.n_pairs = hc->n_pairs;
