@@ -55,8 +55,12 @@ def measured_traffic(kernel, settings, workload):
     if not os.path.exists(path) or workload != "batched" or (settings.get("tile"), settings.get("order")) != (32, 1):
         return None
     src = os.path.join(ROOT, "paper_2511_16144_amd", "csrc")
-    h = hashlib.sha256(open(os.path.join(src, "raster.hip"), "rb").read() +
-                       open(os.path.join(src, "lgs_internal.h"), "rb").read()).hexdigest()
+    if kernel == "step":
+        h = hashlib.sha256(b"".join(open(os.path.join(src, f), "rb").read()
+                                    for f in sorted(os.listdir(src)))).hexdigest()
+    else:
+        h = hashlib.sha256(open(os.path.join(src, "raster.hip"), "rb").read() +
+                           open(os.path.join(src, "lgs_internal.h"), "rb").read()).hexdigest()
     for line in open(path):
         f = line.split()
         if len(f) == 4 and f[0] == "traffic" and f[1] == kernel:
@@ -247,8 +251,8 @@ def cpu_baseline(wl, budget_s=15.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="batched", choices=["batched", "plain", "precision", "differentiation"])
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--mode", default="graph", choices=["eager", "graph"],
@@ -323,6 +327,14 @@ def main():
     fwd_fl = FLOPS_EVAL * c["fwd_evals"] + FLOPS_FWD_CONTRIB * c["fwd_contrib"]
     fwd_tf = fwd_fl / (st[2] / 1e3) / 1e12 if st else None
     eager_ms = re["ms"] if args.mode == "graph" else None
+    # whole-step HBM traffic (both counter passes, every kernel, eager form) over the step time
+    step_bytes = measured_traffic("step", r["settings"], args.workload)
+    hbm = None
+    if step_bytes is not None:
+        gbs = step_bytes / (r["ms"] / 1e3) / 1e9
+        hbm = {"bytes_per_step": step_bytes, "GB/s": round(gbs, 1), "peak": PEAK_HBM_GBS,
+               "frac": round(gbs / PEAK_HBM_GBS, 4),
+               "source": "profiles/hbm_traffic_compositing_batched_c4.md (FETCH_SIZE + WRITE_SIZE, calibrated)"}
     out = {"metric": METRIC, "value": round(mpx, 3), "unit": "Mpixel/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(r["ms"], 4), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32",
@@ -334,6 +346,7 @@ def main():
                       "parallelism": "single GPU"},
            "roofline": roof, "stages_ms": stages,
            "forward_compositing": {"TFLOP/s": fwd_tf, "frac": fwd_tf / PEAK_FP32_TFLOPS if fwd_tf else None},
+           "hbm": hbm,
            "counts": c}
     if eager_ms is not None:
         out["eager_ms_per_step"] = round(eager_ms, 4)

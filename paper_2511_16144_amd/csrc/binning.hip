@@ -127,13 +127,15 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_down(int mode, const uint
 
 __global__ void __launch_bounds__(256) k_compact(const uint32_t* __restrict__ cnt_t,
                                                  const uint32_t* __restrict__ cidx,
-                                                 const uint64_t* __restrict__ dkey, int64_t n_rid,
-                                                 uint32_t* __restrict__ ent, uint64_t* __restrict__ keys) {
+                                                 const uint32_t* __restrict__ dkey, int64_t n_rid,
+                                                 uint32_t* __restrict__ ent, uint32_t* __restrict__ ent_copy,
+                                                 uint32_t* __restrict__ keys) {
   const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (r >= n_rid) return;
   if (cnt_t[r] != 0u) {
     const uint32_t c = cidx[r];
     ent[c] = (uint32_t)r;
+    ent_copy[c] = (uint32_t)r;
     keys[c] = dkey[r];
   }
 }
@@ -285,11 +287,11 @@ void launch_scan(int mode, const uint32_t* src, const uint32_t* idx, uint32_t* o
                        n_dev, n_max, (const uint32_t*)bsum, out);
 }
 
-void launch_compact(const uint32_t* cnt_t, const uint32_t* cidx, const uint64_t* dkey, int64_t n_rid,
-                    uint32_t* ent, uint64_t* keys, hipStream_t s) {
+void launch_compact(const uint32_t* cnt_t, const uint32_t* cidx, const uint32_t* dkey, int64_t n_rid,
+                    uint32_t* ent, uint32_t* ent_copy, uint32_t* keys, hipStream_t s) {
   if (n_rid <= 0) return;
   hipLaunchKernelGGL(k_compact, dim3((unsigned)((n_rid + 255) / 256)), dim3(256), 0, s, cnt_t, cidx,
-                     dkey, n_rid, ent, keys);
+                     dkey, n_rid, ent, ent_copy, keys);
 }
 
 void launch_emit(const GeomRec* geom, const ViewDesc* views, const uint32_t* srid, const uint32_t* off_t,

@@ -92,7 +92,7 @@ void launch_project(const Settings& st, const ViewDesc* views, int n_views,
                     const float* means, const float* log_scales, const float* quats,
                     const float* logits, const void* rgb, const void* feat, int app_bf16,
                     int64_t n, uint32_t npad_shift,
-                    GeomRec* geom, uint32_t* cnt_t, uint32_t* cnt_b, uint64_t* dkey,
+                    GeomRec* geom, uint32_t* cnt_t, uint32_t* cnt_b, uint32_t* dkey,
                     void* app, hipStream_t s);
 
 // scans
@@ -106,8 +106,8 @@ void launch_scan(int mode, const uint32_t* src, const uint32_t* idx, uint32_t* o
                  void* temp, hipStream_t s);
 
 // compaction of visible (view, Gaussian) ids
-void launch_compact(const uint32_t* cnt_t, const uint32_t* cidx, const uint64_t* dkey,
-                    int64_t n_rid, uint32_t* ent, uint64_t* keys, hipStream_t s);
+void launch_compact(const uint32_t* cnt_t, const uint32_t* cidx, const uint32_t* dkey, int64_t n_rid,
+                    uint32_t* ent, uint32_t* ent_copy, uint32_t* keys, hipStream_t s);
 
 // pair emission (load-balanced over pairs), tile ranges
 void launch_emit(const GeomRec* geom, const ViewDesc* views, const uint32_t* srid,

@@ -104,6 +104,16 @@ __device__ void load_app(const void* rgb, const void* feat, int64_t n, int64_t g
   y[3] = 0.f;
 }
 
+// Sort key of a visible Gaussian's camera depth z > z_near: the FP64 bit
+// pattern relative to z_near's, keeping 28 mantissa bits (depths closer than
+// about 2^-28 relative share a key and keep index order; the sort is stable),
+// clamped at z_near * 2^16.  Monotone in z, so sorting the keys sorts by depth.
+__device__ __forceinline__ uint32_t depth_key(double z, double z_near) {
+  const uint64_t d = (uint64_t)__double_as_longlong(z) - (uint64_t)__double_as_longlong(z_near);
+  const uint64_t k = d >> 24;
+  return k > 0xffffffffull ? 0xffffffffu : (uint32_t)k;
+}
+
 template <bool BF16>
 __global__ void __launch_bounds__(256) k_project(
     Settings st, const ViewDesc* __restrict__ views, int n_views,
@@ -111,7 +121,7 @@ __global__ void __launch_bounds__(256) k_project(
     const float* __restrict__ quats, const float* __restrict__ logits,
     const void* __restrict__ rgb, const void* __restrict__ feat, int64_t n, uint32_t npad_shift,
     GeomRec* __restrict__ geom, uint32_t* __restrict__ cnt_t, uint32_t* __restrict__ cnt_b,
-    uint64_t* __restrict__ dkey, void* __restrict__ app) {
+    uint32_t* __restrict__ dkey, void* __restrict__ app) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= ((int64_t)1 << npad_shift)) return;
   if (g >= n) {   // padding ids of the (view, Gaussian) index space: nothing visible
@@ -176,7 +186,7 @@ __global__ void __launch_bounds__(256) k_project(
           r.z = (float)z;
           r.bbox = (uint32_t)bx0 | ((uint32_t)bx1 << 8) | ((uint32_t)by0 << 16) | ((uint32_t)by1 << 24);
           geom[rid] = r;
-          dkey[rid] = ((uint64_t)__double_as_longlong(z)) >> 16;
+          dkey[rid] = depth_key(z, (double)st.z_near);
           any_vis = true;
         }
       }
@@ -408,7 +418,7 @@ __global__ void __launch_bounds__(256) k_twist_final(const double* __restrict__ 
 void launch_project(const Settings& st, const ViewDesc* views, int n_views, const float* means,
                     const float* log_scales, const float* quats, const float* logits,
                     const void* rgb, const void* feat, int app_bf16, int64_t n, uint32_t npad_shift,
-                    GeomRec* geom, uint32_t* cnt_t, uint32_t* cnt_b, uint64_t* dkey, void* app,
+                    GeomRec* geom, uint32_t* cnt_t, uint32_t* cnt_b, uint32_t* dkey, void* app,
                     hipStream_t s) {
   const int64_t npad = (int64_t)1 << npad_shift;
   const int blocks = (int)((npad + 255) / 256);

@@ -245,7 +245,7 @@ struct Work {
   uint32_t *cnt_t = nullptr, *cnt_b = nullptr, *cidx = nullptr, *slot_base = nullptr;
   uint32_t *ent = nullptr, *ent_a = nullptr, *ent_b = nullptr, *srid = nullptr;
   uint32_t *off_t = nullptr, *slot_off = nullptr;
-  uint64_t *dkey = nullptr, *dk0 = nullptr, *dk1 = nullptr;
+  uint32_t *dkey = nullptr, *dk0 = nullptr, *dk1 = nullptr;
   void* app = nullptr;
   Counters* counters = nullptr;
   int32_t* last_idx = nullptr;
@@ -339,9 +339,9 @@ lgs_status w_alloc_front(Work* W) {
   W->ent_b = (uint32_t*)w_alloc(W, 4 * n_rid, ok);
   W->off_t = (uint32_t*)w_alloc(W, 4 * n_rid, ok);
   W->slot_off = (uint32_t*)w_alloc(W, 4 * n_rid, ok);
-  W->dkey = (uint64_t*)w_alloc(W, 8 * n_rid, ok);
-  W->dk0 = (uint64_t*)w_alloc(W, 8 * n_rid, ok);
-  W->dk1 = (uint64_t*)w_alloc(W, 8 * n_rid, ok);
+  W->dkey = (uint32_t*)w_alloc(W, 4 * n_rid, ok);
+  W->dk0 = (uint32_t*)w_alloc(W, 4 * n_rid, ok);
+  W->dk1 = (uint32_t*)w_alloc(W, 4 * n_rid, ok);
   W->app = w_alloc(W, (size_t)std::max<int64_t>(W->n, 1) * (W->app_bf16 ? 40 : 80), ok);
   W->counters = (Counters*)w_alloc(W, sizeof(Counters), ok);
   W->last_idx = (int32_t*)w_alloc(W, 4 * npix, ok);
@@ -409,10 +409,9 @@ void enqueue_front(Work* W, const lgs_gaussians* g, hipStream_t s) {
   launch_scan(SCAN_FLAG_NONZERO, W->cnt_t, nullptr, W->cidx, &W->counters->n_visible, nullptr, n_rid,
               W->scan_tmp, s);
   // the compaction writes ent (kept, index order) and a copy that the depth sort permutes
-  launch_compact(W->cnt_t, W->cidx, W->dkey, n_rid, W->ent, W->dk0, s);
-  launch_compact(W->cnt_t, W->cidx, W->dkey, n_rid, W->ent_a, W->dk0, s);
+  launch_compact(W->cnt_t, W->cidx, W->dkey, n_rid, W->ent, W->ent_a, W->dk0, s);
   bool alt = false;
-  radix_sort_u64(W->dk0, W->ent_a, W->dk1, W->ent_b, &W->counters->n_visible, n_rid, 0, 48, W->radix_small, s,
+  radix_sort_u32(W->dk0, W->ent_a, W->dk1, W->ent_b, &W->counters->n_visible, n_rid, 0, 32, W->radix_small, s,
                  &alt);
   W->srid = alt ? W->ent_b : W->ent_a;
   launch_scan(SCAN_GATHER, W->cnt_t, W->srid, W->off_t, &W->counters->n_pairs, &W->counters->n_visible, n_rid,

@@ -21,8 +21,10 @@ import scenes
 
 # relative margins under which FP32 and FP64 may legitimately take different
 # branches (see the oracle's composite(): m2 cut, alpha cut, alpha clamp,
-# termination, depth order)
-AMBIG = {"m2": 2e-5, "alpha": 2e-5, "clamp": 2e-5, "T": 5e-5, "z": 1e-9}
+# termination, depth order).  The GPU's depth sort key keeps 28 mantissa bits
+# of the FP64 depth, so contributors closer than 2^-28 (3.7e-9) relative keep
+# index order there: the depth margin is 1e-8.
+AMBIG = {"m2": 2e-5, "alpha": 2e-5, "clamp": 2e-5, "T": 5e-5, "z": 1e-8}
 
 TOL_F32 = 1e-4     # FP32 path vs FP64 oracle on the same inputs
 TOL_BF16 = 1e-2    # BF16-stored appearance vs the oracle on unrounded inputs
