@@ -70,41 +70,26 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_reduce(int mode, const ui
 }
 
 // one work-group scans the block sums in place (exclusive) and writes total
-__global__ void __launch_bounds__(1024) k_scan_spine(uint32_t* __restrict__ bsum, const uint32_t* n_dev,
-                                                     int64_t n_max, uint32_t* __restrict__ total) {
-  __shared__ uint32_t sh[16];
-  const int64_t n = count_of(n_dev, n_max);
-  const int64_t nb = (n + kScanTile - 1) / kScanTile;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  uint32_t carry = 0;
-  for (int64_t base = 0; base < nb; base += 1024) {
-    const int64_t i = base + threadIdx.x;
-    uint32_t x = i < nb ? bsum[i] : 0u;
-    uint32_t inc = wave_incl_scan(x, lane);
-    if (lane == 63) sh[wave] = inc;
-    __syncthreads();
-    uint32_t wsum = 0, tot = 0;
-    for (int w = 0; w < 16; ++w) {
-      uint32_t s = sh[w];
-      if (w < wave) wsum += s;
-      tot += s;
-    }
-    if (i < nb) bsum[i] = carry + wsum + inc - x;
-    carry += tot;
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) *total = carry;
-}
 
 __global__ void __launch_bounds__(kScanThreads) k_scan_down(int mode, const uint32_t* __restrict__ src,
                                                             const uint32_t* __restrict__ idx,
                                                             const uint32_t* n_dev, int64_t n_max,
                                                             const uint32_t* __restrict__ bsum,
-                                                            uint32_t* __restrict__ out) {
+                                                            uint32_t* __restrict__ out, uint32_t* __restrict__ total) {
   __shared__ uint32_t sh[4];
   const int64_t n = count_of(n_dev, n_max);
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  if (n == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *total = 0u;
+    return;
+  }
   if (base >= n) return;
+  // offset of this block: the sum of the block sums before it (each block
+  // adds them up itself, so no separate pass over the block sums is needed)
+  uint32_t pre = 0;
+  for (int64_t b = threadIdx.x; b < (int64_t)blockIdx.x; b += kScanThreads) pre += bsum[b];
+  uint32_t boff;
+  block_excl_scan(pre, sh, boff);
   // thread t owns the contiguous items [base + t*8, base + t*8 + 8)
   uint32_t v[kScanItems];
   uint32_t s = 0;
@@ -113,13 +98,14 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_down(int mode, const uint
     v[k] = i < n ? scan_in(mode, src, idx, i) : 0u;
     s += v[k];
   }
-  uint32_t total;
-  uint32_t run = block_excl_scan(s, sh, total) + bsum[blockIdx.x];
+  uint32_t btot;
+  uint32_t run = block_excl_scan(s, sh, btot) + boff;
   for (int k = 0; k < kScanItems; ++k) {
     const int64_t i = base + (int64_t)threadIdx.x * kScanItems + k;
     if (i < n) out[i] = run;
     run += v[k];
   }
+  if (base + kScanTile >= n && threadIdx.x == 0) *total = boff + btot;   // the last block
 }
 
 // reduce kernel must sum the same items as the down-sweep: both cover the
@@ -237,21 +223,55 @@ __global__ void k_set_overflow(Counters* cnt, uint64_t cap_pairs, uint64_t cap_s
   }
 }
 
-__global__ void __launch_bounds__(256) k_item_keys(const ViewDesc* __restrict__ views,
-                                                   const uint2* __restrict__ ranges, int tile_shift,
-                                                   const uint32_t* __restrict__ items, int64_t n_items,
-                                                   uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n_items) return;
-  const uint32_t it = items[i];
+// Work items grouped by queue and, inside a queue, by descending list length
+// (longest first), in one workgroup: a counting sort on 11-bit keys
+// (queue << 8 | 255 - length bucket, bucket = 4 sqrt(length) clamped at 255).
+// Items of one bucket may come out in any order; the order only affects
+// scheduling, not results.
+constexpr int kOrderThreads = 1024;
+constexpr int kOrderBins = kQueues * 256;
+
+__device__ __forceinline__ uint32_t item_key(const ViewDesc* __restrict__ views, const uint2* __restrict__ ranges,
+                                             int tile_shift, uint32_t it) {
   const uint32_t bx = it & 255u, by = (it >> 8) & 255u, v = it >> 16;
   const ViewDesc& V = views[v];
   const uint32_t t = (uint32_t)V.tile_off + (by >> tile_shift) * (uint32_t)V.tiles_x + (bx >> tile_shift);
   const uint2 r = ranges[t];
-  const uint32_t len = r.y - r.x;
-  // grouped by queue, then descending length (ascending key; lengths clamp at 8191)
-  keys[i] = (tile_queue(t) << 13) | (8191u - (len < 8191u ? len : 8191u));
-  vals[i] = it;
+  const uint32_t bucket = min(255u, (uint32_t)(4.f * sqrtf((float)(r.y - r.x))));
+  return (tile_queue(t) << 8) | (255u - bucket);
+}
+
+__global__ void __launch_bounds__(kOrderThreads) k_order_items(const ViewDesc* __restrict__ views,
+                                                             const uint2* __restrict__ ranges, int tile_shift,
+                                                             const uint32_t* __restrict__ items, int64_t n_items,
+                                                             uint32_t* __restrict__ out) {
+  __shared__ uint32_t hist[kOrderBins];
+  __shared__ uint32_t wsum[kOrderThreads / 64];
+  for (int i = threadIdx.x; i < kOrderBins; i += kOrderThreads) hist[i] = 0u;
+  __syncthreads();
+  for (int64_t i = threadIdx.x; i < n_items; i += kOrderThreads)
+    atomicAdd(&hist[item_key(views, ranges, tile_shift, items[i])], 1u);
+  __syncthreads();
+  // exclusive scan of the bins, two per thread
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t a = hist[2 * threadIdx.x], b = hist[2 * threadIdx.x + 1];
+  uint32_t inc = a + b;
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += y;
+  }
+  if (lane == 63) wsum[wave] = inc;
+  __syncthreads();
+  uint32_t pre = 0;
+  for (int w = 0; w < wave; ++w) pre += wsum[w];
+  const uint32_t ex = pre + inc - (a + b);
+  hist[2 * threadIdx.x] = ex;
+  hist[2 * threadIdx.x + 1] = ex + a;
+  __syncthreads();
+  for (int64_t i = threadIdx.x; i < n_items; i += kOrderThreads) {
+    const uint32_t it = items[i];
+    out[atomicAdd(&hist[item_key(views, ranges, tile_shift, it)], 1u)] = it;
+  }
 }
 
 __global__ void __launch_bounds__(256) k_reset_counters(Counters* cnt) {
@@ -281,10 +301,8 @@ void launch_scan(int mode, const uint32_t* src, const uint32_t* idx, uint32_t* o
   if (nb > 0)
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, mode, src, idx,
                        n_dev, n_max, bsum);
-  hipLaunchKernelGGL(k_scan_spine, dim3(1), dim3(1024), 0, s, bsum, n_dev, n_max, total);
-  if (nb > 0)
-    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanThreads), 0, s, mode, src, idx,
-                       n_dev, n_max, (const uint32_t*)bsum, out);
+  hipLaunchKernelGGL(k_scan_down, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(kScanThreads), 0, s, mode, src, idx,
+                     n_dev, n_max, (const uint32_t*)bsum, out, total);
 }
 
 void launch_compact(const uint32_t* cnt_t, const uint32_t* cidx, const uint32_t* dkey, int64_t n_rid,
@@ -326,14 +344,11 @@ void launch_set_overflow(Counters* cnt, uint64_t cap_pairs, uint64_t cap_slots, 
 }
 
 uint32_t* launch_order_items(const ViewDesc* views, const uint2* ranges, int tile_shift, const uint32_t* items,
-                             int64_t n_items, uint32_t* keys_a, uint32_t* items_a, uint32_t* keys_b,
-                             uint32_t* items_b, void* radix_temp, hipStream_t s) {
-  if (n_items <= 0) return items_a;
-  hipLaunchKernelGGL(k_item_keys, dim3((unsigned)((n_items + 255) / 256)), dim3(256), 0, s, views, ranges,
-                     tile_shift, items, n_items, keys_a, items_a);
-  bool alt = false;
-  radix_sort_u32(keys_a, items_a, keys_b, items_b, nullptr, n_items, 0, 16, radix_temp, s, &alt);
-  return alt ? items_b : items_a;
+                             int64_t n_items, uint32_t* out, hipStream_t s) {
+  if (n_items <= 0) return out;
+  hipLaunchKernelGGL(k_order_items, dim3(1), dim3(kOrderThreads), 0, s, views, ranges, tile_shift, items, n_items,
+                     out);
+  return out;
 }
 
 void launch_reset_counters(Counters* cnt, hipStream_t s) {

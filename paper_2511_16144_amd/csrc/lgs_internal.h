@@ -133,12 +133,10 @@ void radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t
                     void* temp, hipStream_t s, bool* result_in_alt);
 
 // work queue ordering (blocks by descending tile-list length)
-// work items ordered by descending length of their tile's list (stable);
-// returns the buffer holding the result (items_a or items_b)
+// work items grouped by queue, each queue by descending length of the tile's
+// list (counting sort on coarse length buckets); returns out
 uint32_t* launch_order_items(const ViewDesc* views, const uint2* ranges, int tile_shift,
-                             const uint32_t* items, int64_t n_items, uint32_t* keys_a,
-                             uint32_t* items_a, uint32_t* keys_b, uint32_t* items_b,
-                             void* radix_temp, hipStream_t s);
+                             const uint32_t* items, int64_t n_items, uint32_t* out, hipStream_t s);
 
 // compositing
 void launch_raster_fwd(const Settings& st, const ViewDesc* views, const ViewImages* out,

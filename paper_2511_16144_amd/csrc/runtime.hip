@@ -254,8 +254,7 @@ struct Work {
   uint32_t *k0 = nullptr, *v0 = nullptr, *k1 = nullptr, *v1 = nullptr, *pkeys = nullptr, *pvals = nullptr;
   uint2* ranges = nullptr;
   const uint32_t* items_static = nullptr;
-  uint32_t *ik_a = nullptr, *ii_a = nullptr, *ik_b = nullptr, *ii_b = nullptr;
-  void* radix_items = nullptr;
+  uint32_t* ii_a = nullptr;   // work items in scheduling order
   const uint32_t* items = nullptr;
   float* partials = nullptr;
   uint8_t* mask = nullptr;
@@ -350,11 +349,7 @@ lgs_status w_alloc_front(Work* W) {
   W->radix_small = w_alloc(W, radix_temp_bytes(n_rid), ok);
   W->ranges = (uint2*)w_alloc(W, 8 * std::max<int64_t>(W->plan.n_tiles, 1), ok);
   const int64_t ni = std::max<int64_t>(W->plan.n_items, 1);
-  W->ik_a = (uint32_t*)w_alloc(W, 4 * ni, ok);
   W->ii_a = (uint32_t*)w_alloc(W, 4 * ni, ok);
-  W->ik_b = (uint32_t*)w_alloc(W, 4 * ni, ok);
-  W->ii_b = (uint32_t*)w_alloc(W, 4 * ni, ok);
-  W->radix_items = w_alloc(W, radix_temp_bytes(ni), ok);
   W->items_static = get_items(W->ctx, W->plan, W->st.tile);
   if (!ok || !W->items_static) return fail(W->ctx, LGS_ERR_HIP, "device allocation failed");
   return LGS_OK;
@@ -436,8 +431,7 @@ void enqueue_pairs(Work* W, hipStream_t s) {
   W->pvals = alt ? W->v1 : W->v0;
   launch_tile_ranges(W->pkeys, W->counters, W->cap_pairs, W->ranges, s);
   if (W->st.order == 1)
-    W->items = launch_order_items(W->d_views, W->ranges, P.tile_shift, W->items_static, P.n_items, W->ik_a,
-                                  W->ii_a, W->ik_b, W->ii_b, W->radix_items, s);
+    W->items = launch_order_items(W->d_views, W->ranges, P.tile_shift, W->items_static, P.n_items, W->ii_a, s);
   else
     W->items = W->items_static;
 }
