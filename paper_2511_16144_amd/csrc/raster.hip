@@ -19,17 +19,19 @@
 // are broadcast to SGPRs (v_readlane from the lane that loaded it, or a
 // scalar load) and used directly as VALU operands, so no LDS staging and no
 // per-lane gathers are needed.  The wave leaves the list as soon as a ballot
-// shows every lane finished.  Waves pop blocks from a device work counter
+// shows every lane finished.  Waves pop blocks from per-XCD work queues
 // (persistent grid).
 //
 // Backward.  Each wave restarts from the last contributor of its pixels and
 // walks the list backwards, recovering T before each entry as T / (1 - alpha)
-// and the weighted sum of what lies behind as a single running scalar.  The
-// 26 per-lane partial derivatives of an entry (mean' 2, conic 3, opacity 1,
-// colour/depth/feature 20) are summed over the wave by a butterfly
-// transpose-reduction and written to the entry's own (Gaussian, block) slot;
-// a segmented reduction over each Gaussian's slots then forms its gradient.
-// No atomics: results are deterministic run to run.
+// and the weighted sum of what lies behind as a single running scalar.  Per
+// entry, the 6 geometric partial derivatives (mean' 2, conic 3, opacity 1) are
+// summed over the wave by a butterfly transpose-reduction; the 20 colour /
+// depth / feature partials, sum_p w_p g_p, are collected for batches of 8
+// entries as a (entries x pixels) x (pixels x channels) product on the matrix
+// cores.  Both go to the entry's own (Gaussian, block) slot; a segmented
+// reduction over each Gaussian's slots then forms its gradient.  No atomics:
+// results are deterministic run to run.
 #include "lgs_internal.h"
 
 namespace lgs {
@@ -332,8 +334,41 @@ __device__ __forceinline__ int wave_max_i32(int x) {
   return x;
 }
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+constexpr int kZRow = 72;                  // bf16 per LDS row (64 pixels + pad; 144 B, 16-B aligned)
+// FP32 -> BF16 bits, round to nearest even (finite inputs)
+__device__ __forceinline__ unsigned short bf16_rne(float x) {
+  const uint32_t u = __float_as_uint(x);
+  return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_to_f(unsigned short h) { return __uint_as_float((uint32_t)h << 16); }
+
+// Transpose-reduction of 8 values over the wave (as transpose_reduce32): on
+// exit lane l holds the wave sum of value l >> 3.
+__device__ __forceinline__ float transpose_reduce8(const float v[8], int lane) {
+  float a[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]), __float_as_uint(v[4 + i]), false, false);
+    a[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  float b[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a[i]), __float_as_uint(a[2 + i]), false, false);
+    b[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  const bool h8 = (lane & 8) != 0;
+  float c = bsel(h8, b[0], b[1]) + dpp<0x128>(bsel(h8, b[1], b[0]));
+  c = c + dpp<0x141>(c);
+  c = c + dpp<0x4E>(c);
+  return c + dpp<0xB1>(c);
+}
+
+// Six waves per SIMD (80 VGPRs; measured fastest for this kernel).
 template <bool BF16, bool FUSED_L1>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) k_raster_bwd(
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))) k_raster_bwd(
     Settings st, const ViewDesc* __restrict__ views, const ViewImages* __restrict__ upstream,
     const ViewImages* __restrict__ fwd_out, const ViewImages* __restrict__ targets,
     const float* __restrict__ loss_w, const uint2* __restrict__ ranges,
@@ -344,6 +379,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))
     const float* __restrict__ T_state, const uint32_t* __restrict__ slot_base,
     float* __restrict__ partials, uint8_t* __restrict__ mask) {
   const int lane = threadIdx.x & 63;
+  extern __shared__ unsigned short lds_z[];
+  // this wave's LDS rows (BF16, 64 pixels + pad each): the block's upstream
+  // per channel, hi (20) and lo (20; the fused L1 sign needs no lo part), and
+  // the blend weights of up to 8 batched entries, hi (8) and lo (8)
+  constexpr int kGRows = FUSED_L1 ? 20 : 40;
+  unsigned short* lz = lds_z + (threadIdx.x >> 6) * ((kGRows + 16) * kZRow);
+  unsigned short* wz = lz + kGRows * kZRow;
+  const int grp = lane >> 4, col = lane & 15;
   if (cnt->overflow) return;
   uint64_t n_eval = 0, n_con = 0;   // this wave's work, added to the counters once at the end
   const uint32_t q = blockIdx.x % (uint32_t)kQueues;
@@ -402,6 +445,67 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))
     const uint32_t kbeg = ranges[tile].x;
     const float gTT = gT * Tfin;
     float Tc = Tfin, sB = 0.f;
+    // upstream rows: for the fused L1 gradient the sign (exact in BF16; the
+    // per-channel scale is applied to the MFMA result), else hi + lo BF16.
+    // The colour partials of a batch of entries, dY[e][c] = sum_p w[p][e] g[p][c],
+    // are a (entries x pixels) x (pixels x channels) product: v_mfma_f32_16x16x32_bf16
+    // on the two-term splits (hi.hi + lo.hi, + hi.lo for a general upstream),
+    // FP32 accumulation.
+    float gscale[3] = {1.f, 1.f, 1.f};
+    if (FUSED_L1) {
+      const float HWf = (float)HW;
+      gscale[0] = loss_w[0] / (3.f * HWf); gscale[1] = loss_w[1] / HWf; gscale[2] = loss_w[2] / (16.f * HWf);
+    }
+#pragma unroll
+    for (int c = 0; c < 20; ++c) {
+      if (FUSED_L1) {
+        const float sgn = g[c] > 0.f ? 1.f : (g[c] < 0.f ? -1.f : 0.f);
+        lz[c * kZRow + lane] = bf16_rne(sgn);
+      } else {
+        const unsigned short hi = bf16_rne(g[c]);
+        lz[c * kZRow + lane] = hi;
+        lz[(20 + c) * kZRow + lane] = bf16_rne(g[c] - bf16_to_f(hi));
+      }
+    }
+    int nb = 0;
+    uint32_t slotv = 0;
+    auto flush = [&]() {
+      f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
+      const int er = col & 7;
+      const int ch1 = col < 4 ? 16 + col : 16;
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) {
+        const int off = 32 * ks + 8 * grp;
+        const bf16x8_t ah = *(const bf16x8_t*)(wz + er * kZRow + off);
+        const bf16x8_t al = *(const bf16x8_t*)(wz + (8 + er) * kZRow + off);
+        const bf16x8_t bh0 = *(const bf16x8_t*)(lz + col * kZRow + off);
+        bf16x8_t bh1 = *(const bf16x8_t*)(lz + ch1 * kZRow + off);
+        if (col >= 4) bh1 = (bf16x8_t){};
+        c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh0, c0, 0, 0, 0);
+        c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh0, c0, 0, 0, 0);
+        c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh1, c1, 0, 0, 0);
+        c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh1, c1, 0, 0, 0);
+        if (!FUSED_L1) {
+          const bf16x8_t bl0 = *(const bf16x8_t*)(lz + (20 + col) * kZRow + off);
+          bf16x8_t bl1 = *(const bf16x8_t*)(lz + (20 + ch1) * kZRow + off);
+          if (col >= 4) bl1 = (bf16x8_t){};
+          c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl0, c0, 0, 0, 0);
+          c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl1, c1, 0, 0, 0);
+        }
+      }
+      const float s0 = FUSED_L1 ? (col < 3 ? gscale[0] : (col == 3 ? gscale[1] : gscale[2])) : 1.f;
+      const float s1 = FUSED_L1 ? gscale[2] : 1.f;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int e = 4 * grp + i;
+        const uint32_t se = (uint32_t)__builtin_amdgcn_ds_bpermute((e & 7) * 4, (int)slotv);
+        if (e < nb) {
+          partials[(size_t)se * kPartials + 6 + col] = c0[i] * s0;
+          if (col < 4) partials[(size_t)se * kPartials + 22 + col] = c1[i] * s1;
+        }
+      }
+      nb = 0;
+    };
     for (int top = kmax; top >= (int)kbeg; top -= 64) {
       // lane l loads entry top - l (the list backwards) and decides whether
       // the wave visits it
@@ -432,7 +536,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))
         float y[20];
         load_y<BF16>(app, rid & npad_mask, y);
         y[3] = gr.z;
-        float vv[32];
+        float vv[8];
         {
           const float rinv = __builtin_amdgcn_rcpf(1.f - e.alpha);
           const float Tp = Tc * rinv;
@@ -452,26 +556,32 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))
           vv[3] = dm2 * 2.f * dx * dy;
           vv[4] = dm2 * dy * dy;
           vv[5] = dgeo * e.G;
-#pragma unroll
-          for (int c = 0; c < 20; ++c) vv[6 + c] = wc * g[c];
-#pragma unroll
-          for (int c = 26; c < 32; ++c) vv[c] = 0.f;
+          vv[6] = 0.f;
+          vv[7] = 0.f;
+          const unsigned short wh = bf16_rne(wc);
+          wz[nb * kZRow + lane] = wh;
+          wz[(8 + nb) * kZRow + lane] = bf16_rne(wc - bf16_to_f(wh));
         }
-        const float s = transpose_reduce32(vv, lane);
         const uint32_t bb = gr.bbox;
         const uint32_t bw = ((bb >> 8) & 255u) - (bb & 255u) + 1u;
         const uint32_t slot = slot_base[rid] + (by - (uint32_t)by0) * bw + (bx - (uint32_t)bx0);
-        const int idx = lane >> 1;
-        if ((lane & 1) == 0 && idx < kPartials) partials[(size_t)slot * kPartials + idx] = s;
+        const float s8 = transpose_reduce8(vv, lane);
+        if ((lane & 7) == 0 && (lane >> 3) < 6) partials[(size_t)slot * kPartials + (lane >> 3)] = s8;
+        slotv = lane == nb ? slot : slotv;
+        ++nb;
+        if (nb == 8) flush();
         if (lane == 0) mask[slot] = 1;
       }
     }
+    if (nb > 0) flush();
   }
   if (lane == 0) {
     atomicAdd(&cnt->bwd_evals, (unsigned long long)n_eval);
     atomicAdd(&cnt->bwd_contrib, (unsigned long long)n_con);
   }
 }
+
+
 
 // Per-Gaussian sum of the backward's partials.  Visible (view, Gaussian) c
 // owns the slot range [slot_off[c], slot_off[c + 1]) (the last one ends at
@@ -546,16 +656,17 @@ static void launch_bwd_t(const Settings& st, const ViewDesc* views, const ViewIm
                          Counters* cnt, int waves_per_group, const int32_t* last_idx, const float* T_state,
                          const uint32_t* slot_base, float* partials, uint8_t* mask, hipStream_t s) {
   const int threads = 64 * waves_per_group;
+  const size_t lds = (size_t)waves_per_group * ((FUSED ? 20 : 40) + 16) * kZRow * sizeof(unsigned short);
   int dev = 0, cus = 256;
   hipGetDevice(&dev);
   hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   int occ = 1;
-  hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_raster_bwd<BF16, FUSED>, threads, 0);
+  hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_raster_bwd<BF16, FUSED>, threads, lds);
   int64_t grid = (int64_t)cus * (occ > 0 ? occ : 1);
   const int64_t need = (n_items + waves_per_group - 1) / waves_per_group;
   if (grid > need) grid = need;
   if (grid < kQueues) grid = kQueues;   // every queue needs a workgroup (index mod kQueues) to drain it
-  hipLaunchKernelGGL((k_raster_bwd<BF16, FUSED>), dim3((unsigned)grid), dim3(threads), 0, s, st, views,
+  hipLaunchKernelGGL((k_raster_bwd<BF16, FUSED>), dim3((unsigned)grid), dim3(threads), lds, s, st, views,
                      upstream, fwd_out, targets, loss_w, ranges, vals, geom, app, npad_mask, items, qoff,
                      (uint32_t)n_items, cnt, last_idx, T_state, slot_base, partials, mask);
 }

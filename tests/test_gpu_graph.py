@@ -13,7 +13,7 @@ import torch
 import scenes
 from oracle import raster_fp64 as R
 from parity import (TOL_F32, ambiguous, forward_errors, fmt, gaussian_ambiguity, gpu_params, grad_errors,
-                    grads_np, to_np, upstream_tensors)
+                    grads_np, rel_err, to_np, upstream_tensors)
 
 pytestmark = pytest.mark.gpu
 
@@ -96,6 +96,16 @@ class GraphRun:
             self.h = None
 
 
+def assert_close_groups(a, b, tol=1e-5):
+    """The fused L1 backward multiplies the exact BF16 sign of the residual by
+    the per-channel scale after the matrix-core product; an explicit upstream
+    is split into two BF16 terms before it.  The two agree to rounding, not
+    bitwise."""
+    for k in a:
+        l2, mx = rel_err(a[k], b[k])
+        assert l2 <= tol and mx <= tol, (k, l2, mx)
+
+
 def l1_upstream_f32(outs, wl):
     """dL/dY of the L1 loss, computed in FP32 exactly as the kernel does."""
     ups = []
@@ -142,13 +152,20 @@ def test_graph_equals_eager_and_replays(ctx):
     outs_e = to_np(outs_e)
     for k in ("rgb", "depth", "feat", "T"):
         assert np.array_equal(outs_e[0][k], outs_g[0][k]), k
-    # eager backward of the FP32 L1 upstream: bitwise equal gradients
+    # eager fused-L1 backward: bitwise equal gradients (same kernels)
+    tg = [{"rgb": torch.as_tensor(t.rgb).cuda(), "depth": torch.as_tensor(t.depth).cuda(),
+           "feat": torch.as_tensor(t.feat).cuda()} for t in wl.targets]
+    outs_t = [{k: torch.as_tensor(v).cuda() for k, v in o.items() if k != "n"} for o in outs_e]
+    gl = grads_np(ctx.backward_l1(state, prm, outs_t, tg, wl.loss_w))
+    torch.cuda.synchronize()
+    for k in gl:
+        assert np.array_equal(gl[k], grads_g[k]), k
+    # eager backward of the same L1 upstream given explicitly: equal to rounding
     ups = l1_upstream_f32(outs_e, wl)
     ge = grads_np(ctx.backward(state, prm, upstream_tensors(ups)))
     torch.cuda.synchronize()
     state.release()
-    for k in ge:
-        assert np.array_equal(ge[k], grads_g[k]), k
+    assert_close_groups(ge, grads_g)
     # and the oracle's loss gradient
     ref = R.render(wl.scene, wl.cams, R.Settings())
     gr = R.vjp(wl.scene, wl.cams, ups, R.Settings())
@@ -232,7 +249,7 @@ def test_batched_views_equal_single_views(ctx, order):
 
 def test_eager_l1_step_vs_oracle(ctx):
     """forward + lgs_backward_l1: the fused L1 gradient equals the FP32 host
-    gradient bitwise (fed through lgs_backward) and the oracle's loss
+    gradient fed through lgs_backward to rounding, and the oracle's loss
     gradient within 1e-4."""
     import paper_2511_16144_amd as P
     wl = scenes.make_workload(1)
@@ -248,8 +265,7 @@ def test_eager_l1_step_vs_oracle(ctx):
     ge = grads_np(ctx.backward(st, prm, upstream_tensors(ups)))
     torch.cuda.synchronize()
     st.release()
-    for k in ge:
-        assert np.array_equal(ge[k], gf[k]), k
+    assert_close_groups(ge, gf)
     ref = R.render(wl.scene, wl.cams, R.Settings())
     gr = R.vjp(wl.scene, wl.cams, ups, R.Settings())
     amb = ambiguous(ref[0]["margin"])
