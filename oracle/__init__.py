@@ -15,7 +15,10 @@ used by the L1 depth loss and optimises Theta through the renderer):
     blocks in torch float64, with the gradient taken by torch.autograd;
   * ``brute``        -- a second, pure-Python (``math`` module) per-pixel
     brute force for tiny scenes, used to pin ``raster_fp64`` (forward) and,
-    through central finite differences, its autodiff gradient.
+    through central finite differences, its autodiff gradient;
+  * ``loss_fp64``    -- the mapping loss of Eq. (1) downstream of the
+    renderer, with its D-SSIM term (Gaussian-window SSIM, zero padding), and
+    its gradient with respect to the rendered images by torch.autograd.
 
 The paper gives no rasterizer formulas; the readings taken where it is silent
 (colour model, depth definition, cut-offs, termination, pose perturbation...)
