@@ -107,7 +107,7 @@ def loss_and_upstream(outs, targets, loss_w, lam: float = SSIM_LAMBDA):
         gr, gd, gf = (g if g is not None else torch.zeros_like(x)
                       for g, x in zip(grads[3 * i:3 * i + 3], (v["rgb"], v["depth"], v["feat"])))
         ups.append(torch.cat([gr, gd[None], gf], 0).numpy())
-    return float(L), terms, ups
+    return float(L.detach()), terms, ups
 
 
 def ssim_brute(X: np.ndarray, Y: np.ndarray, radius: int = SSIM_RADIUS, sigma: float = SSIM_SIGMA,
