@@ -3,7 +3,9 @@
 One step = forward render (RGB + depth + 16-d feature) of every view, the L1
 loss gradient of Eq. (1) (without D-SSIM), and the full backward to the
 Gaussian parameters and the pose twists (lgs_forward + lgs_backward_l1, all
-stages in the library's HIP kernels) on device-resident inputs.  Metric: Mpixel/s = sum over views of W x H per step
+stages in the library's HIP kernels) on device-resident inputs.  The same
+step with the D-SSIM term of the photometric loss (lam = 0.2, lgs_loss
+before the backward) and the loss kernel alone are reported beside it.  Metric: Mpixel/s = sum over views of W x H per step
 / step time.
 
 Default workload: the batched configuration (500k Gaussians in a 6x6x3 m
@@ -145,7 +147,7 @@ def time_workload(ctx, wl, steps, warmup, dev, tune, settings):
             "settings": {"tile": st.tile, "chunk": st.chunk, "order": st.order}}
 
 
-def time_workload_graph(ctx, wl, steps, warmup, dev, tune, settings):
+def time_workload_graph(ctx, wl, steps, warmup, dev, tune, settings, ssim_lambda=0.0):
     """Same step as `time_workload`, captured once as a hipGraph by the
     library (lgs_graph_create) and replayed: one launch per step."""
     import torch
@@ -180,7 +182,7 @@ def time_workload_graph(ctx, wl, steps, warmup, dev, tune, settings):
         st = best
     st.profile = 0     # one graph for the whole step; stage times come from the eager form
     h = C.c_void_p()
-    rc = B.lib().lgs_graph_create(ctx._h, C.byref(st), C.byref(g), V, cams, ti, lw, im, C.byref(grads[1]), 0,
+    rc = B.lib().lgs_graph_create(ctx._h, C.byref(st), C.byref(g), V, cams, ti, lw, C.c_float(ssim_lambda), im, C.byref(grads[1]), 0,
                                   stream, C.byref(h))
     if rc != 0:
         raise B.LgsError(rc, B.lib().lgs_last_error(ctx._h).decode())
@@ -215,6 +217,45 @@ def time_workload_graph(ctx, wl, steps, warmup, dev, tune, settings):
         B.lib().lgs_graph_destroy(h)
     return {"ms": ms, "wall_s": wall, "counts": counts, "stages": stages,
             "settings": {"tile": st.tile, "chunk": st.chunk, "order": st.order}}
+
+
+# Algorithmic HBM bytes of the loss kernel per pixel: rendered and observed
+# RGB read (12 + 12), RGB gradient written (12); depth read 4 + 4, written 4;
+# features read 64 + 64, written 64.
+LOSS_BYTES_PER_PIXEL = 240
+
+
+def time_loss(ctx, wl, dev, settings, lam, reps=50, warmup=5):
+    """Median time of one lgs_loss call (D-SSIM + L1 terms and dL/dY of every
+    view) on the workload's rendered images: HIP events on the launching
+    stream around each call (the call also copies its small view table to
+    the device)."""
+    import torch
+    import paper_2511_16144_amd as P
+    dt = torch.bfloat16 if wl.scene.dtype == "bf16" else torch.float32
+    s = wl.scene
+    params = P.params_from_arrays(s.means, s.log_scales, s.quats, s.logits, s.rgb, s.feat, device=dev,
+                                  appearance_dtype=dt)
+    outs, state = ctx.forward(params, wl.cams, settings)
+    torch.cuda.synchronize()
+    state.release()
+    ims = [{k: o[k] for k in ("rgb", "depth", "feat")} for o in outs]
+    tgts = [{"rgb": torch.as_tensor(t.rgb).to(dev), "depth": torch.as_tensor(t.depth).to(dev),
+             "feat": torch.as_tensor(t.feat).to(dev)} for t in wl.targets]
+    grad = [{"rgb": torch.empty((3, c.height, c.width), device=dev),
+             "depth": torch.empty((c.height, c.width), device=dev),
+             "feat": torch.empty((16, c.height, c.width), device=dev)} for c in wl.cams]
+    for _ in range(warmup):
+        ctx.loss(wl.cams, ims, tgts, wl.loss_w, lam, grad=grad)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in ev:
+        e0.record()
+        _, terms = ctx.loss(wl.cams, ims, tgts, wl.loss_w, lam, grad=grad)
+        e1.record()
+    torch.cuda.synchronize()
+    ts = sorted(e0.elapsed_time(e1) for e0, e1 in ev)
+    return ts[len(ts) // 2], terms.cpu().numpy()
 
 
 def cpu_baseline(wl, budget_s=15.0):
@@ -262,6 +303,8 @@ def main():
     ap.add_argument("--order", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-dssim", action="store_true",
+                    help="skip the step with the D-SSIM loss term (lam = 0.2) and the loss-kernel timing")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device-to-device three times: a kernel of known HBM traffic "
                          "against which rocprofv3 FETCH_SIZE / WRITE_SIZE counts are scaled")
@@ -350,6 +393,19 @@ def main():
            "counts": c}
     if eager_ms is not None:
         out["eager_ms_per_step"] = round(eager_ms, 4)
+    if not args.no_dssim:
+        lam = 0.2
+        log(f"[bench] timing the step with the D-SSIM loss term (lam = {lam}) and the loss kernel")
+        fixed_st = P.Settings(**r["settings"])
+        rd = time_workload_graph(ctx, wl, args.steps, args.warmup, dev, False, fixed_st, ssim_lambda=lam)
+        loss_ms, terms = time_loss(ctx, wl, dev, fixed_st, lam)
+        lb = LOSS_BYTES_PER_PIXEL * wl.pixels
+        out["dssim"] = {"ssim_lambda": lam, "graph_ms_per_step": round(rd["ms"], 4),
+                        "Mpixel/s": round(wl.pixels / (rd["ms"] / 1e3) / 1e6, 3),
+                        "loss_call_ms": round(loss_ms, 4), "loss_bytes": lb,
+                        "loss_GB/s": round(lb / (loss_ms / 1e3) / 1e9, 1),
+                        "loss_hbm_frac": round(lb / (loss_ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4),
+                        "view0_terms": [round(float(x), 6) for x in terms[0]]}
     if not args.no_plain and cfg != 2:
         log("[bench] timing the plain FP32 single-view form (C2)")
         wl2 = scenes.make_workload(2)

@@ -170,6 +170,34 @@ lgs_status lgs_backward_l1(lgs_context *ctx, const lgs_fwd_state *state,
                            const lgs_images *targets, const float loss_w[3],
                            lgs_grads *grads, hipStream_t stream);
 
+/* The mapping loss of Eq. (1) with the D-SSIM term of its photometric part
+ * (Sec. III-B.3), and its gradient with respect to the rendered images:
+ *   L = sum over views of  w_rgb ((1 - lam) mean|I - I*| + lam (1 - SSIM))
+ *                          + w_depth mean|D - D*| + w_feat mean|F - F*|,
+ * loss_w = {w_rgb, w_depth, w_feat}, lam = ssim_lambda in [0, 1] (the 3D
+ * Gaussian Splatting convention is 0.2).  SSIM is the mean over the three
+ * colour channels and every pixel of the SSIM map under an 11 x 11 Gaussian
+ * window (sigma 1.5, weights summing to 1, zero padding at the border),
+ * C1 = 0.01^2, C2 = 0.03^2 (images in [0, 1]).  sign(0) = 0 in the L1
+ * terms.
+ *   cams[n_views]    only width and height are read
+ *   out, targets     rendered and observed images (device FP32 planes;
+ *                    final_T and n_contrib ignored)
+ *   grad             receives dL/dY: rgb [3][H][W], depth, feat [16][H][W]
+ *                    (device, overwritten; final_T and n_contrib ignored);
+ *                    it may be passed to lgs_backward as grad_out
+ *   terms            NULL, or device FP32 [n_views][4] receiving per view
+ *                    mean|I-I*|, 1 - SSIM (0 when ssim_lambda = 0: the SSIM
+ *                    stencil is skipped), mean|D-D*|, mean|F-F*|
+ * Enqueued on `stream` (the context keeps a small view table and partial
+ * sums; calls on one context are ordered by its stream).  Deterministic.
+ * LGS_ERR_INVALID_ARG for NULL or misaligned planes, non-finite weights or
+ * ssim_lambda outside [0, 1]. */
+lgs_status lgs_loss(lgs_context *ctx, int32_t n_views, const lgs_camera *cams,
+                    const lgs_images *out, const lgs_images *targets,
+                    const float loss_w[3], float ssim_lambda,
+                    const lgs_images *grad, float *terms, hipStream_t stream);
+
 lgs_status lgs_state_counts(const lgs_fwd_state *state, lgs_counts *out);
 /* With settings.profile = 1 on the forward, after its backward: elapsed
  * milliseconds of ms[0..4] = projection + depth sort + scans, pair emission
@@ -179,12 +207,16 @@ lgs_status lgs_state_counts(const lgs_fwd_state *state, lgs_counts *out);
 lgs_status lgs_state_stage_ms(const lgs_fwd_state *state, float ms[5]);
 lgs_status lgs_state_release(lgs_context *ctx, lgs_fwd_state *state);
 
-/* Whole mapping-loss step as one captured hipGraph (the eager pair
- * lgs_forward + lgs_backward_l1 computes the same step): forward, L1 loss
- * gradient of Eq. (1) without its D-SSIM term (sum over views of
- * mean|RGB-RGB*| + w_depth mean|D-D*| + w_feat mean|F-F*|, sign(0) = 0,
- * loss_w = {1, w_depth, w_feat}), backward.  targets[n_views] (device
- * planes, final_T ignored), out[n_views] and grads are bound at creation;
+/* Whole mapping-loss step as one captured hipGraph: forward, gradient of the
+ * loss of Eq. (1), backward.  With ssim_lambda = 0 the loss is the L1 form
+ * (sum over views of w_rgb mean|RGB-RGB*| + w_depth mean|D-D*| + w_feat
+ * mean|F-F*|, sign(0) = 0) whose gradient the backward compositing kernel
+ * forms itself (the eager lgs_forward + lgs_backward_l1 computes the same
+ * step); with ssim_lambda in (0, 1] it is the loss of lgs_loss, whose
+ * kernel writes dL/dY into graph-owned planes before the backward (the
+ * eager lgs_forward + lgs_loss + lgs_backward computes the same step).
+ * targets[n_views] (device planes, final_T ignored), out[n_views] and grads
+ * are bound at creation;
  * every launch recomputes them from the current contents of the Gaussian
  * arrays.  pair_capacity bounds the (tile, Gaussian) pairs; a launch that
  * would exceed it writes nothing valid and lgs_graph_status then returns
@@ -192,9 +224,10 @@ lgs_status lgs_state_release(lgs_context *ctx, lgs_fwd_state *state);
 lgs_status lgs_graph_create(lgs_context *ctx, const lgs_settings *st,
                             const lgs_gaussians *g, int32_t n_views,
                             const lgs_camera *cams, const lgs_images *targets,
-                            const float loss_w[3], const lgs_images *out,
-                            const lgs_grads *grads, int64_t pair_capacity,
-                            hipStream_t stream, lgs_graph **graph_out);
+                            const float loss_w[3], float ssim_lambda,
+                            const lgs_images *out, const lgs_grads *grads,
+                            int64_t pair_capacity, hipStream_t stream,
+                            lgs_graph **graph_out);
 lgs_status lgs_graph_launch(lgs_graph *graph, hipStream_t stream);
 /* Synchronises with the graph's last launch; LGS_ERR_CAPACITY after an
  * overflowing launch, else LGS_OK. */
@@ -206,8 +239,8 @@ lgs_status lgs_graph_counts(lgs_graph *graph, lgs_counts *out);
  * HIP events recorded between them on the launching stream (same results as
  * the one-graph form).  Elapsed milliseconds of the last launch's stages,
  * ms[0..4] = projection + depth sort + scans, pair emission + tile sort,
- * forward compositing, backward compositing (with the fused L1 gradient),
- * gradient reduction + projection backward.  Synchronises. */
+ * forward compositing, backward compositing (with the loss gradient: fused
+ * L1, or the lgs_loss kernel), gradient reduction + projection backward.  Synchronises. */
 lgs_status lgs_graph_stage_ms(lgs_graph *graph, float ms[5]);
 void lgs_graph_destroy(lgs_graph *graph);
 

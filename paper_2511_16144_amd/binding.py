@@ -56,7 +56,8 @@ class lgs_counts(C.Structure):
 
 
 EXPORTS = ["lgs_status_string", "lgs_last_error", "lgs_default_settings", "lgs_context_create",
-           "lgs_context_destroy", "lgs_forward", "lgs_backward", "lgs_backward_l1", "lgs_state_counts", "lgs_state_stage_ms",
+           "lgs_context_destroy", "lgs_forward", "lgs_backward", "lgs_backward_l1", "lgs_loss", "lgs_state_counts",
+           "lgs_state_stage_ms",
            "lgs_state_release", "lgs_graph_create", "lgs_graph_launch", "lgs_graph_status",
            "lgs_graph_counts", "lgs_graph_stage_ms", "lgs_graph_destroy", "lgs_autotune"]
 
@@ -86,6 +87,9 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.lgs_backward_l1.restype = C.c_int
     lib.lgs_backward_l1.argtypes = [P, P, C.POINTER(lgs_gaussians), C.POINTER(lgs_images), C.POINTER(lgs_images),
                                     C.POINTER(C.c_float), C.POINTER(lgs_grads), P]
+    lib.lgs_loss.restype = C.c_int
+    lib.lgs_loss.argtypes = [P, C.c_int32, C.POINTER(lgs_camera), C.POINTER(lgs_images), C.POINTER(lgs_images),
+                             C.POINTER(C.c_float), C.c_float, C.POINTER(lgs_images), P, P]
     lib.lgs_state_counts.restype = C.c_int
     lib.lgs_state_counts.argtypes = [P, C.POINTER(lgs_counts)]
     lib.lgs_state_stage_ms.restype = C.c_int
@@ -95,7 +99,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.lgs_graph_create.restype = C.c_int
     lib.lgs_graph_create.argtypes = [P, C.POINTER(lgs_settings), C.POINTER(lgs_gaussians), C.c_int32,
                                      C.POINTER(lgs_camera), C.POINTER(lgs_images), C.POINTER(C.c_float),
-                                     C.POINTER(lgs_images), C.POINTER(lgs_grads), C.c_int64, P,
+                                     C.c_float, C.POINTER(lgs_images), C.POINTER(lgs_grads), C.c_int64, P,
                                      C.POINTER(P)]
     lib.lgs_graph_launch.restype = C.c_int
     lib.lgs_graph_launch.argtypes = [P, P]
@@ -253,6 +257,27 @@ class Context:
 
     def backward_l1(self, state, params, outs, targets, loss_w, stream=None, grads=None) -> dict:
         return backward_l1(self, state, params, outs, targets, loss_w, stream, grads)
+
+    def loss(self, cams, outs, targets, loss_w, ssim_lambda: float = 0.2, stream=None, grad=None,
+             want_terms: bool = True):
+        """Mapping loss of Eq. (1) with its D-SSIM term and dL/dY (lgs_loss).
+        outs / targets: per-view dicts rgb [3,H,W], depth [H,W], feat [16,H,W]
+        (FP32 CUDA).  Returns (per-view gradient dicts, terms [V, 4] or None:
+        mean|I-I*|, 1 - SSIM, mean|D-D*|, mean|F-F*|)."""
+        V = len(cams)
+        shapes = [(int(c.height), int(c.width)) for c in cams]
+        dev = outs[0]["rgb"].device
+        if grad is None:
+            grad = [{"rgb": torch.empty((3, H, W), device=dev), "depth": torch.empty((H, W), device=dev),
+                     "feat": torch.empty((16, H, W), device=dev)} for (H, W) in shapes]
+        terms = torch.empty((V, 4), device=dev) if want_terms else None
+        cams_c = (lgs_camera * V)(*[camera_c(c) for c in cams])
+        lw = (C.c_float * 3)(*[float(x) for x in loss_w])
+        st = lib().lgs_loss(self._h, V, cams_c, _images_c(outs, shapes, False), _images_c(targets, shapes, False),
+                            lw, float(ssim_lambda), _images_c(grad, shapes, False), _ptr(terms), _stream(stream))
+        if st != LGS_OK:
+            self._raise(st)
+        return grad, terms
 
     def backward(self, state: "State", params, grad_outs, stream=None) -> dict:
         """grad_outs: per view dict rgb [3,H,W], depth [H,W], feat [16,H,W],

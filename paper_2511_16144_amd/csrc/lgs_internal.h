@@ -33,6 +33,29 @@ struct ViewImages {
   int32_t *n_contrib;
 };
 
+// One view of the mapping loss (rendered and observed images, gradient
+// planes, FP32 [C][H][W]) and its scale factors:
+//   s_l1 = w_rgb (1 - lam) / (3HW), s_ssim = w_rgb lam / (3HW),
+//   s_d = w_depth / (HW), s_f = w_feat / (16HW).
+// Colour work-groups of the view: [blk_off, blk_off + n_blk), three per
+// 32 x 32 tile (one per channel); depth + feature work-groups: [df_off,
+// df_off + n_df), one per run of kLossDfPixels pixels; vec4: the depth and
+// feature planes allow 16-byte accesses.
+struct LossView {
+  const float *x, *xt, *d, *dt, *f, *ft;
+  float *gx, *gd, *gf;
+  int32_t W, H, tiles_x, blk_off, n_blk, df_off, n_df, vec4;
+  float s_l1, s_ssim, s_d, s_f;
+};
+constexpr int kLossDfPixels = 2048;
+constexpr int kSsimRadius = 5;   // 11 x 11 SSIM window
+struct LossConsts {
+  float w[2 * kSsimRadius + 1];  // normalised 1-D window weights
+  float c1, c2;
+  int32_t ssim;                  // 0: lam = 0, the SSIM stencil is skipped
+  int32_t n_views;
+};
+
 // Screen-space record of one visible (view, Gaussian), 32 bytes, read by the
 // compositing kernels through scalar loads (wave-uniform).
 //   mx, my : mean' relative to the pixel origin (8 bx0, 8 by0) of its bbox
@@ -144,13 +167,36 @@ void launch_raster_fwd(const Settings& st, const ViewDesc* views, const ViewImag
                        const void* app, int app_bf16, uint32_t npad_mask,
                        const uint32_t* items, const uint32_t* qoff, int64_t n_items, Counters* cnt,
                        int waves_per_group, int32_t* last_idx, float* T_state, hipStream_t s);
-void launch_raster_bwd(const Settings& st, const ViewDesc* views, const ViewImages* upstream,
+// Upstream of the backward compositing kernel: dL/dY given per channel
+// (upstream), the L1 loss gradient formed from the forward's images and the
+// targets (loss_w), or the colour channels given and depth + features from
+// the L1 residual (the D-SSIM loss, whose colour gradient a kernel writes).
+enum UpMode { UP_EXPLICIT = 0, UP_L1 = 1, UP_RGB = 2 };
+// LDS upstream rows per wave: hi rows for the 20 channels plus lo rows for
+// the channels given as FP32 values
+__host__ __device__ constexpr int bwd_upstream_rows(int up_mode) {
+  return up_mode == UP_L1 ? 20 : (up_mode == UP_RGB ? 23 : 40);
+}
+void launch_raster_bwd(int up_mode, const Settings& st, const ViewDesc* views, const ViewImages* upstream,
                        const ViewImages* fwd_out, const ViewImages* targets, const float* loss_w,
                        const uint2* ranges, const uint32_t* vals, const GeomRec* geom,
                        const void* app, int app_bf16, uint32_t npad_mask,
                        const uint32_t* items, const uint32_t* qoff, int64_t n_items, Counters* cnt,
                        int waves_per_group, const int32_t* last_idx, const float* T_state,
                        const uint32_t* slot_base, float* partials, uint8_t* mask, hipStream_t s);
+
+// mapping loss (L1 + D-SSIM) and its gradient: the colour channels (L1 and
+// SSIM stencil), the depth and feature channels (L1), and the per-view terms
+// {mean|I-I*|, 1 - SSIM (0 when ssim = 0), mean|D-D*|, mean|F-F*|} from the
+// work-groups' partial sums
+int64_t loss_blocks(int W, int H);
+int64_t loss_df_blocks(int W, int H);
+int loss_tiles_x(int W);
+void launch_loss_rgb(const LossView* views, const LossConsts& k, int64_t n_blocks, float2* partials,
+                     hipStream_t s);
+void launch_loss_df(const LossView* views, int n_views, int64_t n_blocks, float2* partials, hipStream_t s);
+void launch_loss_terms(const LossView* views, int n_views, int ssim, const float2* part_rgb,
+                       const float2* part_df, float* terms, hipStream_t s);
 
 // gradient reduction and projection backward
 void launch_seg_reduce(const uint32_t* slot_off, const float* partials, const uint8_t* mask,

@@ -367,7 +367,7 @@ __device__ __forceinline__ float transpose_reduce8(const float v[8], int lane) {
 }
 
 // Six waves per SIMD (80 VGPRs; measured fastest for this kernel).
-template <bool BF16, bool FUSED_L1>
+template <bool BF16, int UPM>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))) k_raster_bwd(
     Settings st, const ViewDesc* __restrict__ views, const ViewImages* __restrict__ upstream,
     const ViewImages* __restrict__ fwd_out, const ViewImages* __restrict__ targets,
@@ -380,10 +380,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
     float* __restrict__ partials, uint8_t* __restrict__ mask) {
   const int lane = threadIdx.x & 63;
   extern __shared__ unsigned short lds_z[];
+  // upstream per channel: the sign of the L1 residual (formed here from the
+  // forward's images and the targets; exact in BF16, the per-channel scale is
+  // applied after the product) or a given FP32 value (split hi + lo)
+  constexpr bool kSignRGB = UPM == UP_L1;
+  constexpr bool kSignDF = UPM != UP_EXPLICIT;
   // this wave's LDS rows (BF16, 64 pixels + pad each): the block's upstream
-  // per channel, hi (20) and lo (20; the fused L1 sign needs no lo part), and
-  // the blend weights of up to 8 batched entries, hi (8) and lo (8)
-  constexpr int kGRows = FUSED_L1 ? 20 : 40;
+  // per channel, hi (20) and lo (for the given channels: 20, or the 3 colour
+  // channels), and the blend weights of up to 8 batched entries, hi (8) and
+  // lo (8)
+  constexpr int kGRows = bwd_upstream_rows(UPM);
   unsigned short* lz = lds_z + (threadIdx.x >> 6) * ((kGRows + 16) * kZRow);
   unsigned short* wz = lz + kGRows * kZRow;
   const int grp = lane >> 4, col = lane & 15;
@@ -408,14 +414,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
     if (inside) {
       last = last_idx[(size_t)V->pix_off + p];
       Tfin = T_state[(size_t)V->pix_off + p];
-      if (FUSED_L1) {
+      if (kSignDF) {
         const ViewImages Y = fwd_out[v], Yt = targets[v];
         const float s_rgb = loss_w[0] / (3.f * (float)HW), s_d = loss_w[1] / (float)HW;
         const float s_f = loss_w[2] / (16.f * (float)HW);
+        if (kSignRGB) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const float d = Y.rgb[c * HW + p] - Yt.rgb[c * HW + p];
-          g[c] = d > 0.f ? s_rgb : (d < 0.f ? -s_rgb : 0.f);
+          for (int c = 0; c < 3; ++c) {
+            const float d = Y.rgb[c * HW + p] - Yt.rgb[c * HW + p];
+            g[c] = d > 0.f ? s_rgb : (d < 0.f ? -s_rgb : 0.f);
+          }
+        } else {
+          const float* __restrict__ Urgb = upstream[v].rgb;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) g[c] = Urgb[c * HW + p];
         }
         {
           const float d = Y.depth[p] - Yt.depth[p];
@@ -452,13 +464,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
     // on the two-term splits (hi.hi + lo.hi, + hi.lo for a general upstream),
     // FP32 accumulation.
     float gscale[3] = {1.f, 1.f, 1.f};
-    if (FUSED_L1) {
+    if (kSignDF) {
       const float HWf = (float)HW;
-      gscale[0] = loss_w[0] / (3.f * HWf); gscale[1] = loss_w[1] / HWf; gscale[2] = loss_w[2] / (16.f * HWf);
+      gscale[0] = kSignRGB ? loss_w[0] / (3.f * HWf) : 1.f;
+      gscale[1] = loss_w[1] / HWf;
+      gscale[2] = loss_w[2] / (16.f * HWf);
     }
 #pragma unroll
     for (int c = 0; c < 20; ++c) {
-      if (FUSED_L1) {
+      if (c < 3 ? kSignRGB : kSignDF) {
         const float sgn = g[c] > 0.f ? 1.f : (g[c] < 0.f ? -1.f : 0.f);
         lz[c * kZRow + lane] = bf16_rne(sgn);
       } else {
@@ -485,16 +499,21 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
         c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh0, c0, 0, 0, 0);
         c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh1, c1, 0, 0, 0);
         c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh1, c1, 0, 0, 0);
-        if (!FUSED_L1) {
+        if (UPM == UP_EXPLICIT) {
           const bf16x8_t bl0 = *(const bf16x8_t*)(lz + (20 + col) * kZRow + off);
           bf16x8_t bl1 = *(const bf16x8_t*)(lz + (20 + ch1) * kZRow + off);
           if (col >= 4) bl1 = (bf16x8_t){};
           c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl0, c0, 0, 0, 0);
           c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl1, c1, 0, 0, 0);
+        } else if (UPM == UP_RGB) {
+          // lo rows exist for the three colour channels only
+          bf16x8_t bl0 = *(const bf16x8_t*)(lz + (20 + (col < 3 ? col : 0)) * kZRow + off);
+          if (col >= 3) bl0 = (bf16x8_t){};
+          c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl0, c0, 0, 0, 0);
         }
       }
-      const float s0 = FUSED_L1 ? (col < 3 ? gscale[0] : (col == 3 ? gscale[1] : gscale[2])) : 1.f;
-      const float s1 = FUSED_L1 ? gscale[2] : 1.f;
+      const float s0 = col < 3 ? gscale[0] : (col == 3 ? gscale[1] : gscale[2]);
+      const float s1 = gscale[2];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int e = 4 * grp + i;
@@ -648,7 +667,7 @@ void launch_raster_fwd(const Settings& st, const ViewDesc* views, const ViewImag
                        T_state);
 }
 
-template <bool BF16, bool FUSED>
+template <bool BF16, int UPM>
 static void launch_bwd_t(const Settings& st, const ViewDesc* views, const ViewImages* upstream,
                          const ViewImages* fwd_out, const ViewImages* targets, const float* loss_w,
                          const uint2* ranges, const uint32_t* vals, const GeomRec* geom, const void* app,
@@ -656,22 +675,22 @@ static void launch_bwd_t(const Settings& st, const ViewDesc* views, const ViewIm
                          Counters* cnt, int waves_per_group, const int32_t* last_idx, const float* T_state,
                          const uint32_t* slot_base, float* partials, uint8_t* mask, hipStream_t s) {
   const int threads = 64 * waves_per_group;
-  const size_t lds = (size_t)waves_per_group * ((FUSED ? 20 : 40) + 16) * kZRow * sizeof(unsigned short);
+  const size_t lds = (size_t)waves_per_group * (bwd_upstream_rows(UPM) + 16) * kZRow * sizeof(unsigned short);
   int dev = 0, cus = 256;
   hipGetDevice(&dev);
   hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   int occ = 1;
-  hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_raster_bwd<BF16, FUSED>, threads, lds);
+  hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_raster_bwd<BF16, UPM>, threads, lds);
   int64_t grid = (int64_t)cus * (occ > 0 ? occ : 1);
   const int64_t need = (n_items + waves_per_group - 1) / waves_per_group;
   if (grid > need) grid = need;
   if (grid < kQueues) grid = kQueues;   // every queue needs a workgroup (index mod kQueues) to drain it
-  hipLaunchKernelGGL((k_raster_bwd<BF16, FUSED>), dim3((unsigned)grid), dim3(threads), lds, s, st, views,
+  hipLaunchKernelGGL((k_raster_bwd<BF16, UPM>), dim3((unsigned)grid), dim3(threads), lds, s, st, views,
                      upstream, fwd_out, targets, loss_w, ranges, vals, geom, app, npad_mask, items, qoff,
                      (uint32_t)n_items, cnt, last_idx, T_state, slot_base, partials, mask);
 }
 
-void launch_raster_bwd(const Settings& st, const ViewDesc* views, const ViewImages* upstream,
+void launch_raster_bwd(int up_mode, const Settings& st, const ViewDesc* views, const ViewImages* upstream,
                        const ViewImages* fwd_out, const ViewImages* targets, const float* loss_w,
                        const uint2* ranges, const uint32_t* vals, const GeomRec* geom, const void* app,
                        int app_bf16, uint32_t npad_mask, const uint32_t* items, const uint32_t* qoff,
@@ -679,26 +698,20 @@ void launch_raster_bwd(const Settings& st, const ViewDesc* views, const ViewImag
                        const float* T_state, const uint32_t* slot_base, float* partials, uint8_t* mask,
                        hipStream_t s) {
   if (n_items <= 0) return;
-  const bool fused = targets != nullptr;
+#define LGS_BWD(B, M)                                                                                     \
+  launch_bwd_t<B, M>(st, views, upstream, fwd_out, targets, loss_w, ranges, vals, geom, app, npad_mask,   \
+                     items, qoff, n_items, cnt, waves_per_group, last_idx, T_state, slot_base, partials, \
+                     mask, s)
   if (app_bf16) {
-    if (fused)
-      launch_bwd_t<true, true>(st, views, upstream, fwd_out, targets, loss_w, ranges, vals, geom, app,
-                               npad_mask, items, qoff, n_items, cnt, waves_per_group, last_idx, T_state,
-                               slot_base, partials, mask, s);
-    else
-      launch_bwd_t<true, false>(st, views, upstream, fwd_out, targets, loss_w, ranges, vals, geom, app,
-                                npad_mask, items, qoff, n_items, cnt, waves_per_group, last_idx, T_state,
-                                slot_base, partials, mask, s);
+    if (up_mode == UP_L1) LGS_BWD(true, UP_L1);
+    else if (up_mode == UP_RGB) LGS_BWD(true, UP_RGB);
+    else LGS_BWD(true, UP_EXPLICIT);
   } else {
-    if (fused)
-      launch_bwd_t<false, true>(st, views, upstream, fwd_out, targets, loss_w, ranges, vals, geom, app,
-                                npad_mask, items, qoff, n_items, cnt, waves_per_group, last_idx, T_state,
-                                slot_base, partials, mask, s);
-    else
-      launch_bwd_t<false, false>(st, views, upstream, fwd_out, targets, loss_w, ranges, vals, geom, app,
-                                 npad_mask, items, qoff, n_items, cnt, waves_per_group, last_idx, T_state,
-                                 slot_base, partials, mask, s);
+    if (up_mode == UP_L1) LGS_BWD(false, UP_L1);
+    else if (up_mode == UP_RGB) LGS_BWD(false, UP_RGB);
+    else LGS_BWD(false, UP_EXPLICIT);
   }
+#undef LGS_BWD
 }
 
 void launch_seg_reduce(const uint32_t* slot_off, const float* partials, const uint8_t* mask,

@@ -27,6 +27,15 @@ struct lgs_context {
   std::map<void*, size_t> live;               // ptr -> size
   // items tables per (views signature, tile) cached on the device
   std::map<std::string, std::pair<uint32_t*, int64_t>> items_cache;
+  // lgs_loss workspace: view table (pinned staging + device copy, the copy
+  // marked by an event so that the staging is rewritten only after it), and
+  // the work-groups' partial sums
+  LossView* loss_host = nullptr;
+  LossView* loss_tab = nullptr;
+  int loss_tab_cap = 0;
+  float2* loss_part = nullptr;
+  int64_t loss_part_cap = 0;
+  hipEvent_t loss_copied = nullptr;
 };
 
 namespace {
@@ -224,6 +233,65 @@ Settings dev_settings(const lgs_settings* st, int tile_shift) {
   return s;
 }
 
+// Loss constants: the normalised 1-D SSIM window (sigma 1.5, computed in
+// double, rounded once), C1 = 0.01^2, C2 = 0.03^2 (dynamic range 1).
+LossConsts loss_consts(float ssim_lambda, int n_views) {
+  LossConsts k;
+  double w[2 * kSsimRadius + 1], sum = 0.0;
+  for (int i = -kSsimRadius; i <= kSsimRadius; ++i) sum += (w[i + kSsimRadius] = exp(-(double)(i * i) / 4.5));
+  for (int i = 0; i < 2 * kSsimRadius + 1; ++i) k.w[i] = (float)(w[i] / sum);
+  k.c1 = 1e-4f;
+  k.c2 = 9e-4f;
+  k.ssim = ssim_lambda != 0.f;
+  k.n_views = n_views;
+  return k;
+}
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+// Loss view table; returns the number of colour work-groups and, in *n_df,
+// the number of depth + feature work-groups (their partial sums follow the
+// colour ones).
+int64_t make_loss_views(int32_t n_views, const lgs_camera* cams, const lgs_images* out, const lgs_images* tgt,
+                        const lgs_images* grad, const float loss_w[3], float lam, LossView* dst, int64_t* n_df) {
+  int64_t nb = 0, nd = 0;
+  for (int v = 0; v < n_views; ++v) {
+    LossView L;
+    memset(&L, 0, sizeof L);
+    L.x = out[v].rgb; L.xt = tgt[v].rgb;
+    L.d = out[v].depth; L.dt = tgt[v].depth;
+    L.f = out[v].feat; L.ft = tgt[v].feat;
+    L.gx = grad[v].rgb; L.gd = grad[v].depth; L.gf = grad[v].feat;
+    L.W = cams[v].width; L.H = cams[v].height;
+    L.tiles_x = loss_tiles_x(L.W);
+    L.blk_off = (int32_t)nb;
+    L.n_blk = (int32_t)loss_blocks(L.W, L.H);
+    L.df_off = (int32_t)nd;
+    L.n_df = (int32_t)loss_df_blocks(L.W, L.H);
+    const int64_t hw = (int64_t)L.W * L.H;
+    L.vec4 = hw % 4 == 0 && aligned16(L.d) && aligned16(L.dt) && aligned16(L.f) && aligned16(L.ft) &&
+             aligned16(L.gd) && aligned16(L.gf);
+    const double n = (double)L.W * (double)L.H;
+    L.s_l1 = (float)((double)loss_w[0] * (1.0 - (double)lam) / (3.0 * n));
+    L.s_ssim = (float)((double)loss_w[0] * (double)lam / (3.0 * n));
+    L.s_d = (float)((double)loss_w[1] / n);
+    L.s_f = (float)((double)loss_w[2] / (16.0 * n));
+    dst[v] = L;
+    nb += L.n_blk;
+    nd += L.n_df;
+  }
+  *n_df = nd;
+  return nb;
+}
+
+lgs_status check_loss_args(lgs_context* ctx, const float loss_w[3], float lam) {
+  if (!loss_w) return fail(ctx, LGS_ERR_INVALID_ARG, "loss_w is NULL");
+  for (int i = 0; i < 3; ++i)
+    if (!isfinite(loss_w[i])) return fail(ctx, LGS_ERR_INVALID_ARG, "non-finite loss weight");
+  if (!(lam >= 0.f && lam <= 1.f)) return fail(ctx, LGS_ERR_INVALID_ARG, "ssim_lambda must be in [0, 1]");
+  return LGS_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -261,6 +329,13 @@ struct Work {
   float* grad2d = nullptr;
   void* ttmp = nullptr;
   bool bwd_alloc = false;
+  // graph with the D-SSIM loss: upstream planes [20][H][W] per view, the
+  // loss view table and partial sums
+  float* up_buf = nullptr;
+  LossView* loss_tab = nullptr;
+  float2* loss_part = nullptr;
+  int64_t loss_blocks = 0;
+  LossConsts loss_k{};
   // settings.profile: events on the caller's stream around each stage
   // (0 forward start, 1 front end, 2 pairs start, 3 raster start, 4 raster
   // end, 5 backward raster start, 6 backward raster end, 7 backward end)
@@ -444,15 +519,17 @@ void enqueue_raster_fwd(Work* W, hipStream_t s) {
                     W->last_idx, W->T_state, s);
 }
 
-// fused: upstream = dL1/dY from (d_out, d_tgt, d_lossw); else from d_up
-void enqueue_backward_raster(Work* W, bool fused, hipStream_t s) {
+// upstream by mode (UpMode): d_up; dL1/dY from (d_out, d_tgt, d_lossw); or
+// colour channels from d_up and depth + features from the L1 residual
+void enqueue_backward_raster(Work* W, int mode, hipStream_t s) {
+  const bool sign = mode != UP_EXPLICIT;
   const Settings ds = dev_settings(&W->st, W->plan.tile_shift);
   launch_fill_u8(W->mask, 0, &W->counters->n_slots_eff, std::max<int64_t>(W->cap_slots, 1), s);
   launch_fill_u32(W->counters->work_qb, 0u, kQueues * kLineWords, s);
   launch_fill_u32((uint32_t*)&W->counters->bwd_evals, 0u, 4, s);   // bwd_evals, bwd_contrib
   w_mark(W, 5, s);
-  launch_raster_bwd(ds, W->d_views, W->d_up, fused ? W->d_out : nullptr, fused ? W->d_tgt : nullptr,
-                    fused ? W->d_lossw : nullptr, W->ranges, W->pvals, W->geom, W->app, W->app_bf16,
+  launch_raster_bwd(mode, ds, W->d_views, W->d_up, sign ? W->d_out : nullptr, sign ? W->d_tgt : nullptr,
+                    sign ? W->d_lossw : nullptr, W->ranges, W->pvals, W->geom, W->app, W->app_bf16,
                     (uint32_t)((1ull << W->npad_shift) - 1), W->items, W->items_static + W->plan.n_items,
                     W->plan.n_items, W->counters, W->st.chunk,
                     W->last_idx, W->T_state, W->slot_base, W->partials, W->mask, s);
@@ -469,8 +546,8 @@ void enqueue_backward_reduce(Work* W, const lgs_gaussians* g, const lgs_grads* g
   w_mark(W, 7, s);
 }
 
-void enqueue_backward(Work* W, const lgs_gaussians* g, const lgs_grads* gr, bool fused, hipStream_t s) {
-  enqueue_backward_raster(W, fused, s);
+void enqueue_backward(Work* W, const lgs_gaussians* g, const lgs_grads* gr, int mode, hipStream_t s) {
+  enqueue_backward_raster(W, mode, s);
   enqueue_backward_reduce(W, g, gr, s);
 }
 
@@ -569,6 +646,10 @@ void lgs_context_destroy(lgs_context* ctx) {
   for (auto& kv : ctx->free_blocks) hipFree(kv.second);
   for (auto& kv : ctx->live) hipFree(kv.first);
   for (auto& kv : ctx->items_cache) hipFree(kv.second.first);
+  if (ctx->loss_host) hipHostFree(ctx->loss_host);
+  if (ctx->loss_tab) hipFree(ctx->loss_tab);
+  if (ctx->loss_part) hipFree(ctx->loss_part);
+  if (ctx->loss_copied) hipEventDestroy(ctx->loss_copied);
   delete ctx;
 }
 
@@ -669,7 +750,7 @@ lgs_status lgs_backward(lgs_context* ctx, const lgs_fwd_state* Sc, const lgs_gau
   for (int v = 0; v < V; ++v)
     hup[v] = ViewImages{grad_out[v].rgb, grad_out[v].depth, grad_out[v].feat, grad_out[v].final_T, nullptr};
   HIP_TRY(ctx, hipMemcpyAsync(W->d_up, hup.data(), sizeof(ViewImages) * V, hipMemcpyHostToDevice, stream));
-  enqueue_backward(W, g, grads, false, stream);
+  enqueue_backward(W, g, grads, UP_EXPLICIT, stream);
   HIP_TRY(ctx, hipGetLastError());
   Counters hc;   // synchronises: hup goes out of scope
   return read_counts(W, stream, &hc);
@@ -704,10 +785,64 @@ lgs_status lgs_backward_l1(lgs_context* ctx, const lgs_fwd_state* Sc, const lgs_
   HIP_TRY(ctx, hipMemcpyAsync(W->d_out, ho.data(), sizeof(ViewImages) * V, hipMemcpyHostToDevice, stream));
   HIP_TRY(ctx, hipMemcpyAsync(W->d_tgt, ht.data(), sizeof(ViewImages) * V, hipMemcpyHostToDevice, stream));
   HIP_TRY(ctx, hipMemcpyAsync(W->d_lossw, lw, sizeof lw, hipMemcpyHostToDevice, stream));
-  enqueue_backward(W, g, grads, true, stream);
+  enqueue_backward(W, g, grads, UP_L1, stream);
   HIP_TRY(ctx, hipGetLastError());
   Counters hc;   // synchronises: the host arrays go out of scope
   return read_counts(W, stream, &hc);
+}
+
+lgs_status lgs_loss(lgs_context* ctx, int32_t n_views, const lgs_camera* cams, const lgs_images* out,
+                    const lgs_images* targets, const float loss_w[3], float ssim_lambda, const lgs_images* grad,
+                    float* terms, hipStream_t stream) {
+  if (!ctx) return LGS_ERR_INVALID_ARG;
+  ctx->err.clear();
+  lgs_status rc;
+  if ((rc = check_cams(ctx, n_views, cams)) != LGS_OK) return rc;
+  if ((rc = check_images(ctx, n_views, out, false, "out")) != LGS_OK) return rc;
+  if ((rc = check_images(ctx, n_views, targets, false, "targets")) != LGS_OK) return rc;
+  if ((rc = check_images(ctx, n_views, grad, false, "grad")) != LGS_OK) return rc;
+  if ((rc = check_loss_args(ctx, loss_w, ssim_lambda)) != LGS_OK) return rc;
+  if (terms && !aligned4(terms)) return fail(ctx, LGS_ERR_INVALID_ARG, "misaligned terms");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  (void)hipGetLastError();   // launch checks below see only this call's errors
+  if (!ctx->loss_copied) HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->loss_copied, hipEventDisableTiming));
+  HIP_TRY(ctx, hipEventSynchronize(ctx->loss_copied));   // the staging's previous copy is done
+  int64_t nb = 0, nd = 0;
+  for (int v = 0; v < n_views; ++v) {
+    nb += loss_blocks(cams[v].width, cams[v].height);
+    nd += loss_df_blocks(cams[v].width, cams[v].height);
+  }
+  const int64_t np = nb + nd;
+  if (n_views > ctx->loss_tab_cap || np > ctx->loss_part_cap) {
+    HIP_TRY(ctx, hipDeviceSynchronize());   // earlier calls may still read the old buffers
+    if (n_views > ctx->loss_tab_cap) {
+      if (ctx->loss_host) hipHostFree(ctx->loss_host);
+      if (ctx->loss_tab) hipFree(ctx->loss_tab);
+      ctx->loss_host = nullptr;
+      ctx->loss_tab = nullptr;
+      ctx->loss_tab_cap = 0;
+      HIP_TRY(ctx, hipHostMalloc((void**)&ctx->loss_host, sizeof(LossView) * n_views, hipHostMallocDefault));
+      HIP_TRY(ctx, hipMalloc((void**)&ctx->loss_tab, sizeof(LossView) * n_views));
+      ctx->loss_tab_cap = n_views;
+    }
+    if (np > ctx->loss_part_cap) {
+      if (ctx->loss_part) hipFree(ctx->loss_part);
+      ctx->loss_part = nullptr;
+      ctx->loss_part_cap = 0;
+      HIP_TRY(ctx, hipMalloc((void**)&ctx->loss_part, sizeof(float2) * np));
+      ctx->loss_part_cap = np;
+    }
+  }
+  make_loss_views(n_views, cams, out, targets, grad, loss_w, ssim_lambda, ctx->loss_host, &nd);
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->loss_tab, ctx->loss_host, sizeof(LossView) * n_views, hipMemcpyHostToDevice,
+                              stream));
+  HIP_TRY(ctx, hipEventRecord(ctx->loss_copied, stream));
+  const LossConsts k = loss_consts(ssim_lambda, n_views);
+  launch_loss_rgb(ctx->loss_tab, k, nb, ctx->loss_part, stream);
+  launch_loss_df(ctx->loss_tab, n_views, nd, ctx->loss_part + nb, stream);
+  if (terms) launch_loss_terms(ctx->loss_tab, n_views, k.ssim, ctx->loss_part, ctx->loss_part + nb, terms, stream);
+  HIP_TRY(ctx, hipGetLastError());
+  return LGS_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -715,8 +850,8 @@ lgs_status lgs_backward_l1(lgs_context* ctx, const lgs_fwd_state* Sc, const lgs_
 // ---------------------------------------------------------------------------
 lgs_status lgs_graph_create(lgs_context* ctx, const lgs_settings* st, const lgs_gaussians* g, int32_t n_views,
                             const lgs_camera* cams, const lgs_images* targets, const float loss_w[3],
-                            const lgs_images* out, const lgs_grads* grads, int64_t pair_capacity,
-                            hipStream_t stream, lgs_graph** graph_out) {
+                            float ssim_lambda, const lgs_images* out, const lgs_grads* grads,
+                            int64_t pair_capacity, hipStream_t stream, lgs_graph** graph_out) {
   if (!ctx) return LGS_ERR_INVALID_ARG;
   ctx->err.clear();
   if (!graph_out) return fail(ctx, LGS_ERR_INVALID_ARG, "graph_out is NULL");
@@ -727,7 +862,7 @@ lgs_status lgs_graph_create(lgs_context* ctx, const lgs_settings* st, const lgs_
   if ((rc = check_cams(ctx, n_views, cams)) != LGS_OK) return rc;
   if ((rc = check_images(ctx, n_views, out, true, "out")) != LGS_OK) return rc;
   if ((rc = check_images(ctx, n_views, targets, false, "targets")) != LGS_OK) return rc;
-  if (!loss_w) return fail(ctx, LGS_ERR_INVALID_ARG, "loss_w is NULL");
+  if ((rc = check_loss_args(ctx, loss_w, ssim_lambda)) != LGS_OK) return rc;
   if ((rc = check_grads(ctx, g, grads)) != LGS_OK) return rc;
   if (pair_capacity < 0) return fail(ctx, LGS_ERR_INVALID_ARG, "pair_capacity < 0");
   if (!kGraphEnabled) return fail(ctx, LGS_ERR_UNSUPPORTED, "graph mode is switched off in this build");
@@ -780,6 +915,31 @@ lgs_status lgs_graph_create(lgs_context* ctx, const lgs_settings* st, const lgs_
         hipMemcpy(W->d_lossw, lw, sizeof lw, hipMemcpyHostToDevice) != hipSuccess)
       return bail(fail(ctx, LGS_ERR_HIP, "upload failed"));
   }
+  if (ssim_lambda != 0.f) {
+    // the loss kernel writes the colour part of dL/dY (L1 + D-SSIM) into
+    // graph-owned planes [3][H][W] per view; the backward reads them and
+    // forms the depth and feature L1 gradients itself
+    bool ok = true;
+    W->up_buf = (float*)w_alloc(W, sizeof(float) * 3 * std::max<int64_t>(W->plan.n_pix, 1), ok);
+    W->loss_tab = (LossView*)w_alloc(W, sizeof(LossView) * n_views, ok);
+    std::vector<lgs_images> gi(n_views);
+    std::vector<ViewImages> hu(n_views);
+    for (int v = 0; v < n_views; ++v) {
+      float* base = W->up_buf + 3 * (int64_t)W->plan.views[v].pix_off;
+      gi[v] = lgs_images{base, nullptr, nullptr, nullptr, nullptr};
+      hu[v] = ViewImages{base, nullptr, nullptr, nullptr, nullptr};
+    }
+    std::vector<LossView> lv(n_views);
+    int64_t n_df = 0;
+    W->loss_blocks = make_loss_views(n_views, cams, out, targets, gi.data(), loss_w, ssim_lambda, lv.data(),
+                                     &n_df);
+    W->loss_part = (float2*)w_alloc(W, sizeof(float2) * std::max<int64_t>(W->loss_blocks, 1), ok);
+    W->loss_k = loss_consts(ssim_lambda, n_views);
+    if (!ok) return bail(fail(ctx, LGS_ERR_HIP, "device allocation failed (loss)"));
+    if (hipMemcpy(W->loss_tab, lv.data(), sizeof(LossView) * n_views, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(W->d_up, hu.data(), sizeof(ViewImages) * n_views, hipMemcpyHostToDevice) != hipSuccess)
+      return bail(fail(ctx, LGS_ERR_HIP, "upload failed"));
+  }
   if (hipStreamCreateWithFlags(&G->cap_stream, hipStreamNonBlocking) != hipSuccess)
     return bail(fail(ctx, LGS_ERR_HIP, "stream creation failed"));
   if (st->profile)
@@ -791,7 +951,16 @@ lgs_status lgs_graph_create(lgs_context* ctx, const lgs_settings* st, const lgs_
       case 0: enqueue_front(W, &G->g, G->cap_stream); break;
       case 1: enqueue_pairs(W, G->cap_stream); break;
       case 2: enqueue_raster_fwd(W, G->cap_stream); break;
-      case 3: enqueue_backward_raster(W, true, G->cap_stream); break;
+      case 3:
+        if (W->loss_tab) {
+          // the colour gradient (L1 + D-SSIM) into up_buf; depth and feature
+          // L1 gradients are formed inside the backward
+          launch_loss_rgb(W->loss_tab, W->loss_k, W->loss_blocks, W->loss_part, G->cap_stream);
+          enqueue_backward_raster(W, UP_RGB, G->cap_stream);
+        } else {
+          enqueue_backward_raster(W, UP_L1, G->cap_stream);
+        }
+        break;
       default: enqueue_backward_reduce(W, &G->g, &G->grads, G->cap_stream); break;
     }
   };

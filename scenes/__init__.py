@@ -309,3 +309,32 @@ def crop_windows(seed: int, cam: Camera, k: int = 4, size: int = 64) -> list:
         if ok:
             wins.append((x0, y0, min(size, cam.width), min(size, cam.height)))
     return wins
+
+
+def loss_images(seed: int, sizes, noise: float = 0.1, independent: bool = False):
+    """Rendered-like images and targets for the loss alone, per view (W, H):
+    targets drawn like the workloads' (RGB U[0,1], depth U[0.5, 6], unit
+    16-d features); images = target + N(0, noise) noise (RGB clipped to
+    [0, 1]; depth and features with 0.3), or independent draws.  About 1 in
+    500 elements of each image equals its target exactly (sign(0) cases).
+    Returns (list of dicts rgb/depth/feat float32, list of Targets)."""
+    rng = np.random.Generator(np.random.PCG64(11000 + seed))
+    outs, tgts = [], []
+    for (W, H) in sizes:
+        t = _draw_targets(rng, Camera(W, H, 1.0, 1.0, 0.0, 0.0, np.eye(3, dtype=np.float32),
+                                      np.zeros(3, np.float32)), (0.5, 6.0))
+        if independent:
+            o = {"rgb": rng.uniform(0.0, 1.0, size=t.rgb.shape),
+                 "depth": rng.uniform(0.5, 6.0, size=t.depth.shape),
+                 "feat": rng.normal(0.0, 1.0, size=t.feat.shape)}
+        else:
+            o = {"rgb": np.clip(t.rgb + rng.normal(0.0, noise, size=t.rgb.shape), 0.0, 1.0),
+                 "depth": t.depth + rng.normal(0.0, 0.3, size=t.depth.shape),
+                 "feat": t.feat + rng.normal(0.0, 0.3, size=t.feat.shape)}
+        for k in o:
+            o[k] = o[k].astype(np.float32)
+            eq = rng.uniform(size=o[k].shape) < 0.002
+            o[k][eq] = getattr(t, k)[eq]
+        outs.append(o)
+        tgts.append(t)
+    return outs, tgts

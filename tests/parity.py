@@ -127,3 +127,31 @@ def upstream_tensors(ups, device="cuda"):
 
 def fmt(res):
     return ", ".join(f"{k}: L2 {v[0]:.2e} max {v[1]:.2e}" for k, v in res.items())
+
+
+def separate_targets(ref_outs, targets, delta=1e-4):
+    """Targets moved at least `delta` away from the oracle's rendered values
+    wherever they come closer (the kink of the L1 terms), so that every
+    residual has the same sign in the FP32 render and the FP64 one outside
+    ambiguous pixels.  Built from the oracle's images only."""
+    from scenes import Targets
+    out = []
+    for o, t in zip(ref_outs, targets):
+        d = {}
+        for k in ("rgb", "depth", "feat"):
+            r = np.asarray(o[k], np.float64)
+            v = np.asarray(getattr(t, k), np.float64).copy()
+            close = np.abs(v - r) < delta
+            v[close] = r[close] + np.where(v[close] >= r[close], 2 * delta, -2 * delta)
+            d[k] = v.astype(np.float32)
+        out.append(Targets(d["rgb"], d["depth"], d["feat"]))
+    return out
+
+
+def dilate(mask, r):
+    """Pixels within r (Chebyshev distance) of a set pixel: the reach of a
+    (2r+1)-wide window."""
+    from scipy import ndimage
+    if not mask.any():
+        return mask.copy()
+    return ndimage.binary_dilation(mask, structure=np.ones((2 * r + 1, 2 * r + 1), bool))

@@ -40,14 +40,14 @@ def _kernels(asm, pattern):
 def test_persistent_compositing_loops_are_wave_uniform(tmp_path):
     asm = _asm("raster.hip", tmp_path)
     ks = _kernels(asm, "k_raster_(?:fwd|bwd)")
-    assert len(ks) == 6           # fwd x {f32, bf16}, bwd x {f32, bf16} x {upstream, fused L1}
+    assert len(ks) == 8           # fwd x {f32, bf16}, bwd x {f32, bf16} x {upstream, fused L1, colour given}
     for name, lines in ks.items():
         bad = [l for l in lines if l.startswith("s_andn2_b64 exec, exec")]
         assert not bad, (name, bad)
 
 
 @pytest.mark.skipif(not os.path.exists(HIPCC), reason="hipcc not available")
-@pytest.mark.parametrize("src", ["raster.hip", "binning.hip", "radix_sort.hip", "project.hip"])
+@pytest.mark.parametrize("src", ["raster.hip", "binning.hip", "radix_sort.hip", "project.hip", "loss.hip"])
 def test_no_scalar_memory_writes(src, tmp_path):
     asm = _asm(src, tmp_path)
     bad = re.findall(r"^\s+(s_(?:store|buffer_store|atomic|buffer_atomic|dcache_wb|dcache_discard|scratch_store)\w*)",
