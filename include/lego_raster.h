@@ -4,7 +4,7 @@
  *
  * What it computes.  LEGO-SLAM (arXiv 2511.16144) renders its
  * language-embedded Gaussians Theta = {p, q, s, alpha, c, f in R^16}
- * "following the standard 3DGS pipeline" into an RGB image and a feature map
+ * with the usual 3D Gaussian Splatting rasterizer into an RGB image and a feature map
  * (Sec. III-B.1), uses the rendered depth in the L1 depth term of its mapping
  * loss (Sec. III-B.3, Eq. (1)), optimises Theta through the renderer over
  * several iterations per keyframe (Sec. III-B.3) and refines keyframe poses by

@@ -7,7 +7,7 @@ It shares no code with the HIP path; the two meet only through the seeded
 input generators in ``scenes/``.
 
 What it computes (paper: Sec. III-B.1 renders the Gaussians
-Theta = {p, q, s, alpha, c, f} "following the standard 3DGS pipeline" into an
+Theta = {p, q, s, alpha, c, f} with the usual 3DGS rasterizer into an
 RGB image and a feature map; Sec. III-B.3, Eq. (1) adds the rendered depth
 used by the L1 depth loss and optimises Theta through the renderer):
 

@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 A second, deliberately different transcription of the same definition as
-``raster_fp64`` (Sec. III-B.1, "standard 3DGS pipeline"; Eq. (1) for depth),
+``raster_fp64`` (Sec. III-B.1, the 3DGS rasterizer; Eq. (1) for depth),
 for tiny scenes (a few Gaussians, a few hundred pixels):
 
   * the rotation of a unit quaternion (w, v) is built as

@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY (see the package docstring): the product never
 imports this file.
 
-Definition followed (per pixel; Sec. III-B.1 "standard 3DGS pipeline",
+Definition followed (per pixel; Sec. III-B.1, the 3DGS rasterizer it builds on,
 Sec. III-B.3 Eq. (1) for the depth channel and the loss).  Readings where the
 paper is silent are marked [reading]:
 

@@ -39,11 +39,13 @@ constexpr int kPA = kLA + 1;        // odd row pitches: column walks across
 constexpr int kPB = kLB + 1;        // lanes hit distinct LDS banks
 constexpr int kPC = kLT + 1;
 constexpr int kLossThreads = 256;
-// LDS region 0: X, Y (2 x 52 x 53), later the coefficient maps (3 x 42 x 43);
-// region 1: the five horizontal sums (5 x 52 x 43), later the three
-// horizontal coefficient sums (3 x 42 x 33)
-constexpr int kReg0 = (2 * kLA * kPA > 3 * kLB * kPB) ? 2 * kLA * kPA : 3 * kLB * kPB;
-constexpr int kReg1 = (5 * kLA * kPB > 3 * kLB * kPC) ? 5 * kLA * kPB : 3 * kLB * kPC;
+// One LDS region, reused stage by stage (a barrier between a stage's last
+// read of one array and the first write of the next): X, Y (2 x 52 x 53);
+// the five horizontal sums (5 x 52 x 43); the coefficient maps (3 x 42 x 43)
+// followed by their horizontal sums (3 x 42 x 33).  44.7 KB: three
+// work-groups per CU.
+constexpr int kMax2(int a, int b) { return a > b ? a : b; }
+constexpr int kLdsFloats = kMax2(kMax2(2 * kLA * kPA, 5 * kLA * kPB), 3 * kLB * kPB + 3 * kLB * kPC);
 
 static_assert(kLT * kLT == 1024, "tile pixel index uses 10 bits");
 static_assert(kLossDfPixels == 256 * 8, "depth/feature kernel: 8 pixels per thread");
@@ -69,8 +71,7 @@ __device__ __forceinline__ void block_sum2(float& a, float& b, float* red) {
 
 __global__ __launch_bounds__(kLossThreads) void k_loss_rgb(const LossView* __restrict__ views, LossConsts k,
                                                            float2* __restrict__ partials) {
-  __shared__ float lds0[kReg0];
-  __shared__ float lds1[kReg1];
+  __shared__ float lds[kLdsFloats];
   __shared__ float red[8];
   const int b = blockIdx.x, t = threadIdx.x;
   int v = 0;
@@ -97,8 +98,8 @@ __global__ __launch_bounds__(kLossThreads) void k_loss_rgb(const LossView* __res
       }
     } else {
       // (A) X, Y over the tile plus 2 radii (zeros outside the image)
-      float* sx = lds0;
-      float* sy = lds0 + kLA * kPA;
+      float* sx = lds;
+      float* sy = lds + kLA * kPA;
       for (int e = t; e < kLA * kLA; e += kLossThreads) {
         const int r = e / kLA, q = e - r * kLA;
         const int gy = y0 - 2 * kLR + r, gx = x0 - 2 * kLR + q;
@@ -113,107 +114,115 @@ __global__ __launch_bounds__(kLossThreads) void k_loss_rgb(const LossView* __res
       }
       __syncthreads();
       // (B) horizontal window sums of X, Y, X^2, Y^2, XY: 52 rows x 42
-      // statistics columns; thread = (row, segment of 11 columns)
-      float* h5 = lds1;
+      // statistics columns; thread = (row, segment of 11 columns), walking
+      // its 21 inputs once (the three products per input, then 5 FMAs per
+      // tap); results stay in registers until every thread has read X, Y
+      float hb[11][5];
+      const int rb = t % kLA, segb = t / kLA;
+      const int jb0 = min(segb * 11, kLB - 11);   // the last segment overlaps
       if (t < 4 * kLA) {
-        const int r = t % kLA, seg = t / kLA;
-        const int j0 = min(seg * 11, kLB - 11);   // the last segment overlaps
-        float xv[21], yv[21];
 #pragma unroll
-        for (int i = 0; i < 21; ++i) {
-          xv[i] = sx[r * kPA + j0 + i];
-          yv[i] = sy[r * kPA + j0 + i];
-        }
+        for (int o = 0; o < 11; ++o)
 #pragma unroll
-        for (int o = 0; o < 11; ++o) {
-          float m1 = 0.f, m2 = 0.f, s11 = 0.f, s22 = 0.f, s12 = 0.f;
+          for (int q = 0; q < 5; ++q) hb[o][q] = 0.f;
 #pragma unroll
-          for (int i = 0; i < kLTaps; ++i) {
-            const float a = xv[o + i], c = yv[o + i];
-            const float wa = k.w[i] * a, wc = k.w[i] * c;
-            m1 += wa;
-            m2 += wc;
-            s11 = fmaf(wa, a, s11);
-            s22 = fmaf(wc, c, s22);
-            s12 = fmaf(wa, c, s12);
+        for (int m = 0; m < 21; ++m) {
+          const float a = sx[rb * kPA + jb0 + m], c = sy[rb * kPA + jb0 + m];
+          const float pv[5] = {a, c, a * a, c * c, a * c};
+#pragma unroll
+          for (int o = 0; o < 11; ++o) {
+            const int tap = m - o;
+            if (tap >= 0 && tap < kLTaps) {
+#pragma unroll
+              for (int q = 0; q < 5; ++q) hb[o][q] = fmaf(k.w[tap], pv[q], hb[o][q]);
+            }
           }
-          const int j = j0 + o;
-          h5[(0 * kLA + r) * kPB + j] = m1;
-          h5[(1 * kLA + r) * kPB + j] = m2;
-          h5[(2 * kLA + r) * kPB + j] = s11;
-          h5[(3 * kLA + r) * kPB + j] = s22;
-          h5[(4 * kLA + r) * kPB + j] = s12;
         }
+      }
+      __syncthreads();   // X, Y are dead: the sums take their place
+      float* h5 = lds;
+      if (t < 4 * kLA) {
+#pragma unroll
+        for (int o = 0; o < 11; ++o)
+#pragma unroll
+          for (int q = 0; q < 5; ++q) h5[(q * kLA + rb) * kPB + jb0 + o] = hb[o][q];
       }
       __syncthreads();
       // (C) vertical sums -> local statistics over the 42 x 42 statistics
-      // region; SSIM and its three coefficient maps (zero outside the image)
-      float* cf = lds0;
+      // region; SSIM and its three coefficient maps (zero outside the image),
+      // written over the sums once every thread has read them
+      float st5[7][5];
+      const int jc = t % kLB, segc = t / kLB;
+      const int ic0 = segc * 7;
       if (t < 6 * kLB) {
-        const int j = t % kLB, seg = t / kLB;
-        const int i0 = seg * 7;
-        float acc[7][5];
 #pragma unroll
         for (int o = 0; o < 7; ++o)
 #pragma unroll
-          for (int q = 0; q < 5; ++q) acc[o][q] = 0.f;
+          for (int q = 0; q < 5; ++q) st5[o][q] = 0.f;
 #pragma unroll
         for (int ii = 0; ii < 17; ++ii) {
           float val[5];
 #pragma unroll
-          for (int q = 0; q < 5; ++q) val[q] = h5[(q * kLA + i0 + ii) * kPB + j];
+          for (int q = 0; q < 5; ++q) val[q] = h5[(q * kLA + ic0 + ii) * kPB + jc];
 #pragma unroll
           for (int o = 0; o < 7; ++o) {
             const int tap = ii - o;
             if (tap >= 0 && tap < kLTaps) {
 #pragma unroll
-              for (int q = 0; q < 5; ++q) acc[o][q] = fmaf(k.w[tap], val[q], acc[o][q]);
+              for (int q = 0; q < 5; ++q) st5[o][q] = fmaf(k.w[tap], val[q], st5[o][q]);
             }
           }
         }
-        const int gx = x0 - kLR + j;
-        const bool jin = j >= kLR && j < kLR + kLT;
+      }
+      __syncthreads();
+      float* cf = lds;
+      if (t < 6 * kLB) {
+        const int gx = x0 - kLR + jc;
+        const bool jin = jc >= kLR && jc < kLR + kLT;
 #pragma unroll
         for (int o = 0; o < 7; ++o) {
-          const int i = i0 + o, gy = y0 - kLR + i;
+          const int i = ic0 + o, gy = y0 - kLR + i;
           float ca = 0.f, cb = 0.f, cc = 0.f;
           if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
-            const float mx = acc[o][0], my = acc[o][1];
-            const float vx = acc[o][2] - mx * mx, vy = acc[o][3] - my * my, cxy = acc[o][4] - mx * my;
+            const float mx = st5[o][0], my = st5[o][1];
+            const float vx = st5[o][2] - mx * mx, vy = st5[o][3] - my * my, cxy = st5[o][4] - mx * my;
             const float A1 = 2.f * mx * my + k.c1, A2 = 2.f * cxy + k.c2;
             const float B1 = mx * mx + my * my + k.c1, B2 = vx + vy + k.c2;
-            const float rB1 = 1.f / B1, rB2 = 1.f / B2, iB = rB1 * rB2;
+            // B1 >= C1 and B2 >= C2 (up to rounding of the variances): normal
+            // positive numbers, for which the hardware reciprocal is within 1 ulp
+            const float rB1 = __builtin_amdgcn_rcpf(B1), rB2 = __builtin_amdgcn_rcpf(B2), iB = rB1 * rB2;
             const float S = A1 * A2 * iB;
             ca = 2.f * my * (A2 - A1) * iB + 2.f * mx * S * (rB2 - rB1);   // dS/dm_x
             cb = -S * rB2;                                                  // dS/ds_xx
             cc = 2.f * A1 * iB;                                             // dS/ds_xy
             if (jin && i >= kLR && i < kLR + kLT) acc1 += S;
           }
-          cf[(0 * kLB + i) * kPB + j] = ca;
-          cf[(1 * kLB + i) * kPB + j] = cb;
-          cf[(2 * kLB + i) * kPB + j] = cc;
+          cf[(0 * kLB + i) * kPB + jc] = ca;
+          cf[(1 * kLB + i) * kPB + jc] = cb;
+          cf[(2 * kLB + i) * kPB + jc] = cc;
         }
       }
       __syncthreads();
       // (D) horizontal sums of the coefficient maps: 42 rows x 32 columns;
-      // thread = (row, segment of 8 columns)
-      float* h3 = lds1;
-      if (t < 4 * kLB) {
+      // thread = (row, segment of 6 columns; the last overlaps), into the
+      // space after the coefficient maps
+      float* h3 = lds + 3 * kLB * kPB;
+      if (t < 6 * kLB) {
         const int i = t % kLB, seg = t / kLB;
-        const int j0 = seg * 8;
-        float cv[3][18];
+        const int j0 = min(seg * 6, kLT - 6);
+        float cv[3][16];
 #pragma unroll
         for (int q = 0; q < 3; ++q)
 #pragma unroll
-          for (int m = 0; m < 18; ++m) cv[q][m] = cf[(q * kLB + i) * kPB + j0 + m];
+          for (int m = 0; m < 16; ++m) cv[q][m] = cf[(q * kLB + i) * kPB + j0 + m];
 #pragma unroll
-        for (int o = 0; o < 8; ++o)
+        for (int o = 0; o < 6; ++o)
 #pragma unroll
           for (int q = 0; q < 3; ++q) {
-            float s = 0.f;
+            float sum = 0.f;
 #pragma unroll
-            for (int m = 0; m < kLTaps; ++m) s = fmaf(k.w[m], cv[q][o + m], s);
-            h3[(q * kLB + i) * kPC + j0 + o] = s;
+            for (int m = 0; m < kLTaps; ++m) sum = fmaf(k.w[m], cv[q][o + m], sum);
+            h3[(q * kLB + i) * kPC + j0 + o] = sum;
           }
       }
       __syncthreads();

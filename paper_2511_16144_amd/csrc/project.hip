@@ -1,9 +1,9 @@
 // Per-Gaussian stages: projection (forward) and its exact backward.
 //
 // Forward (Sec. III-B.1: the Gaussians Theta = {p, q, s, alpha, c, f} are
-// rendered "following the standard 3DGS pipeline"): activation, view
+// rendered with the usual 3D Gaussian Splatting rasterizer): activation, view
 // transform, EWA screen covariance and conic, the cut-off box in 8x8 pixel
-// blocks and in binning tiles, the 48-bit depth key, and the packed
+// blocks and in binning tiles, the 32-bit depth key, and the packed
 // appearance record.  Backward: the chain rule from the per-Gaussian
 // screen-space gradient (mean', conic, opacity, rgb, depth, feature) to
 // (p, log s, q, logit, c, f) and to the pose twist of Sec. III-B.2.

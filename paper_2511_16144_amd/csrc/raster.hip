@@ -2,8 +2,8 @@
 // reverse-order backward, plus the per-Gaussian segmented reduction of the
 // backward's partial sums.
 //
-// Paper: Sec. III-B.1 renders the image and the feature map "following the
-// standard 3DGS pipeline"; Eq. (1) uses the rendered depth; Sec. III-B.3
+// Paper: Sec. III-B.1 renders the image and the feature map with the usual
+// 3D Gaussian Splatting rasterizer; Eq. (1) uses the rendered depth; Sec. III-B.3
 // optimises the Gaussians through this renderer.  Per pixel, front to back
 // over the Gaussians of its tile in (depth, index) order:
 //   alpha = min(alpha_max, o exp(-m2/2)), skipped unless m2 <= cutoff2 and
