@@ -18,7 +18,9 @@ used by the L1 depth loss and optimises Theta through the renderer):
     through central finite differences, its autodiff gradient;
   * ``loss_fp64``    -- the mapping loss of Eq. (1) downstream of the
     renderer, with its D-SSIM term (Gaussian-window SSIM, zero padding), and
-    its gradient with respect to the rendered images by torch.autograd.
+    its gradient with respect to the rendered images by torch.autograd;
+  * ``decoder_fp64`` -- the feature-distillation loss of Eq. (2) through a
+    1x1-convolution decoder, with its gradients (feature map, weights, bias).
 
 The paper gives no rasterizer formulas; the readings taken where it is silent
 (colour model, depth definition, cut-offs, termination, pose perturbation...)
