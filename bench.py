@@ -258,6 +258,42 @@ def time_loss(ctx, wl, dev, settings, lam, reps=50, warmup=5):
     return ts[len(ts) // 2], terms.cpu().numpy()
 
 
+# Algorithmic HBM bytes of the decoder loss per pixel at C output channels:
+# targets read (2 C in BF16), feature map read (64), its gradient written (64).
+def decoder_bytes_per_pixel(C):
+    return 2 * C + 128
+
+
+def time_decoder(ctx, wl, dev, C=512, reps=20, warmup=3):
+    """Median time of the feature-decoder loss (lgs_decoder_l1) over every
+    view of the workload (one call per view, BF16 targets of C channels),
+    HIP events on the launching stream around the views' calls."""
+    import torch
+    import scenes
+    views = []
+    for v, c in enumerate(wl.cams):
+        F, Wm, b, G = scenes.decoder_inputs(100 + v, c.width, c.height, C)
+        views.append((torch.as_tensor(F).to(dev), torch.as_tensor(Wm).to(dev), torch.as_tensor(b).to(dev),
+                      torch.as_tensor(G).to(torch.bfloat16).to(dev)))
+    outs = [(torch.empty(1, device=dev), torch.empty_like(x[0]), torch.empty_like(x[1]), torch.empty_like(x[2]))
+            for x in views]
+
+    def run():
+        for x, o in zip(views, outs):
+            ctx.decoder_l1(x[0], x[1], x[2], x[3], 1.0, out=o)
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in ev:
+        e0.record()
+        run()
+        e1.record()
+    torch.cuda.synchronize()
+    ts = sorted(e0.elapsed_time(e1) for e0, e1 in ev)
+    return ts[len(ts) // 2]
+
+
 def cpu_baseline(wl, budget_s=15.0):
     """The FP64 oracle (forward + autodiff backward) on a bounded sample of
     the same workload: 64x64 crops of the first view, until about `budget_s`
@@ -303,6 +339,8 @@ def main():
     ap.add_argument("--order", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-decoder", action="store_true",
+                    help="skip the feature-decoder loss timing (1x1 conv 16 -> 512, BF16 targets)")
     ap.add_argument("--no-dssim", action="store_true",
                     help="skip the step with the D-SSIM loss term (lam = 0.2) and the loss-kernel timing")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -406,6 +444,19 @@ def main():
                         "loss_GB/s": round(lb / (loss_ms / 1e3) / 1e9, 1),
                         "loss_hbm_frac": round(lb / (loss_ms / 1e3) / 1e9 / PEAK_HBM_GBS, 4),
                         "view0_terms": [round(float(x), 6) for x in terms[0]]}
+    if not args.no_decoder:
+        Cd = 512
+        log(f"[bench] timing the feature-decoder loss (16 -> {Cd}, every view)")
+        dms = time_decoder(ctx, wl, dev, Cd)
+        db_ = decoder_bytes_per_pixel(Cd) * wl.pixels
+        dfl = 6 * 16 * Cd * wl.pixels       # three products of 16 x C per pixel, FMA = 2
+        out["decoder"] = {"out_dim": Cd, "target_dtype": "bf16", "ms": round(dms, 4),
+                          "Mpixel/s": round(wl.pixels / (dms / 1e3) / 1e6, 3),
+                          "roofline": {"bound": "hbm", "achieved": round(db_ / (dms / 1e3) / 1e9, 1),
+                                       "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                       "frac": round(db_ / (dms / 1e3) / 1e9 / PEAK_HBM_GBS, 4),
+                                       "bytes": db_},
+                          "mfma_TFLOP/s": round(dfl / (dms / 1e3) / 1e12, 2)}
     if not args.no_plain and cfg != 2:
         log("[bench] timing the plain FP32 single-view form (C2)")
         wl2 = scenes.make_workload(2)

@@ -198,6 +198,30 @@ lgs_status lgs_loss(lgs_context *ctx, int32_t n_views, const lgs_camera *cams,
                     const float loss_w[3], float ssim_lambda,
                     const lgs_images *grad, float *terms, hipStream_t stream);
 
+/* The feature-distillation loss of Eq. (2) through the decoder D_theta
+ * (Sec. III-B.3), and its gradients.  D_theta is read as a 1x1 convolution,
+ * one affine map R^16 -> R^C per pixel, Z(p) = W F(p) + b:
+ *   L = w_feat * mean over C x H x W of |Z - F_gt|   (sign(0) = 0)
+ *   grad_feat   = dL/dF        [16][H][W]  (overwritten)
+ *   grad_weight = dL/dW        [C][16]     (overwritten)
+ *   grad_bias   = dL/db        [C]         (overwritten)
+ *   loss        = L            device scalar, or NULL
+ * feat F [16][H][W], weight W [C][16] (row-major), bias b [C]: FP32 device
+ * arrays; target F_gt [C][H][W] in target_dtype (BF16 or FP32), device.
+ * out_dim C: 256 or 512.  The products run on the matrix cores with the
+ * FP32 operands split into two BF16 terms each (relative error of Z about
+ * 2^-16 of |W||F|; the signs are exact).  Enqueued on `stream` (the context
+ * keeps a small partial-sum buffer; calls on one context are ordered by its
+ * stream).  Deterministic (fixed-order reductions).  LGS_ERR_INVALID_ARG for
+ * NULL or misaligned arrays, sizes < 1 or a non-finite w_feat;
+ * LGS_ERR_UNSUPPORTED for another out_dim. */
+lgs_status lgs_decoder_l1(lgs_context *ctx, int32_t width, int32_t height,
+                          int32_t out_dim, const float *feat,
+                          const float *weight, const float *bias,
+                          const void *target, lgs_dtype target_dtype,
+                          float w_feat, float *grad_feat, float *grad_weight,
+                          float *grad_bias, float *loss, hipStream_t stream);
+
 lgs_status lgs_state_counts(const lgs_fwd_state *state, lgs_counts *out);
 /* With settings.profile = 1 on the forward, after its backward: elapsed
  * milliseconds of ms[0..4] = projection + depth sort + scans, pair emission

@@ -44,7 +44,7 @@ def decoder_l1(F: np.ndarray, W: np.ndarray, b: np.ndarray, Fgt: np.ndarray, w_f
     C = W.shape[0]
     n = H * Wd
     Ff = np.asarray(F, np.float64).reshape(d, n)
-    G = np.asarray(Fgt, np.float64).reshape(C, n)
+    G = np.asarray(Fgt).reshape(C, n)          # converted to float64 chunk by chunk
     Wt = torch.tensor(np.asarray(W, np.float64), requires_grad=True)
     bt = torch.tensor(np.asarray(b, np.float64), requires_grad=True)
     scale = w_feat / (C * n)
@@ -56,7 +56,7 @@ def decoder_l1(F: np.ndarray, W: np.ndarray, b: np.ndarray, Fgt: np.ndarray, w_f
         e = min(n, s + chunk)
         Fc = torch.tensor(Ff[:, s:e], requires_grad=True)
         Z = Wt @ Fc + bt[:, None]
-        Lc = scale * (Z - torch.as_tensor(G[:, s:e])).abs().sum()
+        Lc = scale * (Z - torch.as_tensor(np.asarray(G[:, s:e], np.float64))).abs().sum()
         gF, gW, gb = torch.autograd.grad(Lc, [Fc, Wt, bt])
         L += float(Lc.detach())
         dF[:, s:e] = gF.numpy()

@@ -56,7 +56,8 @@ class lgs_counts(C.Structure):
 
 
 EXPORTS = ["lgs_status_string", "lgs_last_error", "lgs_default_settings", "lgs_context_create",
-           "lgs_context_destroy", "lgs_forward", "lgs_backward", "lgs_backward_l1", "lgs_loss", "lgs_state_counts",
+           "lgs_context_destroy", "lgs_forward", "lgs_backward", "lgs_backward_l1", "lgs_loss", "lgs_decoder_l1",
+           "lgs_state_counts",
            "lgs_state_stage_ms",
            "lgs_state_release", "lgs_graph_create", "lgs_graph_launch", "lgs_graph_status",
            "lgs_graph_counts", "lgs_graph_stage_ms", "lgs_graph_destroy", "lgs_autotune"]
@@ -90,6 +91,9 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.lgs_loss.restype = C.c_int
     lib.lgs_loss.argtypes = [P, C.c_int32, C.POINTER(lgs_camera), C.POINTER(lgs_images), C.POINTER(lgs_images),
                              C.POINTER(C.c_float), C.c_float, C.POINTER(lgs_images), P, P]
+    lib.lgs_decoder_l1.restype = C.c_int
+    lib.lgs_decoder_l1.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, P, P, P, P, C.c_int32, C.c_float,
+                                   P, P, P, P, P]
     lib.lgs_state_counts.restype = C.c_int
     lib.lgs_state_counts.argtypes = [P, C.POINTER(lgs_counts)]
     lib.lgs_state_stage_ms.restype = C.c_int
@@ -278,6 +282,31 @@ class Context:
         if st != LGS_OK:
             self._raise(st)
         return grad, terms
+
+    def decoder_l1(self, feat, weight, bias, target, w_feat: float = 1.0, stream=None, out=None):
+        """Feature-distillation loss of Eq. (2) through the 1x1-conv decoder
+        (lgs_decoder_l1).  feat [16,H,W] FP32, weight [C,16], bias [C] FP32,
+        target [C,H,W] BF16 or FP32 (CUDA, contiguous).  Returns (loss [1],
+        grad_feat, grad_weight, grad_bias)."""
+        d, H, W = feat.shape
+        Cd = weight.shape[0]
+        for t, shp, dts, name in ((feat, (16, H, W), (torch.float32,), "feat"),
+                                  (weight, (Cd, 16), (torch.float32,), "weight"),
+                                  (bias, (Cd,), (torch.float32,), "bias"),
+                                  (target, (Cd, H, W), (torch.float32, torch.bfloat16), "target")):
+            if tuple(t.shape) != shp or t.dtype not in dts or not t.is_cuda or not t.is_contiguous():
+                raise ValueError(f"{name}: expected contiguous CUDA tensor of shape {shp}, dtype in {dts}")
+        dev = feat.device
+        if out is None:
+            out = (torch.empty(1, device=dev), torch.empty_like(feat), torch.empty_like(weight),
+                   torch.empty_like(bias))
+        loss, gf, gw, gb = out
+        dt = LGS_BF16 if target.dtype == torch.bfloat16 else LGS_F32
+        st = lib().lgs_decoder_l1(self._h, W, H, Cd, _ptr(feat), _ptr(weight), _ptr(bias), _ptr(target), dt,
+                                  float(w_feat), _ptr(gf), _ptr(gw), _ptr(gb), _ptr(loss), _stream(stream))
+        if st != LGS_OK:
+            self._raise(st)
+        return loss, gf, gw, gb
 
     def backward(self, state: "State", params, grad_outs, stream=None) -> dict:
         """grad_outs: per view dict rgb [3,H,W], depth [H,W], feat [16,H,W],

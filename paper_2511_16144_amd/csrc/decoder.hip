@@ -1,0 +1,360 @@
+// Feature-distillation loss of Eq. (2) through a 1x1-convolution decoder, and
+// its gradients, on the matrix cores:
+//
+//   Z(p) = W F(p) + b  (W [C][16], b [C], F [16][H][W]),
+//   L = w_feat / (C H W) * sum_{c,p} |Z[c][p] - T[c][p]|   (T = F_gt, [C][H][W])
+//   R = sign(Z - T);  dL/dF = s W^T R;  dL/dW = s R F^T;  dL/db = s sum_p R,
+//   s = w_feat / (C H W).
+//
+// Three products per pixel with 16 or 32 as the inner dimension, so each is a
+// run of v_mfma_f32_16x16x32_bf16 (FP32 accumulation).  The FP32 operands are
+// split into two BF16 terms (x = x_hi + x_lo, 16 significant bits); R is
+// -1, 0 or 1, exact in BF16.  Z^T = F^T W^T takes the two splits in one
+// instruction pair: A = [F_hi | F_lo] (K = 32) against B = [W_hi ; W_hi], then
+// A against [W_lo ; 0], i.e. F_hi W_hi + F_lo W_hi + F_hi W_lo.
+//
+// Work-group = 8 waves (two per SIMD: one wave's target loads overlap the
+// other's matrix products); a work-group walks a contiguous run of 32-pixel
+// chunks of the image (a fixed assignment, so its partial sums are
+// deterministic), loading the next chunk's inputs while it works on one.  Wave w owns the channels [C/8 w, C/8 (w+1)): per chunk it
+// forms its Z^T tiles (16 pixels x 16 channels; the pixel order of the rows
+// gives lane l 8 consecutive pixels of one channel over the chunk's two
+// column groups, so its targets are one 16-byte load per channel), the
+// signs, its share of dL/dF (summed over the 8 waves through LDS) and its
+// rows of dL/dW and dL/db (kept in registers over all chunks).  A second
+// kernel adds the work-groups' partials in a fixed order.
+#include "lgs_internal.h"
+
+namespace lgs {
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kDecWaves = 8;
+constexpr int kDecThreads = 64 * kDecWaves;
+constexpr int kChunk = 32;            // pixels per chunk
+constexpr int kFA = 40;               // LDS pitch (u16) of the [pixel][k] F rows (80 B)
+constexpr int kFT = 40;               // LDS pitch (u16) of the [feature][pixel] F rows
+constexpr int kRC = 40;               // LDS pitch (u16) of the [channel][pixel] sign rows
+
+__device__ __forceinline__ unsigned short to_bf16(float x) {
+  const uint32_t u = __float_as_uint(x);
+  return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float from_bf16(unsigned short h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ bf16x8_t as_bf16x8(u16x8 v) { return __builtin_bit_cast(bf16x8_t, v); }
+
+// Work-group barrier for LDS traffic: waits for this wave's LDS accesses
+// only, so the prefetched global loads stay in flight across it (a full
+// __syncthreads() also waits for every outstanding global load).
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+__device__ __forceinline__ f32x4 mfma(bf16x8_t a, bf16x8_t b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Eight consecutive targets as loaded (BF16: 16 bytes, FP32: 32 bytes),
+// vector loads when aligned and in range, else element by element (zero past
+// the end); unpacked to FP32 when used.
+struct F8 { float4 a, b; };
+template <typename T> struct Raw8;
+template <> struct Raw8<unsigned short> { typedef uint4 type; };
+template <> struct Raw8<float> { typedef F8 type; };
+
+__device__ __forceinline__ uint4 load_raw8(const unsigned short* p, bool vec, int64_t left) {
+  if (vec) return *(const uint4*)p;
+  uint32_t h[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) h[i] = i < left ? (uint32_t)p[i] : 0u;
+  return make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
+}
+__device__ __forceinline__ F8 load_raw8(const float* p, bool vec, int64_t left) {
+  F8 r;
+  if (vec) {
+    r.a = *(const float4*)p;
+    r.b = *(const float4*)(p + 4);
+    return r;
+  }
+  float f[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) f[i] = i < left ? p[i] : 0.f;
+  r.a = make_float4(f[0], f[1], f[2], f[3]);
+  r.b = make_float4(f[4], f[5], f[6], f[7]);
+  return r;
+}
+// targets h*4 .. h*4 + 3 of the eight
+__device__ __forceinline__ void unpack4(uint4 v, int h, float t[4]) {
+  const uint32_t x = h ? v.z : v.x, y = h ? v.w : v.y;
+  t[0] = __uint_as_float(x << 16); t[1] = __uint_as_float(x & 0xffff0000u);
+  t[2] = __uint_as_float(y << 16); t[3] = __uint_as_float(y & 0xffff0000u);
+}
+__device__ __forceinline__ void unpack4(const F8& v, int h, float t[4]) {
+  const float4 u = h ? v.b : v.a;
+  t[0] = u.x; t[1] = u.y; t[2] = u.z; t[3] = u.w;
+}
+
+template <typename TT, int NT>   // NT: 16-channel tiles per wave (C = 16 NT kDecWaves, NT >= 2)
+__global__ __launch_bounds__(kDecThreads) void k_decoder(DecArgs a, const TT* __restrict__ target,
+                                                         float* __restrict__ part) {
+  constexpr int Cw = 16 * NT;             // channels per wave
+  constexpr int KS = Cw / 32;             // 32-channel steps of the dF product
+  static_assert(KS >= 1, "at least 32 channels per wave");
+  __shared__ __attribute__((aligned(16))) unsigned short fA[kChunk * kFA];     // [pixel][F_hi 16 | F_lo 16]
+  __shared__ __attribute__((aligned(16))) unsigned short fT[2 * 16 * kFT];     // [hi/lo][feature][pixel]
+  __shared__ __attribute__((aligned(16))) unsigned short rC[kDecWaves][Cw * kRC];      // [channel][pixel] signs
+  __shared__ __attribute__((aligned(16))) unsigned short rP[kDecWaves][kChunk * Cw];   // [pixel][channel] signs
+  __shared__ float red[kDecWaves];
+  static_assert(Cw * kRC * 2 >= 16 * kChunk * 4, "dF partials fit over the sign rows");
+  float* dfr = (float*)&rC[0][0];                      // [wave][feature][pixel] dF partials (after the MFMAs)
+
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int r16 = lane & 15, q4 = lane >> 4;
+  const int64_t n = a.n;
+  const int c0 = w * Cw;   // first channel of this wave
+
+  // W is staged in LDS once (over the sign rows, unused until the first
+  // chunk's first barrier), then every wave builds its operands from there
+  float* wl = (float*)&rC[0][0];
+  static_assert(sizeof(rC) >= (size_t)kDecWaves * Cw * 16 * sizeof(float), "W fits over the sign rows");
+  for (int e = t; e < a.C * 16; e += kDecThreads) wl[e] = a.weight[e];
+  __syncthreads();
+  // this wave's operands of W, split hi/lo, in registers for the whole run
+  // Z^T B operand, tile nt: lane (k block q4, channel r16): [W_hi ; W_hi] and [W_lo ; 0]
+  bf16x8_t bz1[NT], bz2[NT];
+  float bias[NT];
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    const int ch = c0 + 16 * nt + r16;
+    const float* wr = wl + ch * 16 + 8 * (q4 & 1);
+    u16x8 h, l;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const float x = wr[k];
+      const unsigned short hi = to_bf16(x);
+      h[k] = hi;
+      l[k] = q4 < 2 ? to_bf16(x - from_bf16(hi)) : (unsigned short)0;
+    }
+    bz1[nt] = as_bf16x8(h);
+    bz2[nt] = as_bf16x8(l);
+    bias[nt] = a.bias[ch];
+  }
+  // dF A operand (W^T), step ks: lane (feature r16, channels 32 ks + 8 q4 .. + 7)
+  bf16x8_t wt_h[KS], wt_l[KS];
+#pragma unroll
+  for (int ks = 0; ks < KS; ++ks) {
+    u16x8 h, l;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int ch = c0 + 32 * ks + 8 * q4 + k;
+      const float x = wl[ch * 16 + r16];
+      const unsigned short hi = to_bf16(x);
+      h[k] = hi;
+      l[k] = to_bf16(x - from_bf16(hi));
+    }
+    wt_h[ks] = as_bf16x8(h);
+    wt_l[ks] = as_bf16x8(l);
+  }
+
+  f32x4 dw[NT];            // dW^T tiles: lane (features 4 q4 + i, channel 16 nt + r16)
+  float db[NT];            // per lane: channel 16 nt + r16, its pixels 4 q4 .. + 3
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+    dw[nt] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    db[nt] = 0.f;
+  }
+  float lsum = 0.f;
+
+  // The next chunk's targets and feature element are loaded into registers
+  // while the current chunk is processed, so the loads' latency overlaps
+  // the matrix products.
+  typedef typename Raw8<TT>::type RawT;
+  RawT tr[NT];
+  float fr = 0.f;
+  static_assert(kDecThreads == 16 * kChunk, "one feature element per thread and chunk");
+  const int fk = t >> 5, fpx = t & 31;
+  // lane (q4, r16) of the Z^T products holds pixels 8 q4 .. 8 q4 + 7 of the
+  // chunk (rows 4 q4 .. 4 q4 + 3 of column group cg are pixels 8 q4 + 4 cg
+  // + i): its targets of one channel are one 16-byte load
+  auto fetch = [&](int64_t ck) {
+    const int64_t p0 = ck * kChunk;
+    const bool full = p0 + kChunk <= n;
+    fr = p0 + fpx < n ? a.feat[(size_t)fk * n + p0 + fpx] : 0.f;
+    const int64_t pp = p0 + 8 * q4;
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+      const TT* tp = target + (size_t)(c0 + 16 * nt + r16) * n + pp;
+      tr[nt] = load_raw8(tp, full && a.vec, n - pp);
+    }
+  };
+  // each work-group takes a contiguous run of chunks, so the two halves of
+  // a 128-byte target line are read by the same work-group one chunk apart
+  const int64_t n_chunks = (n + kChunk - 1) / kChunk;
+  const int64_t per = (n_chunks + gridDim.x - 1) / gridDim.x;
+  const int64_t ck0 = (int64_t)blockIdx.x * per;
+  const int64_t ck1 = ck0 + per < n_chunks ? ck0 + per : n_chunks;
+  if (ck0 < ck1) fetch(ck0);
+  for (int64_t ck = ck0; ck < ck1; ++ck) {
+    const int64_t p0 = ck * kChunk;
+    // (1) F chunk -> LDS: [pixel][F_hi | F_lo] and [hi/lo][feature][pixel]
+    {
+      const unsigned short hi = to_bf16(fr), lo = to_bf16(fr - from_bf16(hi));
+      fA[fpx * kFA + fk] = hi;
+      fA[fpx * kFA + 16 + fk] = lo;
+      fT[fk * kFT + fpx] = hi;
+      fT[16 * kFT + fk * kFT + fpx] = lo;
+    }
+    RawT cur[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) cur[nt] = tr[nt];
+    if (ck + 1 < ck1) fetch(ck + 1);
+    lds_barrier();   // also: every thread has read the previous chunk's dF partials
+    // (2) Z^T tiles, signs, loss, db; signs to LDS in both layouts
+#pragma unroll
+    for (int cg = 0; cg < 2; ++cg) {
+      // A row r16 of column group cg is pixel 8 (r16 / 4) + 4 cg + r16 % 4
+      const bf16x8_t af = as_bf16x8(*(const u16x8*)(fA + (8 * (r16 >> 2) + 4 * cg + (r16 & 3)) * kFA + 8 * q4));
+      const int pl = 8 * q4 + 4 * cg;    // first of this lane's 4 pixels of this column group
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        f32x4 z = {bias[nt], bias[nt], bias[nt], bias[nt]};
+        z = mfma(af, bz1[nt], z);
+        z = mfma(af, bz2[nt], z);
+        float tv[4];
+        unpack4(cur[nt], cg, tv);
+        unsigned short sg[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const bool valid = p0 + pl + i < n;
+          const float d = z[i] - tv[i];
+          const float s = !valid ? 0.f : (d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f));
+          lsum += valid ? fabsf(d) : 0.f;
+          db[nt] += s;
+          sg[i] = to_bf16(s);
+          rP[w][(pl + i) * Cw + 16 * nt + r16] = sg[i];
+        }
+        uint2 packed;
+        packed.x = (uint32_t)sg[0] | ((uint32_t)sg[1] << 16);
+        packed.y = (uint32_t)sg[2] | ((uint32_t)sg[3] << 16);
+        *(uint2*)(&rC[w][(16 * nt + r16) * kRC + pl]) = packed;
+      }
+    }
+    // (3) dW^T += F R^T over the chunk's 32 pixels (A = F hi/lo, B = signs)
+    {
+      const bf16x8_t fh = as_bf16x8(*(const u16x8*)(fT + r16 * kFT + 8 * q4));
+      const bf16x8_t fl = as_bf16x8(*(const u16x8*)(fT + 16 * kFT + r16 * kFT + 8 * q4));
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt) {
+        const bf16x8_t rb = as_bf16x8(*(const u16x8*)(&rC[w][(16 * nt + r16) * kRC + 8 * q4]));
+        dw[nt] = mfma(fh, rb, dw[nt]);
+        dw[nt] = mfma(fl, rb, dw[nt]);
+      }
+    }
+    // (4) this wave's share of dF = W^T R (A = W^T hi/lo, B = signs [channel][pixel])
+    f32x4 dfa[2];
+#pragma unroll
+    for (int cg = 0; cg < 2; ++cg) {
+      dfa[cg] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const bf16x8_t rb = as_bf16x8(*(const u16x8*)(&rP[w][(16 * cg + r16) * Cw + 32 * ks + 8 * q4]));
+        dfa[cg] = mfma(wt_h[ks], rb, dfa[cg]);
+        dfa[cg] = mfma(wt_l[ks], rb, dfa[cg]);
+      }
+    }
+    lds_barrier();   // every wave is done with rC / rP: the dF partials take their place
+#pragma unroll
+    for (int cg = 0; cg < 2; ++cg)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) dfr[(w * 16 + 4 * q4 + i) * kChunk + 16 * cg + r16] = dfa[cg][i];
+    lds_barrier();
+    for (int e = t; e < 16 * kChunk; e += kDecThreads) {
+      const int k = e >> 5, px = e & 31;
+      float v = 0.f;
+#pragma unroll
+      for (int u = 0; u < kDecWaves; ++u) v += dfr[(u * 16 + k) * kChunk + px];
+      if (p0 + px < n) a.grad_feat[(size_t)k * n + p0 + px] = a.scale * v;
+    }
+    // no barrier here: the next chunk writes fA / fT (free since the last
+    // barrier) before its first barrier, and rC / rP only after it
+  }
+
+  // partials of this work-group: dW [C][16], db [C], loss
+  float* pb = part + (size_t)blockIdx.x * a.part_stride;
+#pragma unroll
+  for (int nt = 0; nt < NT; ++nt) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) pb[(size_t)(c0 + 16 * nt + r16) * 16 + 4 * q4 + i] = dw[nt][i];
+    float s = db[nt];
+    s += __shfl_xor(s, 16);
+    s += __shfl_xor(s, 32);
+    if (q4 == 0) pb[(size_t)a.C * 16 + c0 + 16 * nt + r16] = s;
+  }
+  for (int o = 32; o > 0; o >>= 1) lsum += __shfl_xor(lsum, o);
+  if (lane == 0) red[w] = lsum;
+  __syncthreads();
+  if (t == 0) {
+    float s = 0.f;
+#pragma unroll
+    for (int u = 0; u < kDecWaves; ++u) s += red[u];
+    pb[(size_t)a.C * 17] = s;
+  }
+}
+
+// dW, db and the loss: partials of every work-group added in a fixed order
+// (64 outputs per work-group; 4 threads per output take every 4th partial,
+// then their sums are added in a fixed order).
+__global__ __launch_bounds__(256) void k_decoder_reduce(DecArgs a, const float* __restrict__ part, int n_parts) {
+  __shared__ double red[4][64];
+  const int o = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * 64 + o;
+  const int64_t m = (int64_t)a.C * 17 + 1;
+  double s = 0.0;
+  if (i < m)
+    for (int b = g; b < n_parts; b += 4) s += (double)part[(size_t)b * a.part_stride + i];
+  red[g][o] = s;
+  __syncthreads();
+  if (g != 0 || i >= m) return;
+  s = (red[0][o] + red[1][o]) + (red[2][o] + red[3][o]);
+  if (i < (int64_t)a.C * 16) {
+    a.grad_weight[i] = (float)(a.scale * s);
+  } else if (i < (int64_t)a.C * 17) {
+    a.grad_bias[i - (int64_t)a.C * 16] = (float)(a.scale * s);
+  } else if (a.loss) {
+    *a.loss = (float)(a.scale * s);
+  }
+}
+
+template <typename TT>
+void launch_t(const DecArgs& a, const void* target, float* part, int grid, hipStream_t s) {
+  const TT* tp = (const TT*)target;
+  if (a.C == 256)
+    hipLaunchKernelGGL((k_decoder<TT, 2>), dim3(grid), dim3(kDecThreads), 0, s, a, tp, part);
+  else
+    hipLaunchKernelGGL((k_decoder<TT, 4>), dim3(grid), dim3(kDecThreads), 0, s, a, tp, part);
+}
+
+}  // namespace
+
+bool decoder_dim_ok(int C) { return C == 256 || C == 512; }
+
+int decoder_grid(int64_t n) {
+  int dev = 0, cus = 256;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const int64_t chunks = (n + kChunk - 1) / kChunk;
+  int64_t g = (int64_t)cus;   // one 8-wave work-group per CU
+  if (g > chunks) g = chunks;
+  return (int)(g > 0 ? g : 1);
+}
+
+void launch_decoder(const DecArgs& a, const void* target, int target_bf16, float* part, int grid, hipStream_t s) {
+  if (target_bf16) launch_t<unsigned short>(a, target, part, grid, s);
+  else launch_t<float>(a, target, part, grid, s);
+  const int64_t m = (int64_t)a.C * 17 + 1;
+  hipLaunchKernelGGL(k_decoder_reduce, dim3((unsigned)((m + 63) / 64)), dim3(256), 0, s, a, part, grid);
+}
+
+}  // namespace lgs

@@ -198,6 +198,22 @@ void launch_loss_df(const LossView* views, int n_views, int64_t n_blocks, float2
 void launch_loss_terms(const LossView* views, int n_views, int ssim, const float2* part_rgb,
                        const float2* part_df, float* terms, hipStream_t s);
 
+// feature decoder (1x1 convolution 16 -> C) and its L1 distillation loss:
+// dL/dF, dL/dW, dL/db and the loss; part holds grid x part_stride floats of
+// per-work-group partial sums (dW [C][16], db [C], loss)
+struct DecArgs {
+  const float *feat, *weight, *bias;   // F [16][n], W [C][16], b [C]
+  float *grad_feat, *grad_weight, *grad_bias, *loss;
+  int64_t n;                           // pixels
+  int64_t part_stride;                 // >= 17 C + 1
+  int32_t C;                           // 256 or 512
+  int32_t vec;                         // targets allow 8-element vector loads (n % 8 == 0, 16-B base)
+  float scale;                         // w_feat / (C n)
+};
+bool decoder_dim_ok(int C);
+int decoder_grid(int64_t n);
+void launch_decoder(const DecArgs& a, const void* target, int target_bf16, float* part, int grid, hipStream_t s);
+
 // gradient reduction and projection backward
 void launch_seg_reduce(const uint32_t* slot_off, const float* partials, const uint8_t* mask,
                        const Counters* cnt, int64_t n_max, float* grad2d, hipStream_t s);

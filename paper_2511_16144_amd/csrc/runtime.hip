@@ -36,6 +36,9 @@ struct lgs_context {
   float2* loss_part = nullptr;
   int64_t loss_part_cap = 0;
   hipEvent_t loss_copied = nullptr;
+  // lgs_decoder_l1 workspace: per-work-group partial sums
+  float* dec_part = nullptr;
+  int64_t dec_part_cap = 0;
 };
 
 namespace {
@@ -650,6 +653,7 @@ void lgs_context_destroy(lgs_context* ctx) {
   if (ctx->loss_tab) hipFree(ctx->loss_tab);
   if (ctx->loss_part) hipFree(ctx->loss_part);
   if (ctx->loss_copied) hipEventDestroy(ctx->loss_copied);
+  if (ctx->dec_part) hipFree(ctx->dec_part);
   delete ctx;
 }
 
@@ -841,6 +845,51 @@ lgs_status lgs_loss(lgs_context* ctx, int32_t n_views, const lgs_camera* cams, c
   launch_loss_rgb(ctx->loss_tab, k, nb, ctx->loss_part, stream);
   launch_loss_df(ctx->loss_tab, n_views, nd, ctx->loss_part + nb, stream);
   if (terms) launch_loss_terms(ctx->loss_tab, n_views, k.ssim, ctx->loss_part, ctx->loss_part + nb, terms, stream);
+  HIP_TRY(ctx, hipGetLastError());
+  return LGS_OK;
+}
+
+lgs_status lgs_decoder_l1(lgs_context* ctx, int32_t width, int32_t height, int32_t out_dim, const float* feat,
+                          const float* weight, const float* bias, const void* target, lgs_dtype target_dtype,
+                          float w_feat, float* grad_feat, float* grad_weight, float* grad_bias, float* loss,
+                          hipStream_t stream) {
+  if (!ctx) return LGS_ERR_INVALID_ARG;
+  ctx->err.clear();
+  if (width < 1 || height < 1) return fail(ctx, LGS_ERR_INVALID_ARG, "width and height must be >= 1");
+  const int64_t n = (int64_t)width * height;
+  if (n > ((int64_t)1 << 31)) return fail(ctx, LGS_ERR_UNSUPPORTED, "more than 2^31 pixels");
+  if (!decoder_dim_ok(out_dim)) return fail(ctx, LGS_ERR_UNSUPPORTED, "out_dim must be 256 or 512");
+  if (target_dtype != LGS_F32 && target_dtype != LGS_BF16)
+    return fail(ctx, LGS_ERR_INVALID_ARG, "unknown target dtype");
+  if (!isfinite(w_feat)) return fail(ctx, LGS_ERR_INVALID_ARG, "non-finite w_feat");
+  if (!feat || !weight || !bias || !target || !grad_feat || !grad_weight || !grad_bias)
+    return fail(ctx, LGS_ERR_INVALID_ARG, "NULL array");
+  if (!aligned4(feat) || !aligned4(weight) || !aligned4(bias) || !aligned4(grad_feat) || !aligned4(grad_weight) ||
+      !aligned4(grad_bias) || (loss && !aligned4(loss)) ||
+      ((uintptr_t)target & (target_dtype == LGS_BF16 ? 1u : 3u)) != 0)
+    return fail(ctx, LGS_ERR_INVALID_ARG, "misaligned array");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  (void)hipGetLastError();   // launch checks below see only this call's errors
+  const int grid = decoder_grid(n);
+  const int64_t stride = ((17 * (int64_t)out_dim + 1 + 63) / 64) * 64;
+  const int64_t need = (int64_t)grid * stride;
+  if (need > ctx->dec_part_cap) {
+    HIP_TRY(ctx, hipDeviceSynchronize());   // earlier calls may still use the old buffer
+    if (ctx->dec_part) hipFree(ctx->dec_part);
+    ctx->dec_part = nullptr;
+    ctx->dec_part_cap = 0;
+    HIP_TRY(ctx, hipMalloc((void**)&ctx->dec_part, sizeof(float) * need));
+    ctx->dec_part_cap = need;
+  }
+  DecArgs a;
+  a.feat = feat; a.weight = weight; a.bias = bias;
+  a.grad_feat = grad_feat; a.grad_weight = grad_weight; a.grad_bias = grad_bias; a.loss = loss;
+  a.n = n;
+  a.part_stride = stride;
+  a.C = out_dim;
+  a.vec = n % 8 == 0 && ((uintptr_t)target & 15u) == 0;
+  a.scale = (float)((double)w_feat / ((double)out_dim * (double)n));
+  launch_decoder(a, target, target_dtype == LGS_BF16, ctx->dec_part, grid, stream);
   HIP_TRY(ctx, hipGetLastError());
   return LGS_OK;
 }

@@ -338,3 +338,16 @@ def loss_images(seed: int, sizes, noise: float = 0.1, independent: bool = False)
         outs.append(o)
         tgts.append(t)
     return outs, tgts
+
+
+def decoder_inputs(seed: int, W: int, H: int, C: int = 512):
+    """Inputs of the feature-decoder loss: a rendered-like 16-channel feature
+    map F [16, H, W] (N(0, 0.25) per channel), decoder weights W [C, 16]
+    (N(0, 1/16)), bias [C] (N(0, 0.05)) and extractor-like targets F_gt
+    [C, H, W] (N(0, 0.25)), all float32."""
+    rng = np.random.Generator(np.random.PCG64(12000 + seed))
+    F = rng.normal(0.0, 0.25, size=(16, H, W)).astype(np.float32)
+    Wm = rng.normal(0.0, 0.25, size=(C, 16)).astype(np.float32)
+    b = rng.normal(0.0, 0.05, size=C).astype(np.float32)
+    G = rng.normal(0.0, 0.25, size=(C, H, W)).astype(np.float32)
+    return F, Wm, b, G

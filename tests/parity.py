@@ -155,3 +155,33 @@ def dilate(mask, r):
     if not mask.any():
         return mask.copy()
     return ndimage.binary_dilation(mask, structure=np.ones((2 * r + 1, 2 * r + 1), bool))
+
+
+def separate_decoder_targets(Z_fn, G, delta=2e-3, bf16=True, chunk=1 << 16):
+    """Decoder targets moved at least `delta` away from the oracle's decoded
+    values Z (Z_fn(s, e) returns the oracle's Z for pixels [s, e) as
+    [C, e - s] float64), then rounded to BF16 when `bf16`, so that every
+    sign(Z - F_gt) is the same in the matrix-core product and in FP64.
+    Built from the oracle's values only."""
+    C = G.shape[0]
+    Gf = G.reshape(C, -1).astype(np.float32, copy=True)
+    n = Gf.shape[1]
+    for s in range(0, n, chunk):
+        e = min(n, s + chunk)
+        Z = Z_fn(s, e)
+        g = Gf[:, s:e].astype(np.float64)
+        if bf16:
+            g = round_bf16_np(g)
+        close = np.abs(g - Z) < delta
+        sgn = np.where(g[close] >= Z[close], 1.0, -1.0)
+        v = Z[close] + 3 * delta * sgn
+        g[close] = round_bf16_np(v) if bf16 else v.astype(np.float32)
+        Gf[:, s:e] = g
+    return Gf.reshape(G.shape)
+
+
+def round_bf16_np(x):
+    """FP64/FP32 values rounded to BF16 (nearest even), returned as float64."""
+    u = np.ascontiguousarray(x, np.float32).view(np.uint32)
+    r = (u + np.uint32(0x7FFF) + ((u >> np.uint32(16)) & np.uint32(1))) & np.uint32(0xFFFF0000)
+    return r.view(np.float32).astype(np.float64)

@@ -1,0 +1,117 @@
+"""GPU parity of the feature-distillation loss through the 1x1-conv decoder
+(lgs_decoder_l1, through the C ABI) against the FP64 decoder oracle.
+
+Inputs: ``scenes.decoder_inputs`` (seeded).  The targets are first moved at
+least 2e-3 away from the oracle's decoded values and rounded to their
+storage type (``parity.separate_decoder_targets``, from the oracle's values
+only), so that every sign(Z - F_gt) is a decision both sides take the same
+way; then every element of dL/dF, dL/dW and dL/db and the loss are compared
+(1e-4 relative per group, rel_L2 and rel_max).  Sizes: 1x1, ragged (not a
+multiple of the 32-pixel chunk, nor of 4), a multiple of the chunk, the
+640x480 keyframe and the 1296x968 frame; BF16 and FP32 targets; C = 256
+and 512.
+"""
+import ctypes as C
+
+import numpy as np
+import pytest
+import torch
+
+import scenes
+from oracle import decoder_fp64 as DF
+from parity import TOL_F32, fmt, rel_err, separate_decoder_targets
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2511_16144_amd as P
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+def prepared(seed, W, H, Cd, bf16):
+    F, Wm, b, G = scenes.decoder_inputs(seed, W, H, Cd)
+    Ff = F.reshape(16, -1).astype(np.float64)
+
+    def z_fn(s, e):
+        return Wm.astype(np.float64) @ Ff[:, s:e] + b.astype(np.float64)[:, None]
+    G = separate_decoder_targets(z_fn, G, bf16=bf16)
+    return F, Wm, b, G
+
+
+def run_gpu(ctx, F, Wm, b, G, bf16, w_feat):
+    dt = torch.bfloat16 if bf16 else torch.float32
+    t = [torch.as_tensor(x).cuda() for x in (F, Wm, b)]
+    g = torch.as_tensor(G).to(dt).cuda()
+    loss, gf, gw, gb = ctx.decoder_l1(t[0], t[1], t[2], g, w_feat)
+    torch.cuda.synchronize()
+    return float(loss.item()), gf.cpu().numpy(), gw.cpu().numpy(), gb.cpu().numpy()
+
+
+def check(label, gpu, ref, tol=TOL_F32):
+    res = {"dF": rel_err(gpu[1], ref[1]), "dW": rel_err(gpu[2], ref[2]), "db": rel_err(gpu[3], ref[3])}
+    say(f"  {label}: loss gpu {gpu[0]:.7g} oracle {ref[0]:.7g};", fmt(res))
+    assert abs(gpu[0] - ref[0]) <= 1e-5 * abs(ref[0]), (label, gpu[0], ref[0])
+    for k, (l2, mx) in res.items():
+        assert l2 <= tol and mx <= tol, (label, k, l2, mx)
+
+
+CASES = [
+    ("1x1 C256 bf16", 1, 1, 256, True),
+    ("7x5 C256 f32", 7, 5, 256, False),
+    ("33x17 C512 bf16 ragged", 33, 17, 512, True),
+    ("64x48 C512 bf16", 64, 48, 512, True),
+    ("61x37 C512 f32 ragged", 61, 37, 512, False),
+    ("640x480 C512 bf16", 640, 480, 512, True),
+]
+
+
+@pytest.mark.parametrize("label,W,H,Cd,bf16", CASES, ids=[c[0] for c in CASES])
+def test_decoder_vs_oracle(ctx, label, W, H, Cd, bf16):
+    say(f"[case] decoder {label}")
+    F, Wm, b, G = prepared(W * 7 + H, W, H, Cd, bf16)
+    gpu = run_gpu(ctx, F, Wm, b, G, bf16, 0.8)
+    ref = DF.decoder_l1(F, Wm, b, G, w_feat=0.8)
+    check(label, gpu, ref)
+
+
+def test_decoder_full_frame_1296x968(ctx):
+    say("[case] decoder 1296x968 C512 bf16")
+    F, Wm, b, G = prepared(5, 1296, 968, 512, True)
+    gpu = run_gpu(ctx, F, Wm, b, G, True, 1.0)
+    ref = DF.decoder_l1(F, Wm, b, G, w_feat=1.0, chunk=1 << 17)
+    check("1296x968", gpu, ref)
+
+
+def test_decoder_deterministic_and_rejects_bad_arguments(ctx):
+    from paper_2511_16144_amd import binding as B
+    F, Wm, b, G = prepared(9, 50, 30, 256, True)
+    a1 = run_gpu(ctx, F, Wm, b, G, True, 1.0)
+    a2 = run_gpu(ctx, F, Wm, b, G, True, 1.0)
+    assert a1[0] == a2[0]
+    for x, y in zip(a1[1:], a2[1:]):
+        assert np.array_equal(x, y)
+    t = [torch.as_tensor(x).cuda() for x in (F, Wm, b)]
+    g = torch.as_tensor(G).to(torch.bfloat16).cuda()
+    out = [torch.empty(1, device="cuda"), torch.empty_like(t[0]), torch.empty_like(t[1]), torch.empty_like(t[2])]
+    lib, h = B.lib(), ctx._h
+    s = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    args = [t[0].data_ptr(), t[1].data_ptr(), t[2].data_ptr(), g.data_ptr(), B.LGS_BF16, C.c_float(1.0),
+            out[1].data_ptr(), out[2].data_ptr(), out[3].data_ptr(), out[0].data_ptr(), s]
+    assert lib.lgs_decoder_l1(h, 50, 30, 256, *args) == B.LGS_OK
+    assert lib.lgs_decoder_l1(h, 50, 30, 128, *args) == B.LGS_ERR_UNSUPPORTED
+    assert lib.lgs_decoder_l1(h, 0, 30, 256, *args) == B.LGS_ERR_INVALID_ARG
+    bad = list(args)
+    bad[6] = None
+    assert lib.lgs_decoder_l1(h, 50, 30, 256, *bad) == B.LGS_ERR_INVALID_ARG
+    bad = list(args)
+    bad[5] = C.c_float(float("nan"))
+    assert lib.lgs_decoder_l1(h, 50, 30, 256, *bad) == B.LGS_ERR_INVALID_ARG
+    torch.cuda.synchronize()
