@@ -20,7 +20,10 @@ used by the L1 depth loss and optimises Theta through the renderer):
     renderer, with its D-SSIM term (Gaussian-window SSIM, zero padding), and
     its gradient with respect to the rendered images by torch.autograd;
   * ``decoder_fp64`` -- the feature-distillation loss of Eq. (2) through a
-    1x1-convolution decoder, with its gradients (feature map, weights, bias).
+    1x1-convolution decoder, with its gradients (feature map, weights, bias);
+  * ``prune_fp64``   -- language-guided pruning, Eq. (4): K nearest
+    neighbours, distance and feature-similarity thresholds, and the geometric
+    criteria.
 
 The paper gives no rasterizer formulas; the readings taken where it is silent
 (colour model, depth definition, cut-offs, termination, pose perturbation...)
