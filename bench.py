@@ -294,6 +294,29 @@ def time_decoder(ctx, wl, dev, C=512, reps=20, warmup=3):
     return ts[len(ts) // 2]
 
 
+def time_prune(ctx, dev, reps=10, warmup=2):
+    """Median time of lgs_prune (grid keys, sort, K-nearest search with the
+    similarity test, geometric criteria, mask) on the batched workload's 500k
+    Gaussians with object-coherent features; each call synchronises."""
+    import torch
+    import scenes
+    import paper_2511_16144_amd as P
+    sc = scenes.prune_scene(0)
+    prm = P.params_from_arrays(sc.means, sc.log_scales, sc.quats, sc.logits, sc.rgb, sc.feat, device=dev,
+                               appearance_dtype=torch.bfloat16)
+    mask = torch.empty(sc.n, dtype=torch.uint8, device=dev)
+    for _ in range(warmup):
+        _, counts = ctx.prune(prm, mask=mask)
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, counts = ctx.prune(prm, mask=mask)
+        ts.append((time.perf_counter() - t0) * 1e3)
+    ts.sort()
+    return ts[len(ts) // 2], counts, sc.n
+
+
 def cpu_baseline(wl, budget_s=15.0):
     """The FP64 oracle (forward + autodiff backward) on a bounded sample of
     the same workload: 64x64 crops of the first view, until about `budget_s`
@@ -339,6 +362,8 @@ def main():
     ap.add_argument("--order", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-prune", action="store_true",
+                    help="skip the language-guided pruning timing (500k Gaussians)")
     ap.add_argument("--no-decoder", action="store_true",
                     help="skip the feature-decoder loss timing (1x1 conv 16 -> 512, BF16 targets)")
     ap.add_argument("--no-dssim", action="store_true",
@@ -457,6 +482,12 @@ def main():
                                        "frac": round(db_ / (dms / 1e3) / 1e9 / PEAK_HBM_GBS, 4),
                                        "bytes": db_},
                           "mfma_TFLOP/s": round(dfl / (dms / 1e3) / 1e12, 2)}
+    if not args.no_prune:
+        log("[bench] timing language-guided pruning (500k Gaussians)")
+        pms, pcounts, pn = time_prune(ctx, dev)
+        out["prune"] = {"gaussians": pn, "ms": round(pms, 3), "Mgaussians/s": round(pn / (pms / 1e3) / 1e6, 2),
+                        "redundant": pcounts[0], "geometric": pcounts[1], "pruned": pcounts[2],
+                        "timing": "host wall clock per call (the call synchronises)"}
     if not args.no_plain and cfg != 2:
         log("[bench] timing the plain FP32 single-view form (C2)")
         wl2 = scenes.make_workload(2)

@@ -222,6 +222,37 @@ lgs_status lgs_decoder_l1(lgs_context *ctx, int32_t width, int32_t height,
                           float w_feat, float *grad_feat, float *grad_weight,
                           float *grad_bias, float *loss, hipStream_t stream);
 
+/* Language-guided pruning (Sec. III-D, Eq. (4)) combined with the geometric
+ * criteria.  The paper publishes neither K nor the thresholds; the defaults
+ * (lgs_default_prune_params) are readings:
+ *   k           16     neighbours examined per Gaussian (1..32): the k
+ *                      nearest other Gaussians by distance of the means,
+ *                      ties by index
+ *   tau_dist    0.02   redundant only if closer than this (scene units)
+ *   tau_sim     0.9    ... and cosine similarity of the 16-d features above
+ *                      this (0 when either feature is zero)
+ *   min_opacity 0.005  geometric: sigmoid(logit) below this
+ *   max_scale   0.3    geometric: exp(largest log-scale) above this
+ * Of a redundant pair the dominated Gaussian is marked (smaller opacity
+ * logit; equal logits: the larger index), so one of the two survives.
+ * Non-finite means, logits or log-scales fail the geometric test.
+ * Uses means, log_scales, opacity_logits and feat of `g` (rgb unused).
+ *   mask    device uint8 [n]: bit 0 redundant (Eq. (4)), bit 1 geometric;
+ *           prune where non-zero (overwritten)
+ *   counts  NULL or host int64 [3]: redundant, geometric, pruned (either)
+ * Distances and similarities are evaluated in FP64.  Synchronises with
+ * `stream` (two small readbacks).  LGS_ERR_INVALID_ARG for bad parameters
+ * or NULL arrays; LGS_ERR_UNSUPPORTED when a mean lies more than 2^20 cells
+ * of tau_dist from the origin along an axis. */
+typedef struct {
+  int32_t k;
+  float tau_dist, tau_sim, min_opacity, max_scale;
+} lgs_prune_params;
+lgs_prune_params lgs_default_prune_params(void);
+lgs_status lgs_prune(lgs_context *ctx, const lgs_gaussians *g,
+                     const lgs_prune_params *params, uint8_t *mask,
+                     int64_t counts[3], hipStream_t stream);
+
 lgs_status lgs_state_counts(const lgs_fwd_state *state, lgs_counts *out);
 /* With settings.profile = 1 on the forward, after its backward: elapsed
  * milliseconds of ms[0..4] = projection + depth sort + scans, pair emission

@@ -50,12 +50,12 @@ def geometric(means, logits, log_scales, min_opacity, max_scale):
 
 
 def prune(means, feat, logits, log_scales, k=16, tau_dist=0.02, tau_sim=0.9, min_opacity=0.005,
-          max_scale=0.3, extra=48, want_margins=False):
+          max_scale=0.3, extra=48, want_margins=False, rows=1 << 16):
     """means [N,3], feat [N,D], logits [N], log_scales [N,3] (any float
     dtype).  Returns (semantic [N] bool, geometric [N] bool) and, with
     want_margins, per Gaussian i the smallest relative margin of any decision
     it takes (distance vs tau_dist, the K-th / (K+1)-th distance order,
-    similarity vs tau_sim)."""
+    similarity vs tau_sim).  Rows are processed `rows` Gaussians at a time."""
     P = np.asarray(means, np.float64)
     Fe = np.asarray(feat, np.float64)
     lam = np.asarray(logits, np.float64)
@@ -68,36 +68,51 @@ def prune(means, feat, logits, log_scales, k=16, tau_dist=0.02, tau_sim=0.9, min
     if len(idx) < 2:
         return (sem, geo, margin) if want_margins else (sem, geo)
     tree = cKDTree(P[idx])
-    q = min(len(idx), k + 1 + extra)
-    dist, nb = tree.query(P[idx], k=q, distance_upper_bound=tau_dist * 1.001)
-    nb = np.where(np.isfinite(dist), nb, len(idx))
-    if q == k + 1 + extra and np.isfinite(dist[:, -1]).any():
-        raise RuntimeError("neighbour query saturated: raise `extra`")
     tau2 = tau_dist * tau_dist
     norm = np.sqrt((Fe * Fe).sum(1))
-    for r, i in enumerate(idx):
-        cand = nb[r][nb[r] < len(idx)]
-        js = idx[cand]
-        js = js[js != i]
-        if len(js) == 0:
-            continue
-        d = P[js] - P[i]
-        d2 = d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1] + d[:, 2] * d[:, 2]
+    for r0 in range(0, len(idx), rows):
+        ii = idx[r0:r0 + rows]
+        q = min(len(idx), k + 1 + extra)
+        while True:   # enough candidates to hold every neighbour within the threshold
+            dist, nb = tree.query(P[ii], k=q, distance_upper_bound=tau_dist * 1.001)
+            if q == len(idx) or not np.isfinite(dist[:, -1]).any():
+                break
+            q = min(len(idx), 2 * q)
+        ok = np.isfinite(dist)
+        js = np.where(ok, idx[np.minimum(nb, len(idx) - 1)], -1)
+        ok &= js != ii[:, None]                                   # not itself
+        d = P[np.maximum(js, 0)] - P[ii][:, None, :]
+        d2 = d[..., 0] * d[..., 0] + d[..., 1] * d[..., 1] + d[..., 2] * d[..., 2]
         if want_margins:
-            margin[i] = min(margin[i], np.min(np.abs(d2 - tau2)) / tau2)
-        keep = d2 < tau2
-        js, d2 = js[keep], d2[keep]
-        order = np.lexsort((js, d2))
-        js, d2 = js[order], d2[order]
-        if want_margins and len(d2) > k:
-            margin[i] = min(margin[i], (d2[k] - d2[k - 1]) / tau2)
-        js = js[:k]
-        den = norm[i] * norm[js]
-        sim = np.where(den > 0, (Fe[js] @ Fe[i]) / np.where(den > 0, den, 1.0), 0.0)
+            dm = np.where(ok, np.abs(d2 - tau2) / tau2, np.inf).min(1)
+            margin[ii] = np.minimum(margin[ii], dm)
+        ok &= d2 < tau2
+        # order each row by (squared distance, index); invalid entries last
+        key_d = np.where(ok, d2, np.inf)
+        key_j = np.where(ok, js, np.iinfo(np.int64).max)
+        order = np.lexsort((key_j, key_d), axis=1)
+        key_d = np.take_along_axis(key_d, order, 1)
+        js = np.take_along_axis(np.where(ok, js, -1), order, 1)
+        if want_margins and dist.shape[1] > k:
+            # an exact tie (equal squared distances, e.g. duplicate means) is
+            # the same on both sides and broken by index; only a near tie is a
+            # decision that rounding could flip
+            with np.errstate(invalid="ignore"):
+                gap = (key_d[:, k] - key_d[:, k - 1]) / tau2
+            margin[ii] = np.minimum(margin[ii], np.where(np.isfinite(gap) & (gap > 0), gap, np.inf))
+        js = js[:, :k]
+        valid = js >= 0
+        jj = np.maximum(js, 0)
+        den = norm[ii][:, None] * norm[jj]
+        dot = np.einsum("rkd,rd->rk", Fe[jj], Fe[ii])
+        sim = np.where(den > 0, dot / np.where(den > 0, den, 1.0), 0.0)
         if want_margins:
-            margin[i] = min(margin[i], np.min(np.abs(sim - tau_sim)))
-        dom = (lam[i] > lam[js]) | ((lam[i] == lam[js]) & (i < js))
-        sem[js[(sim > tau_sim) & dom]] = True
+            sm = np.where(valid, np.abs(sim - tau_sim), np.inf).min(1)
+            margin[ii] = np.minimum(margin[ii], sm)
+        li, lj = lam[ii][:, None], lam[jj]
+        dom = (li > lj) | ((li == lj) & (ii[:, None] < jj))
+        hit = valid & (sim > tau_sim) & dom
+        sem[jj[hit]] = True
     return (sem, geo, margin) if want_margins else (sem, geo)
 
 

@@ -49,6 +49,11 @@ class lgs_grads(C.Structure):
                 ("twist", C.c_void_p)]
 
 
+class lgs_prune_params(C.Structure):
+    _fields_ = [("k", C.c_int32), ("tau_dist", C.c_float), ("tau_sim", C.c_float), ("min_opacity", C.c_float),
+                ("max_scale", C.c_float)]
+
+
 class lgs_counts(C.Structure):
     _fields_ = [("n_visible", C.c_int64), ("n_pairs", C.c_int64), ("n_slots", C.c_int64),
                 ("n_tiles", C.c_int64), ("n_items", C.c_int64), ("fwd_evals", C.c_int64),
@@ -57,6 +62,7 @@ class lgs_counts(C.Structure):
 
 EXPORTS = ["lgs_status_string", "lgs_last_error", "lgs_default_settings", "lgs_context_create",
            "lgs_context_destroy", "lgs_forward", "lgs_backward", "lgs_backward_l1", "lgs_loss", "lgs_decoder_l1",
+           "lgs_default_prune_params", "lgs_prune",
            "lgs_state_counts",
            "lgs_state_stage_ms",
            "lgs_state_release", "lgs_graph_create", "lgs_graph_launch", "lgs_graph_status",
@@ -94,6 +100,11 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.lgs_decoder_l1.restype = C.c_int
     lib.lgs_decoder_l1.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, P, P, P, P, C.c_int32, C.c_float,
                                    P, P, P, P, P]
+    lib.lgs_default_prune_params.restype = lgs_prune_params
+    lib.lgs_default_prune_params.argtypes = []
+    lib.lgs_prune.restype = C.c_int
+    lib.lgs_prune.argtypes = [P, C.POINTER(lgs_gaussians), C.POINTER(lgs_prune_params), P,
+                              C.POINTER(C.c_int64), P]
     lib.lgs_state_counts.restype = C.c_int
     lib.lgs_state_counts.argtypes = [P, C.POINTER(lgs_counts)]
     lib.lgs_state_stage_ms.restype = C.c_int
@@ -307,6 +318,26 @@ class Context:
         if st != LGS_OK:
             self._raise(st)
         return loss, gf, gw, gb
+
+    def prune(self, params, k=None, tau_dist=None, tau_sim=None, min_opacity=None, max_scale=None,
+              stream=None, mask=None):
+        """Language-guided + geometric pruning (lgs_prune).  params: the
+        Gaussian tensors (as for forward).  Returns (mask [N] uint8: bit 0
+        redundant, bit 1 geometric; counts (redundant, geometric, pruned))."""
+        g = gaussians_c(params["means"], params["log_scales"], params["quats"], params["logits"],
+                        params["rgb"], params["feat"])
+        p = lib().lgs_default_prune_params()
+        for name, v in (("k", k), ("tau_dist", tau_dist), ("tau_sim", tau_sim), ("min_opacity", min_opacity),
+                        ("max_scale", max_scale)):
+            if v is not None:
+                setattr(p, name, v)
+        if mask is None:
+            mask = torch.empty(g.n, dtype=torch.uint8, device=params["means"].device)
+        cnt = (C.c_int64 * 3)()
+        st = lib().lgs_prune(self._h, C.byref(g), C.byref(p), _ptr(mask), cnt, _stream(stream))
+        if st != LGS_OK:
+            self._raise(st)
+        return mask, tuple(cnt)
 
     def backward(self, state: "State", params, grad_outs, stream=None) -> dict:
         """grad_outs: per view dict rgb [3,H,W], depth [H,W], feat [16,H,W],

@@ -22,7 +22,7 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-munsafe-fp-atomics", "-Wno-unused-command-line-argument", "-Wno-unused-result",
          "-I", os.path.join(HERE, "..", "include")]
 
-SOURCES = ["project.hip", "binning.hip", "radix_sort.hip", "raster.hip", "loss.hip", "decoder.hip", "runtime.hip"]
+SOURCES = ["project.hip", "binning.hip", "radix_sort.hip", "raster.hip", "loss.hip", "decoder.hip", "prune.hip", "runtime.hip"]
 
 
 def _hipcc() -> str:

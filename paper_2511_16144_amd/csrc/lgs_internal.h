@@ -214,6 +214,25 @@ bool decoder_dim_ok(int C);
 int decoder_grid(int64_t n);
 void launch_decoder(const DecArgs& a, const void* target, int target_bf16, float* part, int grid, hipStream_t s);
 
+// language-guided pruning (K nearest neighbours in a uniform grid of cell
+// side tau_dist) and the geometric criteria
+struct PruneArgs {
+  const float *means, *logits, *log_scales;   // [3][n], [n], [3][n]
+  const void* feat;                           // [16][n], FP32 or BF16
+  int32_t feat_bf16, k;                       // k <= prune_k_max()
+  int64_t n, n_valid;                         // Gaussians; those with a grid cell (sorted first)
+  double tau2, inv_cell, tau_sim;             // tau_dist^2, 1 / tau_dist, tau_sim
+  double logit_min, log_scale_max;            // log(o / (1 - o)) of min_opacity, log(max_scale)
+};
+int prune_k_max();
+size_t prune_temp_bytes(int64_t n);
+void launch_prune_keys(const PruneArgs& a, uint64_t* keys, uint32_t* vals, uint8_t* geo, uint32_t* range_err,
+                       hipStream_t s);
+void launch_prune_count_valid(const uint64_t* keys, int64_t n, int64_t* n_valid, hipStream_t s);
+void launch_prune_knn(const PruneArgs& a, const uint64_t* keys, const uint32_t* vals, uint8_t* sem, hipStream_t s);
+void launch_prune_final(int64_t n, const uint8_t* sem, const uint8_t* geo, uint8_t* mask,
+                        unsigned long long* counts, hipStream_t s);
+
 // gradient reduction and projection backward
 void launch_seg_reduce(const uint32_t* slot_off, const float* partials, const uint8_t* mask,
                        const Counters* cnt, int64_t n_max, float* grad2d, hipStream_t s);

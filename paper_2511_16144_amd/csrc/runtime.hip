@@ -894,6 +894,102 @@ lgs_status lgs_decoder_l1(lgs_context* ctx, int32_t width, int32_t height, int32
   return LGS_OK;
 }
 
+lgs_prune_params lgs_default_prune_params(void) {
+  lgs_prune_params p;
+  p.k = 16;
+  p.tau_dist = 0.02f;
+  p.tau_sim = 0.9f;
+  p.min_opacity = 0.005f;
+  p.max_scale = 0.3f;
+  return p;
+}
+
+lgs_status lgs_prune(lgs_context* ctx, const lgs_gaussians* g, const lgs_prune_params* prm, uint8_t* mask,
+                     int64_t counts[3], hipStream_t stream) {
+  if (!ctx) return LGS_ERR_INVALID_ARG;
+  ctx->err.clear();
+  lgs_status rc;
+  if ((rc = check_gaussians(ctx, g)) != LGS_OK) return rc;
+  if (!prm) return fail(ctx, LGS_ERR_INVALID_ARG, "params is NULL");
+  if (prm->k < 1 || prm->k > prune_k_max()) return fail(ctx, LGS_ERR_INVALID_ARG, "k must be in [1, 32]");
+  if (!(prm->tau_dist > 0.f) || !isfinite(prm->tau_dist) || !isfinite(prm->tau_sim) ||
+      !(prm->min_opacity > 0.f && prm->min_opacity < 1.f) || !(prm->max_scale > 0.f))
+    return fail(ctx, LGS_ERR_INVALID_ARG, "pruning thresholds out of range");
+  if (g->n > 0 && !mask) return fail(ctx, LGS_ERR_INVALID_ARG, "mask is NULL");
+  if (counts) counts[0] = counts[1] = counts[2] = 0;
+  if (g->n == 0) return LGS_OK;
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  (void)hipGetLastError();   // launch checks below see only this call's errors
+  const int64_t n = g->n;
+  std::vector<void*> held;
+  auto take = [&](size_t bytes) {
+    void* p = pool_alloc(ctx, bytes);
+    if (p) held.push_back(p);
+    return p;
+  };
+  auto release = [&]() {
+    for (void* p : held) pool_free(ctx, p);
+  };
+  uint64_t* keys = (uint64_t*)take(8 * n);
+  uint64_t* keys_b = (uint64_t*)take(8 * n);
+  uint32_t* vals = (uint32_t*)take(4 * n);
+  uint32_t* vals_b = (uint32_t*)take(4 * n);
+  uint8_t* geo = (uint8_t*)take(n);
+  uint8_t* sem = (uint8_t*)take(n);
+  void* temp = take(prune_temp_bytes(n));
+  // small device words: range flag (u32), pad, valid count (i64), counts (3 x u64)
+  unsigned char* misc = (unsigned char*)take(64);
+  if (!keys || !keys_b || !vals || !vals_b || !geo || !sem || !temp || !misc) {
+    release();
+    return fail(ctx, LGS_ERR_HIP, "device allocation failed (pruning)");
+  }
+  uint32_t* range_err = (uint32_t*)misc;
+  int64_t* n_valid_d = (int64_t*)(misc + 8);
+  unsigned long long* counts_d = (unsigned long long*)(misc + 16);
+  PruneArgs a;
+  a.means = g->means; a.logits = g->opacity_logits; a.log_scales = g->log_scales; a.feat = g->feat;
+  a.feat_bf16 = g->appearance_dtype == LGS_BF16;
+  a.k = prm->k;
+  a.n = n;
+  a.n_valid = 0;
+  const double tau = (double)prm->tau_dist;
+  a.tau2 = tau * tau;
+  a.inv_cell = 1.0 / tau;
+  a.tau_sim = (double)prm->tau_sim;
+  a.logit_min = log((double)prm->min_opacity / (1.0 - (double)prm->min_opacity));
+  a.log_scale_max = log((double)prm->max_scale);
+  auto run = [&]() -> lgs_status {
+    HIP_TRY(ctx, hipMemsetAsync(misc, 0, 64, stream));
+    HIP_TRY(ctx, hipMemsetAsync(sem, 0, n, stream));
+    launch_prune_keys(a, keys, vals, geo, range_err, stream);
+    bool alt = false;
+    radix_sort_u64(keys, vals, keys_b, vals_b, nullptr, n, 0, 64, temp, stream, &alt);
+    const uint64_t* sk = alt ? keys_b : keys;
+    const uint32_t* sv = alt ? vals_b : vals;
+    launch_prune_count_valid(sk, n, n_valid_d, stream);
+    HIP_TRY(ctx, hipGetLastError());
+    int64_t hv[2] = {0, 0};
+    HIP_TRY(ctx, hipMemcpyAsync(hv, misc, 16, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(ctx, hipStreamSynchronize(stream));
+    if ((uint32_t)hv[0] != 0u)
+      return fail(ctx, LGS_ERR_UNSUPPORTED, "a mean lies more than 2^20 cells of tau_dist from the origin");
+    a.n_valid = hv[1];
+    launch_prune_knn(a, sk, sv, sem, stream);
+    launch_prune_final(n, sem, geo, mask, counts_d, stream);
+    HIP_TRY(ctx, hipGetLastError());
+    unsigned long long hc[3] = {0, 0, 0};
+    HIP_TRY(ctx, hipMemcpyAsync(hc, counts_d, sizeof hc, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(ctx, hipStreamSynchronize(stream));
+    if (counts)
+      for (int i = 0; i < 3; ++i) counts[i] = (int64_t)hc[i];
+    return LGS_OK;
+  };
+  rc = run();
+  if (rc != LGS_OK) hipStreamSynchronize(stream);   // queued work may still use the buffers
+  release();
+  return rc;
+}
+
 // ---------------------------------------------------------------------------
 // whole-step graph
 // ---------------------------------------------------------------------------

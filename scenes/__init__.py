@@ -351,3 +351,26 @@ def decoder_inputs(seed: int, W: int, H: int, C: int = 512):
     b = rng.normal(0.0, 0.05, size=C).astype(np.float32)
     G = rng.normal(0.0, 0.25, size=(C, H, W)).astype(np.float32)
     return F, Wm, b, G
+
+
+def prune_scene(seed: int, n: int = 500_000, objects: int = 64, spread: float = 0.08) -> Scene:
+    """The batched workload's room-surface Gaussians with language features
+    that follow objects: the room is split among `objects` random centres
+    (each point belongs to its nearest centre), each object has a random unit
+    feature, and a point's feature is that vector plus N(0, spread) noise per
+    component, normalised (neighbours on one object then have cosine
+    similarity near 1 / (1 + 16 spread^2)).  Appearance stored in BF16."""
+    wl = make_workload(4, n=n, with_targets=False)
+    sc = wl.scene
+    rng = np.random.Generator(np.random.PCG64(13000 + seed))
+    centres = rng.uniform([-3.0, -3.0, 0.0], [3.0, 3.0, 3.0], size=(objects, 3))
+    obj = np.empty(n, np.int64)
+    for s0 in range(0, n, 65536):
+        d = ((sc.means[s0:s0 + 65536, None, :].astype(np.float64) - centres[None]) ** 2).sum(-1)
+        obj[s0:s0 + 65536] = d.argmin(1)
+    base = rng.normal(size=(objects, 16))
+    base /= np.linalg.norm(base, axis=1, keepdims=True)
+    f = base[obj] + rng.normal(0.0, spread, size=(n, 16))
+    f /= np.linalg.norm(f, axis=1, keepdims=True)
+    f = f.astype(np.float32)
+    return Scene(sc.means, sc.log_scales, sc.quats, sc.logits, sc.rgb, round_bf16(f), "bf16", sc.rgb_unrounded, f)
