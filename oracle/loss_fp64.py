@@ -77,7 +77,7 @@ def ssim_map(X: torch.Tensor, Y: torch.Tensor, radius: int = SSIM_RADIUS, sigma:
 def view_terms(out: dict, tgt, lam: float):
     """The four per-view terms as torch scalars: mean|I - I*|, 1 - SSIM
     (None when lam = 0: not evaluated), mean|D - D*|, mean|F - F*|.  `out`
-    holds torch tensors (rgb [3,H,W], depth [H,W], feat [16,H,W]); `tgt` has
+    holds torch tensors (rgb [3,H,W], depth [H,W], feat [D,H,W]); `tgt` has
     numpy arrays of the same shapes."""
     trgb = torch.as_tensor(np.asarray(tgt.rgb, np.float64))
     l1 = (out["rgb"] - trgb).abs().mean()
@@ -89,7 +89,7 @@ def view_terms(out: dict, tgt, lam: float):
 
 def loss_and_upstream(outs, targets, loss_w, lam: float = SSIM_LAMBDA):
     """L_total summed over views, its per-view terms, and dL/dY per view as
-    [20, H, W] float64 arrays (RGB 3, depth 1, feature 16).  `outs` are the
+    [4 + D, H, W] float64 arrays (RGB 3, depth 1, feature D).  `outs` are the
     rendered images (numpy, any float dtype), `targets` the observed ones."""
     L = torch.zeros((), dtype=F64)
     leaves, terms = [], []

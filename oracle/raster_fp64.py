@@ -26,7 +26,7 @@ paper is silent are marked [reading]:
       alpha >= 1/255, ordered by (z, index) ascending [reading].
   O11 front to back: T' = T (1 - alpha); if T' < 1e-4 stop before this
       Gaussian [reading]; else w = alpha T, Y += w [c, z, f], T = T'.
-      Y = [RGB (3), depth (1), feature (16)]; background 0; outputs Y, the
+      Y = [RGB (3), depth (1), feature (D)]; background 0; outputs Y, the
       final transmittance T and the contributor count n.
   O12 colour is per-Gaussian RGB (spherical-harmonics degree 0, no view
       dependence) [reading]; depth is the unnormalised sum w z [reading];
@@ -100,7 +100,7 @@ def project_view(P: dict, cam, xi: torch.Tensor, st: Settings) -> dict:
     """Per-Gaussian screen-space quantities for one camera.
 
     P holds float64 tensors: means [N,3], log_scales [N,3], quats [N,4],
-    logits [N], rgb [N,3], feat [N,16].  Returns mu [N,2], conic [N,3]
+    logits [N], rgb [N,3], feat [N,D].  Returns mu [N,2], conic [N,3]
     (Q_xx, Q_xy, Q_yy), cov2d [N,3] (Sigma'_xx, Sigma'_xy, Sigma'_yy),
     opac [N], z [N], vis [N] bool (culling decision) and clampx/clampy [N]
     bool (Jacobian clamp sides, for decision signatures)."""
@@ -165,9 +165,9 @@ def composite(px: torch.Tensor, py: torch.Tensor, mu, conic, opac, z, y, ids,
     """Composite K candidate Gaussians over P pixels.
 
     px, py [P] pixel centres; mu [K,2], conic [K,3], opac [K], z [K],
-    y [K,20] = [rgb, z, feat]; ids [K] Gaussian indices (tie-break).
-    Candidates may be in any order; they are sorted by (z, id) here.
-    Returns Y [P,20], T [P], n [P], and (want_margin) a dict of each
+    y [K,C] = [rgb, z, feat] (C = 4 + the feature dimension); ids [K]
+    Gaussian indices (tie-break).  Candidates may be in any order; they are
+    sorted by (z, id) here.  Returns Y [P,C], T [P], n [P], and (want_margin) a dict of each
     pixel's smallest relative distance to every kind of discrete decision:
     "m2" (m2 vs cutoff2), "alpha" (alpha vs alpha_min), "clamp" (o G vs
     alpha_max), "T" (T' vs T_eps) over the candidates up to the one that ends
@@ -176,7 +176,7 @@ def composite(px: torch.Tensor, py: torch.Tensor, mu, conic, opac, z, y, ids,
     K = mu.shape[0]
     P = px.shape[0]
     if K == 0:
-        Y = torch.zeros((P, 20), dtype=F64)
+        Y = torch.zeros((P, y.shape[1]), dtype=F64)
         mg = {k: torch.full((P,), math.inf, dtype=F64) for k in ("m2", "alpha", "clamp", "T", "z")}
         if sig is not None:
             sig.append(torch.zeros(P, dtype=torch.int64))
@@ -295,13 +295,14 @@ def _candidates(proj, blk, st, pad=1.0):
 
 
 def _y_of(P, proj):
-    return torch.cat([P["rgb"], proj["z"][:, None], P["feat"]], 1)   # [N, 20]
+    return torch.cat([P["rgb"], proj["z"][:, None], P["feat"]], 1)   # [N, 4 + D]
 
 
 def render(scene, cams, st: Settings = Settings(), rects=None, block=16,
            want_margin=True) -> list:
     """Forward render of every view.  Returns one dict per view with
-    rgb [3,H,W], depth [H,W], feat [16,H,W], T [H,W], n [H,W] (int64),
+    rgb [3,H,W], depth [H,W], feat [D,H,W] (D = the scene's feature
+    dimension), T [H,W], n [H,W] (int64),
     margin {kind: [H,W]} (see ``composite``; inf where not evaluated) and the
     per-Gaussian projection (mu, conic, cov2d, opac, z, vis); pixels outside
     `rects` (per view list of (x0, y0, w, h)) are NaN."""
@@ -311,8 +312,9 @@ def render(scene, cams, st: Settings = Settings(), rects=None, block=16,
         for vi, cam in enumerate(cams):
             proj = project_view(P, cam, torch.zeros(6, dtype=F64), st)
             y = _y_of(P, proj)
+            C = y.shape[1]
             H, W = cam.height, cam.width
-            Y = torch.full((20, H, W), math.nan, dtype=F64)
+            Y = torch.full((C, H, W), math.nan, dtype=F64)
             T = torch.full((H, W), math.nan, dtype=F64)
             n = torch.full((H, W), -1, dtype=torch.int64)
             mg = {k: torch.full((H, W), math.inf, dtype=F64)
@@ -327,7 +329,7 @@ def render(scene, cams, st: Settings = Settings(), rects=None, block=16,
                                            proj["opac"][cand], proj["z"][cand], y[cand],
                                            cand, st, want_margin)
                 h, w = y1 - y0, x1 - x0
-                Y[:, y0:y1, x0:x1] = Yb.T.reshape(20, h, w)
+                Y[:, y0:y1, x0:x1] = Yb.T.reshape(C, h, w)
                 T[y0:y1, x0:x1] = Tb.reshape(h, w)
                 n[y0:y1, x0:x1] = nb.reshape(h, w)
                 if mb is not None:
@@ -347,16 +349,17 @@ def vjp(scene, cams, upstream, st: Settings = Settings(), upstream_T=None,
         rects=None, block=16) -> dict:
     """Vector-Jacobian product of the renderer.
 
-    upstream: per view [20, H, W] arrays dL/dY (RGB, depth, feature);
+    upstream: per view [4 + D, H, W] arrays dL/dY (RGB, depth, feature);
     upstream_T: optional per view [H, W] dL/dT.  Only pixels inside `rects`
     (per view; default: whole image) are evaluated, so the upstream gradient
     must vanish elsewhere.  Returns float64 numpy gradients: means [N,3],
-    log_scales [N,3], quats [N,4], logits [N], rgb [N,3], feat [N,16],
+    log_scales [N,3], quats [N,4], logits [N], rgb [N,3], feat [N,D],
     twist [V,6] (rho, phi)."""
     P = _params(scene, requires_grad=True)
     N = scene.n
     g_rgb = torch.zeros((N, 3), dtype=F64)
-    g_feat = torch.zeros((N, 16), dtype=F64)
+    D = scene.feat.shape[1]
+    g_feat = torch.zeros((N, D), dtype=F64)
     twist = []
     for vi, cam in enumerate(cams):
         xi = torch.zeros(6, dtype=F64, requires_grad=True)
@@ -368,7 +371,7 @@ def vjp(scene, cams, upstream, st: Settings = Settings(), upstream_T=None,
         upT = None if upstream_T is None else _t(upstream_T[vi])
         for blk in _blocks(cam, None if rects is None else rects[vi], block):
             x0, y0, x1, y1 = blk
-            gb = up[:, y0:y1, x0:x1].reshape(20, -1).T
+            gb = up[:, y0:y1, x0:x1].reshape(4 + D, -1).T
             gT = None if upT is None else upT[y0:y1, x0:x1].reshape(-1)
             if not bool(gb.abs().sum() > 0) and (gT is None or not bool(gT.abs().sum() > 0)):
                 continue
@@ -424,14 +427,15 @@ def l1_loss(outs, targets, loss_w) -> float:
 
 def l1_upstream(outs, targets, loss_w) -> list:
     """dL/dY of ``l1_loss``: w_group sign(Y - Y*) / n_group with sign(0) = 0,
-    as per-view [20, H, W] float64 arrays."""
+    as per-view [4 + D, H, W] float64 arrays."""
     gs = []
     for o, t in zip(outs, targets):
         H, W = t.depth.shape
-        g = np.empty((20, H, W))
+        D = t.feat.shape[0]
+        g = np.empty((4 + D, H, W))
         g[:3] = loss_w[0] * np.sign(o["rgb"] - t.rgb) / (3 * H * W)
         g[3] = loss_w[1] * np.sign(o["depth"] - t.depth) / (H * W)
-        g[4:] = loss_w[2] * np.sign(o["feat"] - t.feat) / (16 * H * W)
+        g[4:] = loss_w[2] * np.sign(o["feat"] - t.feat) / (D * H * W)
         gs.append(g)
     return gs
 

@@ -130,14 +130,14 @@ def round_bf16(x: np.ndarray) -> np.ndarray:
 # Gaussian parameter draws (draw order: means, log-scales, quats, logits,
 # RGB, features; then cameras; then targets)
 # --------------------------------------------------------------------------
-def _draw_attributes(rng, n):
+def _draw_attributes(rng, n, feat_dim=16):
     log_scales = rng.normal(-3.0, 0.5, size=(n, 3)).astype(np.float32)
     quats = rng.normal(0.0, 1.0, size=(n, 4))
     quats /= np.linalg.norm(quats, axis=1, keepdims=True)
     quats = quats.astype(np.float32)
     logits = rng.normal(0.0, 1.0, size=n).astype(np.float32)
     rgb = rng.uniform(0.0, 1.0, size=(n, 3)).astype(np.float32)
-    feat = rng.normal(0.0, 1.0, size=(n, 16))
+    feat = rng.normal(0.0, 1.0, size=(n, feat_dim))
     feat /= np.linalg.norm(feat, axis=1, keepdims=True)
     feat = feat.astype(np.float32)
     return log_scales, quats, logits, rgb, feat
@@ -179,19 +179,21 @@ def _yaw_camera(center, yaw, W, H, f, cx, cy) -> Camera:
                   R_cw.astype(np.float32), t_cw.astype(np.float32))
 
 
-def _draw_targets(rng, cam: Camera, depth_range) -> Targets:
+def _draw_targets(rng, cam: Camera, depth_range, feat_dim=16) -> Targets:
     H, W = cam.height, cam.width
     rgb = rng.uniform(0.0, 1.0, size=(3, H, W)).astype(np.float32)
     depth = rng.uniform(depth_range[0], depth_range[1], size=(H, W)).astype(np.float32)
-    f = rng.normal(0.0, 1.0, size=(16, H, W))
+    f = rng.normal(0.0, 1.0, size=(feat_dim, H, W))
     f /= np.linalg.norm(f, axis=0, keepdims=True)
     return Targets(rgb, depth, f.astype(np.float32))
 
 
 def make_workload(k: int, n: int | None = None, res_scale: float = 1.0,
-                  with_targets: bool = True) -> Workload:
+                  with_targets: bool = True, feat_dim: int = 16) -> Workload:
     """Config k in 1..5 with its default sizes, or smaller ones for parity
-    tests (`n` Gaussians, image sides times `res_scale`).  Seed = k."""
+    tests (`n` Gaussians, image sides times `res_scale`).  Seed = k.
+    `feat_dim` sets the language-feature dimension (16 in every config; the
+    feature-dimension sweep varies it)."""
     rng = np.random.Generator(np.random.PCG64(k))
 
     def sz(w, h):
@@ -206,7 +208,7 @@ def make_workload(k: int, n: int | None = None, res_scale: float = 1.0,
         u = rng.uniform(-0.5, W - 0.5, size=n)
         v = rng.uniform(-0.5, H - 0.5, size=n)
         means = np.stack([(u - cx) * z / f, (v - cy) * z / f, z], 1).astype(np.float32)
-        attrs = _draw_attributes(rng, n)
+        attrs = _draw_attributes(rng, n, feat_dim)
         cams = [Camera(W, H, float(np.float32(f)), float(np.float32(f)),
                        float(np.float32(cx)), float(np.float32(cy)),
                        np.eye(3, dtype=np.float32), np.zeros(3, np.float32))]
@@ -221,7 +223,7 @@ def make_workload(k: int, n: int | None = None, res_scale: float = 1.0,
         W, H = sz(W0, H0)
         f = f0 * res_scale
         means = _room_surface_points(rng, n)
-        attrs = _draw_attributes(rng, n)
+        attrs = _draw_attributes(rng, n, feat_dim)
         center = rng.uniform([-2.5, -2.5, 0.5], [2.5, 2.5, 2.5])
         yaw = rng.uniform(0.0, 2.0 * math.pi)
         cams = [_yaw_camera(center, yaw, W, H, f, (W - 1) / 2.0, (H - 1) / 2.0)]
@@ -229,7 +231,7 @@ def make_workload(k: int, n: int | None = None, res_scale: float = 1.0,
     elif k == 4:
         n = 500_000 if n is None else n
         means = _room_surface_points(rng, n)
-        attrs = _draw_attributes(rng, n)
+        attrs = _draw_attributes(rng, n, feat_dim)
         cams = []
         for v in range(8):
             ang = 2.0 * math.pi * v / 8.0
@@ -249,7 +251,7 @@ def make_workload(k: int, n: int | None = None, res_scale: float = 1.0,
     if dtype == "bf16":
         scene = Scene(means, log_scales, quats, logits, round_bf16(rgb),
                       round_bf16(feat), "bf16", rgb, feat)
-    targets = [_draw_targets(rng, c, drange) for c in cams] if with_targets else []
+    targets = [_draw_targets(rng, c, drange, feat_dim) for c in cams] if with_targets else []
     return Workload(CONFIG_NAMES[k] if (n is None or res_scale == 1.0) else
                     f"C{k} reduced: {n} Gaussians, x{res_scale:g} resolution",
                     scene, cams, targets, loss_w,
@@ -278,14 +280,14 @@ def tiny_scene(seed: int, n: int, W: int, H: int, f: float = 40.0,
     return Workload(f"tiny seed={seed} n={n} {W}x{H}", scene, [cam], [tg])
 
 
-def random_upstream(seed: int, cams, windows=None) -> list:
-    """Seeded upstream gradients dL/dY per view: [20, H, W] float32
-    (RGB 3, depth 1, feature 16).  With `windows` (list per view of
+def random_upstream(seed: int, cams, windows=None, feat_dim: int = 16) -> list:
+    """Seeded upstream gradients dL/dY per view: [4 + feat_dim, H, W] float32
+    (RGB 3, depth 1, feature feat_dim).  With `windows` (list per view of
     (x0, y0, w, h) rectangles) the gradient is zero outside them."""
     rng = np.random.Generator(np.random.PCG64(7000 + seed))
     out = []
     for vi, c in enumerate(cams):
-        g = rng.normal(0.0, 1.0, size=(20, c.height, c.width)).astype(np.float32)
+        g = rng.normal(0.0, 1.0, size=(4 + feat_dim, c.height, c.width)).astype(np.float32)
         if windows is not None:
             m = np.zeros((c.height, c.width), bool)
             for (x0, y0, w, h) in windows[vi]:

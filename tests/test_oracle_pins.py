@@ -513,3 +513,40 @@ def test_margin_flags_depth_near_ties():
         o = R.render(sc, [cam], ST)[0]
         assert o["n"][4, 4] == 2
         assert lo <= o["margin"]["z"][4, 4] <= hi
+
+
+def _with_feat(sc, feat):
+    return scenes.Scene(sc.means, sc.log_scales, sc.quats, sc.logits, sc.rgb, np.ascontiguousarray(feat, np.float32),
+                        "f32")
+
+
+def test_feature_dimension_is_a_set_of_independent_groups():
+    # The feature channels do not enter the blend weights: a 32-d render is
+    # the two 16-d renders of its halves side by side, and its gradient is
+    # the sum over the halves (the second half carrying no colour or depth
+    # upstream).  An 8-d render is a 16-d render with the last 8 channels 0.
+    wl = scenes.tiny_scene(3, 24, 20, 16)
+    cams, sc = wl.cams, wl.scene
+    rng = np.random.Generator(np.random.PCG64(77))
+    f32 = rng.normal(size=(sc.n, 32)).astype(np.float32)
+    full = R.render(_with_feat(sc, f32), cams, want_margin=False)[0]
+    a = R.render(_with_feat(sc, f32[:, :16]), cams, want_margin=False)[0]
+    b = R.render(_with_feat(sc, f32[:, 16:]), cams, want_margin=False)[0]
+    for k in ("rgb", "depth", "T"):
+        assert np.array_equal(full[k], a[k]) and np.array_equal(full[k], b[k])
+    assert np.array_equal(full["feat"], np.concatenate([a["feat"], b["feat"]], 0))
+    up = rng.normal(size=(36, 16, 20))
+    g = R.vjp(_with_feat(sc, f32), cams, [up])
+    ua = up[:20].copy()
+    ub = np.concatenate([np.zeros((4, 16, 20)), up[20:]], 0)
+    ga = R.vjp(_with_feat(sc, f32[:, :16]), cams, [ua])
+    gb = R.vjp(_with_feat(sc, f32[:, 16:]), cams, [ub])
+    for k in ("means", "log_scales", "quats", "logits", "twist"):
+        assert np.allclose(g[k], ga[k] + gb[k], rtol=1e-12, atol=1e-14), k
+    assert np.allclose(g["rgb"], ga["rgb"], rtol=1e-12, atol=1e-15)
+    assert np.allclose(g["feat"], np.concatenate([ga["feat"], gb["feat"]], 1), rtol=1e-12, atol=1e-15)
+    f8 = f32[:, :8]
+    r8 = R.render(_with_feat(sc, f8), cams, want_margin=False)[0]
+    r16 = R.render(_with_feat(sc, np.concatenate([f8, np.zeros((sc.n, 8), np.float32)], 1)), cams,
+                   want_margin=False)[0]
+    assert np.array_equal(r8["feat"], r16["feat"][:8]) and not r16["feat"][8:].any()
