@@ -88,13 +88,14 @@ def time_workload(ctx, wl, steps, warmup, dev, tune, settings):
     params = P.params_from_arrays(s.means, s.log_scales, s.quats, s.logits, s.rgb, s.feat, device=dev,
                                   appearance_dtype=dt)
     V = len(wl.cams)
+    D = wl.scene.feat.shape[1]
     outs = [{"rgb": torch.empty((3, c.height, c.width), device=dev),
              "depth": torch.empty((c.height, c.width), device=dev),
-             "feat": torch.empty((16, c.height, c.width), device=dev),
+             "feat": torch.empty((D, c.height, c.width), device=dev),
              "T": torch.empty((c.height, c.width), device=dev)} for c in wl.cams]
     tgts = [{"rgb": torch.as_tensor(t.rgb).to(dev), "depth": torch.as_tensor(t.depth).to(dev),
              "feat": torch.as_tensor(t.feat).to(dev)} for t in wl.targets]
-    grads = B._grad_buffers(s.n, V, dev)
+    grads = B._grad_buffers(s.n, V, dev, wl.scene.feat.shape[1])
     st = settings
     if tune:
         shapes = [(c.height, c.width) for c in wl.cams]
@@ -147,6 +148,31 @@ def time_workload(ctx, wl, steps, warmup, dev, tune, settings):
             "settings": {"tile": st.tile, "chunk": st.chunk, "order": st.order}}
 
 
+def featdim_sweep(ctx, steps, warmup, dev, settings, dims=(8, 16, 32, 64, 128)):
+    """The batched step (graph mode, fixed settings) for several language-
+    feature dimensions D: step time, the D-dependent arrays the caller holds
+    (BF16 features, rendered and target feature images, feature gradients)
+    and the D-dependent part of the library's workspace (one appearance
+    record per Gaussian and 16-channel group beyond the first; for D > 16 the
+    per-group partial sums and scratch images), both counted from sizes."""
+    import math
+    import scenes
+    out = []
+    for D in dims:
+        wl = scenes.make_workload(4, feat_dim=D)
+        r = time_workload_graph(ctx, wl, steps, warmup, dev, False, settings)
+        n, V, G = wl.scene.n, len(wl.cams), (D + 15) // 16
+        n_rid = V << max(0, math.ceil(math.log2(max(n, 1))))
+        caller = n * D * 2 + wl.pixels * D * 4 * 2 + n * D * 4
+        work = (G - 1) * n * 40 + ((9 * 4 * wl.pixels + 32 * 4 * n_rid) if G > 1 else 0)
+        out.append({"feat_dim": D, "ms_per_step": round(r["ms"], 4),
+                    "Mpixel/s": round(wl.pixels / (r["ms"] / 1e3) / 1e6, 3),
+                    "feature_arrays_MB": round(caller / 1e6, 1), "extra_workspace_MB": round(work / 1e6, 1)})
+        log(f"[bench] feat_dim {D}: {out[-1]}")
+        del wl
+    return out
+
+
 def time_workload_graph(ctx, wl, steps, warmup, dev, tune, settings, ssim_lambda=0.0):
     """Same step as `time_workload`, captured once as a hipGraph by the
     library (lgs_graph_create) and replayed: one launch per step."""
@@ -159,13 +185,14 @@ def time_workload_graph(ctx, wl, steps, warmup, dev, tune, settings, ssim_lambda
                                   appearance_dtype=dt)
     V = len(wl.cams)
     shapes = [(c.height, c.width) for c in wl.cams]
+    D = wl.scene.feat.shape[1]
     outs = [{"rgb": torch.empty((3, c.height, c.width), device=dev),
              "depth": torch.empty((c.height, c.width), device=dev),
-             "feat": torch.empty((16, c.height, c.width), device=dev),
+             "feat": torch.empty((D, c.height, c.width), device=dev),
              "T": torch.empty((c.height, c.width), device=dev)} for c in wl.cams]
     tgts = [{"rgb": torch.as_tensor(t.rgb).to(dev), "depth": torch.as_tensor(t.depth).to(dev),
              "feat": torch.as_tensor(t.feat).to(dev)} for t in wl.targets]
-    grads = B._grad_buffers(s.n, V, dev)
+    grads = B._grad_buffers(s.n, V, dev, wl.scene.feat.shape[1])
     g = B.gaussians_c(params["means"], params["log_scales"], params["quats"], params["logits"],
                       params["rgb"], params["feat"])
     cams = (B.lgs_camera * V)(*[B.camera_c(c) for c in wl.cams])
@@ -244,7 +271,7 @@ def time_loss(ctx, wl, dev, settings, lam, reps=50, warmup=5):
              "feat": torch.as_tensor(t.feat).to(dev)} for t in wl.targets]
     grad = [{"rgb": torch.empty((3, c.height, c.width), device=dev),
              "depth": torch.empty((c.height, c.width), device=dev),
-             "feat": torch.empty((16, c.height, c.width), device=dev)} for c in wl.cams]
+             "feat": torch.empty((wl.scene.feat.shape[1], c.height, c.width), device=dev)} for c in wl.cams]
     for _ in range(warmup):
         ctx.loss(wl.cams, ims, tgts, wl.loss_w, lam, grad=grad)
     torch.cuda.synchronize()
@@ -362,6 +389,8 @@ def main():
     ap.add_argument("--order", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--featdim-sweep", action="store_true",
+                    help="also time the batched step for language-feature dimensions 8, 16, 32, 64, 128")
     ap.add_argument("--no-prune", action="store_true",
                     help="skip the language-guided pruning timing (500k Gaussians)")
     ap.add_argument("--no-decoder", action="store_true",
@@ -482,6 +511,10 @@ def main():
                                        "frac": round(db_ / (dms / 1e3) / 1e9 / PEAK_HBM_GBS, 4),
                                        "bytes": db_},
                           "mfma_TFLOP/s": round(dfl / (dms / 1e3) / 1e12, 2)}
+    if args.featdim_sweep:
+        log("[bench] feature-dimension sweep (batched step, graph mode)")
+        out["feat_dim_sweep"] = featdim_sweep(ctx, min(args.steps, 30), min(args.warmup, 5), dev,
+                                              P.Settings(**r["settings"]))
     if not args.no_prune:
         log("[bench] timing language-guided pruning (500k Gaussians)")
         pms, pcounts, pn = time_prune(ctx, dev)

@@ -83,17 +83,23 @@ typedef struct {
 
 /* Gaussians: SoA planes, n of each (Sec. III-B.1, Theta).  means [3][n],
  * log_scales [3][n], quats [4][n] (w, x, y, z; need not be unit),
- * opacity_logits [n] are FP32; rgb [3][n] and feat [16][n] are FP32 or BF16
- * (appearance_dtype).  All device pointers. */
+ * opacity_logits [n] are FP32; rgb [3][n] and feat [D][n] are FP32 or BF16
+ * (appearance_dtype).  All device pointers.  feat_dim D is the language
+ * feature dimension: 8 or a multiple of 16 up to 128 (0 means 16; the paper
+ * uses 16 and its ablation varies it).  Features are rendered in groups of
+ * 16 channels: each group beyond the first repeats the compositing passes
+ * (the blend weights do not depend on the features), so the cost of the
+ * compositing kernels grows with ceil(D / 16). */
 typedef struct {
   int64_t n;
   const float *means, *log_scales, *quats, *opacity_logits;
   const void *rgb, *feat;
   lgs_dtype appearance_dtype;
+  int32_t feat_dim;
 } lgs_gaussians;
 
 /* Per-view images, FP32 planes of the view's H x W pixels (device):
- * rgb [3][H][W], depth [H][W], feat [16][H][W], final_T [H][W].
+ * rgb [3][H][W], depth [H][W], feat [D][H][W], final_T [H][W].
  * n_contrib [H][W] (int32, optional, may be NULL) receives each pixel's
  * contributor count.  As a backward input (dL/dY) rgb/depth/feat hold the
  * upstream gradients and final_T (dL/dT) may be NULL. */
@@ -104,7 +110,7 @@ typedef struct {
 
 /* Parameter gradients, FP32 SoA planes shaped like the inputs (device):
  * means [3][n], log_scales [3][n], quats [4][n], opacity_logits [n],
- * rgb [3][n], feat [16][n] (always FP32, w.r.t. the stored values, summed
+ * rgb [3][n], feat [D][n] (always FP32, w.r.t. the stored values, summed
  * over views), and twist [n_views][6] = dL/d(rho, phi) of the left pose
  * perturbation T_cw <- Exp(xi) T_cw at xi = 0 (may be NULL). */
 typedef struct {
@@ -181,9 +187,11 @@ lgs_status lgs_backward_l1(lgs_context *ctx, const lgs_fwd_state *state,
  * C1 = 0.01^2, C2 = 0.03^2 (images in [0, 1]).  sign(0) = 0 in the L1
  * terms.
  *   cams[n_views]    only width and height are read
+ *   feat_dim         D, feature planes of the images (as lgs_gaussians;
+ *                    0 means 16); the feature term is a mean over D planes
  *   out, targets     rendered and observed images (device FP32 planes;
  *                    final_T and n_contrib ignored)
- *   grad             receives dL/dY: rgb [3][H][W], depth, feat [16][H][W]
+ *   grad             receives dL/dY: rgb [3][H][W], depth, feat [D][H][W]
  *                    (device, overwritten; final_T and n_contrib ignored);
  *                    it may be passed to lgs_backward as grad_out
  *   terms            NULL, or device FP32 [n_views][4] receiving per view
@@ -194,7 +202,7 @@ lgs_status lgs_backward_l1(lgs_context *ctx, const lgs_fwd_state *state,
  * LGS_ERR_INVALID_ARG for NULL or misaligned planes, non-finite weights or
  * ssim_lambda outside [0, 1]. */
 lgs_status lgs_loss(lgs_context *ctx, int32_t n_views, const lgs_camera *cams,
-                    const lgs_images *out, const lgs_images *targets,
+                    int32_t feat_dim, const lgs_images *out, const lgs_images *targets,
                     const float loss_w[3], float ssim_lambda,
                     const lgs_images *grad, float *terms, hipStream_t stream);
 

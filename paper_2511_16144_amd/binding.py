@@ -35,7 +35,7 @@ class lgs_settings(C.Structure):
 class lgs_gaussians(C.Structure):
     _fields_ = [("n", C.c_int64), ("means", C.c_void_p), ("log_scales", C.c_void_p),
                 ("quats", C.c_void_p), ("opacity_logits", C.c_void_p), ("rgb", C.c_void_p),
-                ("feat", C.c_void_p), ("appearance_dtype", C.c_int32)]
+                ("feat", C.c_void_p), ("appearance_dtype", C.c_int32), ("feat_dim", C.c_int32)]
 
 
 class lgs_images(C.Structure):
@@ -95,7 +95,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.lgs_backward_l1.argtypes = [P, P, C.POINTER(lgs_gaussians), C.POINTER(lgs_images), C.POINTER(lgs_images),
                                     C.POINTER(C.c_float), C.POINTER(lgs_grads), P]
     lib.lgs_loss.restype = C.c_int
-    lib.lgs_loss.argtypes = [P, C.c_int32, C.POINTER(lgs_camera), C.POINTER(lgs_images), C.POINTER(lgs_images),
+    lib.lgs_loss.argtypes = [P, C.c_int32, C.POINTER(lgs_camera), C.c_int32, C.POINTER(lgs_images),
+                             C.POINTER(lgs_images),
                              C.POINTER(C.c_float), C.c_float, C.POINTER(lgs_images), P, P]
     lib.lgs_decoder_l1.restype = C.c_int
     lib.lgs_decoder_l1.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, P, P, P, P, C.c_int32, C.c_float,
@@ -199,12 +200,13 @@ def gaussians_c(means, log_scales, quats, logits, rgb, feat) -> lgs_gaussians:
     _check_param(quats, 4, n, "quats")
     _check_param(logits, 0, n, "logits")
     _check_param(rgb, 3, n, "rgb", (torch.float32, torch.bfloat16))
-    _check_param(feat, 16, n, "feat", (torch.float32, torch.bfloat16))
+    D = feat.shape[0] if feat.dim() == 2 else -1
+    _check_param(feat, D, n, "feat", (torch.float32, torch.bfloat16))
     if rgb.dtype != feat.dtype:
         raise ValueError("rgb and feat must share a dtype")
     dt = LGS_BF16 if rgb.dtype == torch.bfloat16 else LGS_F32
     return lgs_gaussians(n, _ptr(means), _ptr(log_scales), _ptr(quats), _ptr(logits), _ptr(rgb),
-                         _ptr(feat), dt)
+                         _ptr(feat), dt, D)
 
 
 def _stream(stream=None):
@@ -240,8 +242,8 @@ class Context:
     def forward(self, params, cams, settings: Settings | None = None, want_n: bool = False,
                 stream=None, out=None):
         """params: dict of CUDA tensors means [3,N], log_scales [3,N], quats [4,N],
-        logits [N], rgb [3,N], feat [16,N].  Returns (list of per-view dicts
-        rgb [3,H,W], depth [H,W], feat [16,H,W], T [H,W] (and n [H,W] int32),
+        logits [N], rgb [3,N], feat [D,N].  Returns (list of per-view dicts
+        rgb [3,H,W], depth [H,W], feat [D,H,W], T [H,W] (and n [H,W] int32),
         state)."""
         settings = settings or Settings()
         g = gaussians_c(params["means"], params["log_scales"], params["quats"], params["logits"],
@@ -256,7 +258,7 @@ class Context:
                 o = out[v]
             else:
                 o = {"rgb": torch.empty((3, H, W), device=dev), "depth": torch.empty((H, W), device=dev),
-                     "feat": torch.empty((16, H, W), device=dev), "T": torch.empty((H, W), device=dev)}
+                     "feat": torch.empty((g.feat_dim, H, W), device=dev), "T": torch.empty((H, W), device=dev)}
                 if want_n:
                     o["n"] = torch.empty((H, W), device=dev, dtype=torch.int32)
             imgs[v] = lgs_images(_ptr(o["rgb"]), _ptr(o["depth"]), _ptr(o["feat"]), _ptr(o["T"]),
@@ -268,7 +270,7 @@ class Context:
                                _stream(stream))
         if st != LGS_OK:
             self._raise(st)
-        return outs, State(self, state, V, [(int(c.height), int(c.width)) for c in cams])
+        return outs, State(self, state, V, [(int(c.height), int(c.width)) for c in cams], g.feat_dim)
 
     def backward_l1(self, state, params, outs, targets, loss_w, stream=None, grads=None) -> dict:
         return backward_l1(self, state, params, outs, targets, loss_w, stream, grads)
@@ -276,20 +278,22 @@ class Context:
     def loss(self, cams, outs, targets, loss_w, ssim_lambda: float = 0.2, stream=None, grad=None,
              want_terms: bool = True):
         """Mapping loss of Eq. (1) with its D-SSIM term and dL/dY (lgs_loss).
-        outs / targets: per-view dicts rgb [3,H,W], depth [H,W], feat [16,H,W]
+        outs / targets: per-view dicts rgb [3,H,W], depth [H,W], feat [D,H,W]
         (FP32 CUDA).  Returns (per-view gradient dicts, terms [V, 4] or None:
         mean|I-I*|, 1 - SSIM, mean|D-D*|, mean|F-F*|)."""
         V = len(cams)
         shapes = [(int(c.height), int(c.width)) for c in cams]
         dev = outs[0]["rgb"].device
+        D = outs[0]["feat"].shape[0]
         if grad is None:
             grad = [{"rgb": torch.empty((3, H, W), device=dev), "depth": torch.empty((H, W), device=dev),
-                     "feat": torch.empty((16, H, W), device=dev)} for (H, W) in shapes]
+                     "feat": torch.empty((D, H, W), device=dev)} for (H, W) in shapes]
         terms = torch.empty((V, 4), device=dev) if want_terms else None
         cams_c = (lgs_camera * V)(*[camera_c(c) for c in cams])
         lw = (C.c_float * 3)(*[float(x) for x in loss_w])
-        st = lib().lgs_loss(self._h, V, cams_c, _images_c(outs, shapes, False), _images_c(targets, shapes, False),
-                            lw, float(ssim_lambda), _images_c(grad, shapes, False), _ptr(terms), _stream(stream))
+        st = lib().lgs_loss(self._h, V, cams_c, D, _images_c(outs, shapes, False, D),
+                            _images_c(targets, shapes, False, D), lw, float(ssim_lambda),
+                            _images_c(grad, shapes, False, D), _ptr(terms), _stream(stream))
         if st != LGS_OK:
             self._raise(st)
         return grad, terms
@@ -340,7 +344,7 @@ class Context:
         return mask, tuple(cnt)
 
     def backward(self, state: "State", params, grad_outs, stream=None) -> dict:
-        """grad_outs: per view dict rgb [3,H,W], depth [H,W], feat [16,H,W],
+        """grad_outs: per view dict rgb [3,H,W], depth [H,W], feat [D,H,W],
         optional T [H,W] (FP32 CUDA).  Returns FP32 gradients shaped like the
         parameters plus twist [V, 6]."""
         g = gaussians_c(params["means"], params["log_scales"], params["quats"], params["logits"],
@@ -355,14 +359,14 @@ class Context:
             t = {k: go[k].contiguous().float() for k in ("rgb", "depth", "feat")}
             if go.get("T") is not None:
                 t["T"] = go["T"].contiguous().float()
-            for k, shp in (("rgb", (3, H, W)), ("depth", (H, W)), ("feat", (16, H, W))):
+            for k, shp in (("rgb", (3, H, W)), ("depth", (H, W)), ("feat", (state.feat_dim, H, W))):
                 if tuple(t[k].shape) != shp or not t[k].is_cuda:
                     raise ValueError(f"grad_outs[{v}][{k}] must be a CUDA tensor of shape {shp}")
             keep.append(t)
             ups[v] = lgs_images(_ptr(t["rgb"]), _ptr(t["depth"]), _ptr(t["feat"]), _ptr(t.get("T")), None)
         out = {"means": torch.empty((3, n), device=dev), "log_scales": torch.empty((3, n), device=dev),
                "quats": torch.empty((4, n), device=dev), "logits": torch.empty((n,), device=dev),
-               "rgb": torch.empty((3, n), device=dev), "feat": torch.empty((16, n), device=dev),
+               "rgb": torch.empty((3, n), device=dev), "feat": torch.empty((g.feat_dim, n), device=dev),
                "twist": torch.empty((V, 6), device=dev)}
         gr = lgs_grads(_ptr(out["means"]), _ptr(out["log_scales"]), _ptr(out["quats"]),
                        _ptr(out["logits"]), _ptr(out["rgb"]), _ptr(out["feat"]), _ptr(out["twist"]))
@@ -372,12 +376,13 @@ class Context:
         return out
 
 
-def _images_c(ims, shapes, with_T):
+def _images_c(ims, shapes, with_T, feat_dim=None):
     V = len(ims)
     arr = (lgs_images * V)()
     for v, im in enumerate(ims):
         H, W = shapes[v]
-        for k, shp in (("rgb", (3, H, W)), ("depth", (H, W)), ("feat", (16, H, W))):
+        D = im["feat"].shape[0] if feat_dim is None else feat_dim
+        for k, shp in (("rgb", (3, H, W)), ("depth", (H, W)), ("feat", (D, H, W))):
             t = im[k]
             if tuple(t.shape) != shp or not t.is_cuda or t.dtype != torch.float32 or not t.is_contiguous():
                 raise ValueError(f"image {v} {k}: expected contiguous FP32 CUDA tensor of shape {shp}")
@@ -386,10 +391,10 @@ def _images_c(ims, shapes, with_T):
     return arr
 
 
-def _grad_buffers(n, V, dev):
+def _grad_buffers(n, V, dev, feat_dim=16):
     out = {"means": torch.empty((3, n), device=dev), "log_scales": torch.empty((3, n), device=dev),
            "quats": torch.empty((4, n), device=dev), "logits": torch.empty((n,), device=dev),
-           "rgb": torch.empty((3, n), device=dev), "feat": torch.empty((16, n), device=dev),
+           "rgb": torch.empty((3, n), device=dev), "feat": torch.empty((feat_dim, n), device=dev),
            "twist": torch.empty((V, 6), device=dev)}
     gr = lgs_grads(_ptr(out["means"]), _ptr(out["log_scales"]), _ptr(out["quats"]), _ptr(out["logits"]),
                    _ptr(out["rgb"]), _ptr(out["feat"]), _ptr(out["twist"]))
@@ -404,10 +409,10 @@ def backward_l1(context: "Context", state: "State", params, outs, targets, loss_
     g = gaussians_c(params["means"], params["log_scales"], params["quats"], params["logits"],
                     params["rgb"], params["feat"])
     if grads is None:
-        grads = _grad_buffers(g.n, state.n_views, params["means"].device)
+        grads = _grad_buffers(g.n, state.n_views, params["means"].device, g.feat_dim)
     out, gr = grads
-    o = _images_c(outs, state.shapes, True)
-    t = _images_c(targets, state.shapes, False)
+    o = _images_c(outs, state.shapes, True, state.feat_dim)
+    t = _images_c(targets, state.shapes, False, state.feat_dim)
     lw = (C.c_float * 3)(*[float(x) for x in loss_w])
     st = lib().lgs_backward_l1(context._h, state.handle, C.byref(g), o, t, lw, C.byref(gr), _stream(stream))
     if st != LGS_OK:
@@ -416,8 +421,9 @@ def backward_l1(context: "Context", state: "State", params, outs, targets, loss_
 
 
 class State:
-    def __init__(self, ctx: Context, handle, n_views, shapes):
+    def __init__(self, ctx: Context, handle, n_views, shapes, feat_dim=16):
         self.ctx, self.handle, self.n_views, self.shapes = ctx, handle, n_views, shapes
+        self.feat_dim = feat_dim
 
     def counts(self) -> dict:
         c = lgs_counts()
@@ -474,7 +480,7 @@ class RasterFn(torch.autograd.Function):
             dev = means.device
             gos.append({"rgb": gr if gr is not None else torch.zeros((3, H, W), device=dev),
                         "depth": gd if gd is not None else torch.zeros((H, W), device=dev),
-                        "feat": gf if gf is not None else torch.zeros((16, H, W), device=dev),
+                        "feat": gf if gf is not None else torch.zeros((state.feat_dim, H, W), device=dev),
                         "T": gt})
         g = ctx.context.backward(state, params, gos)
         state.release()

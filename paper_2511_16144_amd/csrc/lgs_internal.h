@@ -36,7 +36,7 @@ struct ViewImages {
 // One view of the mapping loss (rendered and observed images, gradient
 // planes, FP32 [C][H][W]) and its scale factors:
 //   s_l1 = w_rgb (1 - lam) / (3HW), s_ssim = w_rgb lam / (3HW),
-//   s_d = w_depth / (HW), s_f = w_feat / (16HW).
+//   s_d = w_depth / (HW), s_f = w_feat / (D HW).
 // Colour work-groups of the view: [blk_off, blk_off + n_blk), three per
 // 32 x 32 tile (one per channel); depth + feature work-groups: [df_off,
 // df_off + n_df), one per run of kLossDfPixels pixels; vec4: the depth and
@@ -44,7 +44,7 @@ struct ViewImages {
 struct LossView {
   const float *x, *xt, *d, *dt, *f, *ft;
   float *gx, *gd, *gf;
-  int32_t W, H, tiles_x, blk_off, n_blk, df_off, n_df, vec4;
+  int32_t W, H, tiles_x, blk_off, n_blk, df_off, n_df, vec4, nf, pad;   // nf: feature planes D
   float s_l1, s_ssim, s_d, s_f;
 };
 constexpr int kLossDfPixels = 2048;
@@ -68,9 +68,16 @@ struct __attribute__((aligned(32))) GeomRec {
   uint32_t bbox;
 };
 
+// The language features of dimension D are processed in groups of 16
+// channels (the last group of D = 8 has 8): the compositing kernels carry
+// RGB + depth + one group; further groups re-run them with that group's
+// appearance records (blend weights do not depend on the features).
+constexpr int kFeatGroup = 16;
 struct Settings {
   float z_near, eps2d, fov_clamp, alpha_max, alpha_min, T_eps, cutoff2;
   int32_t tile, tile_shift;   // tile side and log2(tile / 8)
+  int32_t feat_dim;           // D: feature planes of the inputs
+  int32_t nfeat;              // feature channels of the group being processed (8 or 16)
 };
 
 // Device-resident counters of one forward (written by kernels, read by
@@ -232,6 +239,16 @@ void launch_prune_count_valid(const uint64_t* keys, int64_t n, int64_t* n_valid,
 void launch_prune_knn(const PruneArgs& a, const uint64_t* keys, const uint32_t* vals, uint8_t* sem, hipStream_t s);
 void launch_prune_final(int64_t n, const uint8_t* sem, const uint8_t* geo, uint8_t* mask,
                         unsigned long long* counts, hipStream_t s);
+
+// feature groups beyond the first: appearance records (RGB 0, the group's
+// features), the geometric partials of a group's backward added to the
+// first group's, and a group's feature gradients summed over views
+void launch_pack_app_group(const void* feat_g, int nfeat, int app_bf16, int64_t n, void* app, hipStream_t s);
+void launch_group_geo_acc(const float* grad2d_g, const Counters* cnt, int64_t n_max, float* geo_acc, int first,
+                          hipStream_t s);
+void launch_group_geo_add(float* grad2d, const Counters* cnt, int64_t n_max, const float* geo_acc, hipStream_t s);
+void launch_group_feat_grad(int n_views, int64_t n, uint32_t npad_shift, const Counters* cnt, const uint32_t* cnt_t,
+                            const uint32_t* cidx, const float* grad2d_g, int nfeat, float* g_feat_g, hipStream_t s);
 
 // gradient reduction and projection backward
 void launch_seg_reduce(const uint32_t* slot_off, const float* partials, const uint8_t* mask,

@@ -270,7 +270,7 @@ __global__ __launch_bounds__(kLossThreads) void k_loss_rgb(const LossView* __res
 }
 
 // Depth and feature L1 terms: work-group = a run of kLossDfPixels pixels of
-// one view, all 17 channels (depth, then the 16 feature planes); each thread
+// one view, all 1 + D channels (depth, then the D feature planes); each thread
 // takes 8 pixels per channel (two 16-byte vectors when the view allows it)
 // and loads four channels ahead before it computes and stores them.
 constexpr int kDfGroup = 4;
@@ -284,18 +284,19 @@ __global__ __launch_bounds__(256) void k_loss_df(const LossView* __restrict__ vi
   const LossView V = views[v];
   const int64_t n = (int64_t)V.W * V.H;
   const int64_t p0 = (int64_t)(b - V.df_off) * kLossDfPixels;
+  const int nch = 1 + V.nf;
   float acc0 = 0.f, acc1 = 0.f;
   if (V.vec4) {
     const int64_t n4 = n >> 2;
     const int64_t i0 = (p0 >> 2) + t, i1 = i0 + 256;
     const bool in0 = i0 < n4, in1 = i1 < n4;
-    for (int c0 = 0; c0 < 17; c0 += kDfGroup) {
+    for (int c0 = 0; c0 < nch; c0 += kDfGroup) {
       float4 y[kDfGroup][2], r[kDfGroup][2];
 #pragma unroll
       for (int u = 0; u < kDfGroup; ++u) {
         const int ch = c0 + u;
         y[u][0] = y[u][1] = r[u][0] = r[u][1] = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (ch < 17) {
+        if (ch < nch) {
           const float4* Y4 = (const float4*)(ch == 0 ? V.d : V.f + (size_t)(ch - 1) * n);
           const float4* R4 = (const float4*)(ch == 0 ? V.dt : V.ft + (size_t)(ch - 1) * n);
           if (in0) { y[u][0] = Y4[i0]; r[u][0] = R4[i0]; }
@@ -305,7 +306,7 @@ __global__ __launch_bounds__(256) void k_loss_df(const LossView* __restrict__ vi
 #pragma unroll
       for (int u = 0; u < kDfGroup; ++u) {
         const int ch = c0 + u;
-        if (ch < 17) {
+        if (ch < nch) {
           float4* G4 = (float4*)(ch == 0 ? V.gd : V.gf + (size_t)(ch - 1) * n);
           const float sc = ch == 0 ? V.s_d : V.s_f;
 #pragma unroll
@@ -322,7 +323,7 @@ __global__ __launch_bounds__(256) void k_loss_df(const LossView* __restrict__ vi
       }
     }
   } else {
-    for (int c0 = 0; c0 < 17; c0 += kDfGroup) {
+    for (int c0 = 0; c0 < nch; c0 += kDfGroup) {
       float y[kDfGroup][8], r[kDfGroup][8];
 #pragma unroll
       for (int u = 0; u < kDfGroup; ++u) {
@@ -331,7 +332,7 @@ __global__ __launch_bounds__(256) void k_loss_df(const LossView* __restrict__ vi
         for (int h = 0; h < 8; ++h) {
           const int64_t p = p0 + t + 256 * h;
           y[u][h] = r[u][h] = 0.f;
-          if (ch < 17 && p < n) {
+          if (ch < nch && p < n) {
             y[u][h] = ch == 0 ? V.d[p] : V.f[(size_t)(ch - 1) * n + p];
             r[u][h] = ch == 0 ? V.dt[p] : V.ft[(size_t)(ch - 1) * n + p];
           }
@@ -340,7 +341,7 @@ __global__ __launch_bounds__(256) void k_loss_df(const LossView* __restrict__ vi
 #pragma unroll
       for (int u = 0; u < kDfGroup; ++u) {
         const int ch = c0 + u;
-        if (ch < 17) {
+        if (ch < nch) {
           float* G = ch == 0 ? V.gd : V.gf + (size_t)(ch - 1) * n;
           const float sc = ch == 0 ? V.s_d : V.s_f;
 #pragma unroll
@@ -390,7 +391,7 @@ __global__ __launch_bounds__(256) void k_loss_terms(const LossView* __restrict__
     terms[4 * v + 0] = (float)(red[0][0] / (3.0 * n));
     terms[4 * v + 1] = ssim ? (float)(1.0 - red[1][0] / (3.0 * n)) : 0.f;
     terms[4 * v + 2] = (float)(red[2][0] / n);
-    terms[4 * v + 3] = (float)(red[3][0] / (16.0 * n));
+    terms[4 * v + 3] = (float)(red[3][0] / ((double)V.nf * n));
   }
 }
 

@@ -88,20 +88,33 @@ __device__ void to_screen(const ViewDesc& V, const double p[3], const Proj& P, d
   S.det = S.a * S.c - S.b * S.b;
 }
 
+// RGB and the first feature group (nfeat <= 16 channels; the rest 0)
 template <bool BF16>
-__device__ void load_app(const void* rgb, const void* feat, int64_t n, int64_t g, float y[20]) {
+__device__ void load_app(const void* rgb, const void* feat, int64_t n, int64_t g, int nfeat, float y[20]) {
   if (BF16) {
     const uint16_t* r = (const uint16_t*)rgb;
     const uint16_t* f = (const uint16_t*)feat;
     for (int k = 0; k < 3; ++k) y[k] = __uint_as_float((uint32_t)r[k * n + g] << 16);
-    for (int k = 0; k < 16; ++k) y[4 + k] = __uint_as_float((uint32_t)f[k * n + g] << 16);
+    for (int k = 0; k < 16; ++k) y[4 + k] = k < nfeat ? __uint_as_float((uint32_t)f[k * n + g] << 16) : 0.f;
   } else {
     const float* r = (const float*)rgb;
     const float* f = (const float*)feat;
     for (int k = 0; k < 3; ++k) y[k] = r[k * n + g];
-    for (int k = 0; k < 16; ++k) y[4 + k] = f[k * n + g];
+    for (int k = 0; k < 16; ++k) y[4 + k] = k < nfeat ? f[k * n + g] : 0.f;
   }
   y[3] = 0.f;
+}
+
+// every feature plane of Gaussian g is finite (all D of them)
+template <bool BF16>
+__device__ bool feat_finite(const void* feat, int64_t n, int64_t g, int D) {
+  bool fin = true;
+  for (int k = 0; k < D; ++k) {
+    const float x = BF16 ? __uint_as_float((uint32_t)((const uint16_t*)feat)[k * n + g] << 16)
+                         : ((const float*)feat)[k * n + g];
+    fin &= isfinite(x);
+  }
+  return fin;
 }
 
 // Sort key of a visible Gaussian's camera depth z > z_near: the FP64 bit
@@ -196,9 +209,10 @@ __global__ void __launch_bounds__(256) k_project(
   }
   if (!any_vis) return;
   float y[20];
-  load_app<BF16>(rgb, feat, n, g, y);
+  load_app<BF16>(rgb, feat, n, g, st.nfeat, y);
   bool fin = true;
-  for (int k = 0; k < 20; ++k) fin &= isfinite(y[k]);
+  for (int k = 0; k < 4; ++k) fin &= isfinite(y[k]);
+  fin &= feat_finite<BF16>(feat, n, g, st.feat_dim);
   if (!fin) {   // a non-finite colour or feature culls the Gaussian everywhere
     for (int v = 0; v < n_views; ++v) {
       const uint64_t rid = ((uint64_t)v << npad_shift) | (uint64_t)g;
@@ -213,8 +227,11 @@ __global__ void __launch_bounds__(256) k_project(
     uint32_t w[10];
     w[0] = (uint32_t)r[g] | ((uint32_t)r[n + g] << 16);
     w[1] = (uint32_t)r[2 * n + g];
-    for (int k = 0; k < 8; ++k)
-      w[2 + k] = (uint32_t)f[(2 * k) * n + g] | ((uint32_t)f[(2 * k + 1) * n + g] << 16);
+    for (int k = 0; k < 8; ++k) {
+      const uint32_t lo = 2 * k < st.nfeat ? (uint32_t)f[(2 * k) * n + g] : 0u;
+      const uint32_t hi = 2 * k + 1 < st.nfeat ? (uint32_t)f[(2 * k + 1) * n + g] : 0u;
+      w[2 + k] = lo | (hi << 16);
+    }
     uint32_t* dst = (uint32_t*)app + (size_t)g * 10;
     uint2* d2 = (uint2*)dst;
     for (int k = 0; k < 5; ++k) d2[k] = make_uint2(w[2 * k], w[2 * k + 1]);
@@ -393,7 +410,83 @@ __global__ void __launch_bounds__(256) k_project_bwd(
   for (int k = 0; k < 4; ++k) g_q[k * n + g] = (float)gq[k];
   g_logit[g] = (float)glogit;
   for (int k = 0; k < 3; ++k) g_rgb[k * n + g] = gy[k];
-  for (int k = 0; k < 16; ++k) g_feat[k * n + g] = gy[4 + k];
+  for (int k = 0; k < 16; ++k)
+    if (k < st.nfeat) g_feat[k * n + g] = gy[4 + k];
+}
+
+// Appearance records of a feature group beyond the first: RGB 0, slot 3
+// unused, the group's nfeat feature planes starting at feat_g (the rest 0).
+template <bool BF16>
+__global__ void __launch_bounds__(256) k_pack_app_group(const void* __restrict__ feat_g, int nfeat, int64_t n,
+                                                        void* __restrict__ app) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  if (BF16) {
+    const uint16_t* f = (const uint16_t*)feat_g;
+    uint32_t w[10];
+    w[0] = 0u;
+    w[1] = 0u;
+    for (int k = 0; k < 8; ++k) {
+      const uint32_t lo = 2 * k < nfeat ? (uint32_t)f[(2 * k) * n + g] : 0u;
+      const uint32_t hi = 2 * k + 1 < nfeat ? (uint32_t)f[(2 * k + 1) * n + g] : 0u;
+      w[2 + k] = lo | (hi << 16);
+    }
+    uint2* d2 = (uint2*)((uint32_t*)app + (size_t)g * 10);
+    for (int k = 0; k < 5; ++k) d2[k] = make_uint2(w[2 * k], w[2 * k + 1]);
+  } else {
+    const float* f = (const float*)feat_g;
+    float y[20];
+    for (int k = 0; k < 4; ++k) y[k] = 0.f;
+    for (int k = 0; k < 16; ++k) y[4 + k] = k < nfeat ? f[k * n + g] : 0.f;
+    float4* dst = (float4*)((float*)app + (size_t)g * 20);
+    for (int k = 0; k < 5; ++k) dst[k] = make_float4(y[4 * k], y[4 * k + 1], y[4 * k + 2], y[4 * k + 3]);
+  }
+}
+
+// geo_acc[c][0..5] (=|+=) the geometric partials (mean', conic, opacity) of
+// a feature group's backward, per visible (view, Gaussian)
+__global__ void __launch_bounds__(256) k_group_geo_acc(const float* __restrict__ grad2d_g,
+                                                       const Counters* __restrict__ cnt,
+                                                       float* __restrict__ geo_acc, int first) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t m = (int64_t)cnt->n_visible * 6;
+  if (i >= m || cnt->overflow) return;
+  const int64_t c = i / 6, k = i - 6 * c;
+  const float v = grad2d_g[(size_t)c * kPartials + k];
+  geo_acc[i] = first ? v : geo_acc[i] + v;
+}
+
+__global__ void __launch_bounds__(256) k_group_geo_add(float* __restrict__ grad2d, const Counters* __restrict__ cnt,
+                                                       const float* __restrict__ geo_acc) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t m = (int64_t)cnt->n_visible * 6;
+  if (i >= m || cnt->overflow) return;
+  const int64_t c = i / 6, k = i - 6 * c;
+  grad2d[(size_t)c * kPartials + k] += geo_acc[i];
+}
+
+// a feature group's gradients: sum over the views where the Gaussian is
+// visible of its colour partials f0.. (slots 10 ..), zero elsewhere
+__global__ void __launch_bounds__(256) k_group_feat_grad(int n_views, int64_t n, uint32_t npad_shift,
+                                                         const Counters* __restrict__ cnt,
+                                                         const uint32_t* __restrict__ cnt_t,
+                                                         const uint32_t* __restrict__ cidx,
+                                                         const float* __restrict__ grad2d_g, int nfeat,
+                                                         float* __restrict__ g_feat_g) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  float acc[16];
+  for (int k = 0; k < 16; ++k) acc[k] = 0.f;
+  if (cnt->overflow == 0u)
+    for (int v = 0; v < n_views; ++v) {
+      const uint64_t rid = ((uint64_t)v << npad_shift) | (uint64_t)g;
+      if (cnt_t[rid] != 0) {
+        const float* G = grad2d_g + (size_t)cidx[rid] * kPartials;
+        for (int k = 0; k < 16; ++k) acc[k] += G[10 + k];
+      }
+    }
+  for (int k = 0; k < 16; ++k)
+    if (k < nfeat) g_feat_g[k * n + g] = acc[k];
 }
 
 // twist[v][k] = sum over the projection-backward blocks of their partial sums;
@@ -428,6 +521,33 @@ void launch_project(const Settings& st, const ViewDesc* views, int n_views, cons
   else
     hipLaunchKernelGGL(k_project<false>, dim3(blocks), dim3(256), 0, s, st, views, n_views, means,
                        log_scales, quats, logits, rgb, feat, n, npad_shift, geom, cnt_t, cnt_b, dkey, app);
+}
+
+void launch_pack_app_group(const void* feat_g, int nfeat, int app_bf16, int64_t n, void* app, hipStream_t s) {
+  if (n <= 0) return;
+  const int blocks = (int)((n + 255) / 256);
+  if (app_bf16) hipLaunchKernelGGL(k_pack_app_group<true>, dim3(blocks), dim3(256), 0, s, feat_g, nfeat, n, app);
+  else hipLaunchKernelGGL(k_pack_app_group<false>, dim3(blocks), dim3(256), 0, s, feat_g, nfeat, n, app);
+}
+
+void launch_group_geo_acc(const float* grad2d_g, const Counters* cnt, int64_t n_max, float* geo_acc, int first,
+                          hipStream_t s) {
+  if (n_max <= 0) return;
+  hipLaunchKernelGGL(k_group_geo_acc, dim3((unsigned)((6 * n_max + 255) / 256)), dim3(256), 0, s, grad2d_g, cnt,
+                     geo_acc, first);
+}
+
+void launch_group_geo_add(float* grad2d, const Counters* cnt, int64_t n_max, const float* geo_acc, hipStream_t s) {
+  if (n_max <= 0) return;
+  hipLaunchKernelGGL(k_group_geo_add, dim3((unsigned)((6 * n_max + 255) / 256)), dim3(256), 0, s, grad2d, cnt,
+                     geo_acc);
+}
+
+void launch_group_feat_grad(int n_views, int64_t n, uint32_t npad_shift, const Counters* cnt, const uint32_t* cnt_t,
+                            const uint32_t* cidx, const float* grad2d_g, int nfeat, float* g_feat_g, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_group_feat_grad, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n_views, n, npad_shift,
+                     cnt, cnt_t, cidx, grad2d_g, nfeat, g_feat_g);
 }
 
 size_t twist_temp_bytes(int64_t n, int n_views) {

@@ -264,7 +264,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))
       for (int c = 0; c < 3; ++c) o.rgb[c * HW + p] = acc[c];
       o.depth[p] = acc[3];
 #pragma unroll
-      for (int c = 0; c < 16; ++c) o.feat[c * HW + p] = acc[4 + c];
+      for (int c = 0; c < 16; ++c)
+        if (c < st.nfeat) o.feat[c * HW + p] = acc[4 + c];
       o.T[p] = T;
       if (o.n_contrib) o.n_contrib[p] = ncon;
       last_idx[(size_t)V->pix_off + p] = last;
@@ -435,7 +436,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
         }
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
-          const float d = Y.feat[c * HW + p] - Yt.feat[c * HW + p];
+          const float d = c < st.nfeat ? Y.feat[c * HW + p] - Yt.feat[c * HW + p] : 0.f;
           g[4 + c] = d > 0.f ? s_f : (d < 0.f ? -s_f : 0.f);
         }
       } else {
@@ -444,7 +445,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
         for (int c = 0; c < 3; ++c) g[c] = U.rgb[c * HW + p];
         g[3] = U.depth[p];
 #pragma unroll
-        for (int c = 0; c < 16; ++c) g[4 + c] = U.feat[c * HW + p];
+        for (int c = 0; c < 16; ++c) g[4 + c] = c < st.nfeat ? U.feat[c * HW + p] : 0.f;
         if (U.T) gT = U.T[p];
       }
     }

@@ -112,6 +112,9 @@ lgs_status check_gaussians(lgs_context* ctx, const lgs_gaussians* g) {
   if (g->n > (int64_t)1 << 30) return fail(ctx, LGS_ERR_UNSUPPORTED, "n > 2^30");
   if (g->appearance_dtype != LGS_F32 && g->appearance_dtype != LGS_BF16)
     return fail(ctx, LGS_ERR_INVALID_ARG, "unknown appearance dtype");
+  if (!(g->feat_dim == 0 || g->feat_dim == 8 || (g->feat_dim % kFeatGroup == 0 && g->feat_dim >= 16 &&
+                                                  g->feat_dim <= 128)))
+    return fail(ctx, LGS_ERR_INVALID_ARG, "feat_dim must be 8 or a multiple of 16 up to 128 (0: 16)");
   if (g->n > 0) {
     const void* ps[6] = {g->means, g->log_scales, g->quats, g->opacity_logits, g->rgb, g->feat};
     for (int i = 0; i < 6; ++i) {
@@ -228,13 +231,20 @@ std::vector<uint32_t> make_items(const Plan& P, int tile) {
 }
 
 
-Settings dev_settings(const lgs_settings* st, int tile_shift) {
+// feature channels of group g when the features have D channels
+int group_nfeat(int D, int g) { return D >= kFeatGroup * (g + 1) ? kFeatGroup : D - kFeatGroup * g; }
+
+Settings dev_settings(const lgs_settings* st, int tile_shift, int D = kFeatGroup, int group = 0) {
   Settings s;
   s.z_near = st->z_near; s.eps2d = st->eps2d; s.fov_clamp = st->fov_clamp;
   s.alpha_max = st->alpha_max; s.alpha_min = st->alpha_min; s.T_eps = st->T_eps;
   s.cutoff2 = st->cutoff2; s.tile = st->tile; s.tile_shift = tile_shift;
+  s.feat_dim = D;
+  s.nfeat = group_nfeat(D, group);
   return s;
 }
+
+int feat_dim_of(const lgs_gaussians* g) { return g->feat_dim == 0 ? kFeatGroup : g->feat_dim; }
 
 // Loss constants: the normalised 1-D SSIM window (sigma 1.5, computed in
 // double, rounded once), C1 = 0.01^2, C2 = 0.03^2 (dynamic range 1).
@@ -255,8 +265,9 @@ bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 // Loss view table; returns the number of colour work-groups and, in *n_df,
 // the number of depth + feature work-groups (their partial sums follow the
 // colour ones).
-int64_t make_loss_views(int32_t n_views, const lgs_camera* cams, const lgs_images* out, const lgs_images* tgt,
-                        const lgs_images* grad, const float loss_w[3], float lam, LossView* dst, int64_t* n_df) {
+int64_t make_loss_views(int32_t n_views, const lgs_camera* cams, int feat_dim, const lgs_images* out,
+                        const lgs_images* tgt, const lgs_images* grad, const float loss_w[3], float lam, LossView* dst,
+                        int64_t* n_df) {
   int64_t nb = 0, nd = 0;
   for (int v = 0; v < n_views; ++v) {
     LossView L;
@@ -278,7 +289,8 @@ int64_t make_loss_views(int32_t n_views, const lgs_camera* cams, const lgs_image
     L.s_l1 = (float)((double)loss_w[0] * (1.0 - (double)lam) / (3.0 * n));
     L.s_ssim = (float)((double)loss_w[0] * (double)lam / (3.0 * n));
     L.s_d = (float)((double)loss_w[1] / n);
-    L.s_f = (float)((double)loss_w[2] / (16.0 * n));
+    L.s_f = (float)((double)loss_w[2] / ((double)feat_dim * n));
+    L.nf = feat_dim;
     dst[v] = L;
     nb += L.n_blk;
     nd += L.n_df;
@@ -310,8 +322,16 @@ struct Work {
   int64_t cap_pairs = 0, cap_slots = 0;
   lgs_counts counts{};
   ViewDesc* d_views = nullptr;
-  ViewImages *d_out = nullptr, *d_up = nullptr, *d_tgt = nullptr;
+  // per-view image tables, one set of n_views per feature group: forward
+  // outputs (d_out), upstream (d_up), the forward's images read by the fused
+  // loss gradient (d_fo), targets (d_tgt); loss weights (4 per group)
+  ViewImages *d_out = nullptr, *d_up = nullptr, *d_fo = nullptr, *d_tgt = nullptr;
   float* d_lossw = nullptr;
+  int D = kFeatGroup, G = 1;                 // feature dimension and groups
+  std::vector<void*> app_g;                  // appearance records of groups 1 ..
+  float* scratch_img = nullptr;              // groups 1 ..: their RGB / depth / T outputs (discarded)
+  float* zero_img = nullptr;                 // groups 1 ..: zero RGB / depth upstream
+  float *grad2d_g = nullptr, *geo_acc = nullptr;
   GeomRec* geom = nullptr;
   uint32_t *cnt_t = nullptr, *cnt_b = nullptr, *cidx = nullptr, *slot_base = nullptr;
   uint32_t *ent = nullptr, *ent_a = nullptr, *ent_b = nullptr, *srid = nullptr;
@@ -389,6 +409,8 @@ lgs_status w_init(Work* W, lgs_context* ctx, const lgs_settings* st, const lgs_g
   W->plan = make_plan(st, n_views, cams);
   W->n = g->n;
   W->app_bf16 = g->appearance_dtype == LGS_BF16;
+  W->D = feat_dim_of(g);
+  W->G = (W->D + kFeatGroup - 1) / kFeatGroup;
   W->npad_shift = (int)ceil_log2((uint64_t)std::max<int64_t>(g->n, 1));
   W->n_rid = (int64_t)n_views << W->npad_shift;
   if (W->n_rid > ((int64_t)1 << 32)) return fail(ctx, LGS_ERR_UNSUPPORTED, "n_views * 2^ceil(log2 n) exceeds 2^32");
@@ -402,10 +424,19 @@ lgs_status w_alloc_front(Work* W) {
   const int V = (int)W->plan.views.size();
   const int64_t n_rid = W->n_rid, npix = std::max<int64_t>(W->plan.n_pix, 1);
   W->d_views = (ViewDesc*)w_alloc(W, sizeof(ViewDesc) * V, ok);
-  W->d_out = (ViewImages*)w_alloc(W, sizeof(ViewImages) * V, ok);
-  W->d_up = (ViewImages*)w_alloc(W, sizeof(ViewImages) * V, ok);
-  W->d_tgt = (ViewImages*)w_alloc(W, sizeof(ViewImages) * V, ok);
-  W->d_lossw = (float*)w_alloc(W, 16, ok);
+  const int G = W->G;
+  W->d_out = (ViewImages*)w_alloc(W, sizeof(ViewImages) * V * G, ok);
+  W->d_up = (ViewImages*)w_alloc(W, sizeof(ViewImages) * V * G, ok);
+  W->d_fo = (ViewImages*)w_alloc(W, sizeof(ViewImages) * V * G, ok);
+  W->d_tgt = (ViewImages*)w_alloc(W, sizeof(ViewImages) * V * G, ok);
+  W->d_lossw = (float*)w_alloc(W, 16 * G, ok);
+  for (int gi = 1; gi < G; ++gi)
+    W->app_g.push_back(w_alloc(W, (size_t)std::max<int64_t>(W->n, 1) * (W->app_bf16 ? 40 : 80), ok));
+  if (G > 1) {
+    W->scratch_img = (float*)w_alloc(W, sizeof(float) * 5 * npix, ok);
+    W->zero_img = (float*)w_alloc(W, sizeof(float) * 4 * npix, ok);
+    if (ok && hipMemset(W->zero_img, 0, sizeof(float) * 4 * npix) != hipSuccess) ok = false;
+  }
   W->geom = (GeomRec*)w_alloc(W, sizeof(GeomRec) * n_rid, ok);
   W->cnt_t = (uint32_t*)w_alloc(W, 4 * n_rid, ok);
   W->cnt_b = (uint32_t*)w_alloc(W, 4 * n_rid, ok);
@@ -455,25 +486,72 @@ lgs_status w_alloc_bwd(Work* W) {
   W->mask = (uint8_t*)w_alloc(W, S + 8, ok);
   W->grad2d = (float*)w_alloc(W, sizeof(float) * kPartials * std::max<int64_t>(W->n_rid, 1), ok);
   W->ttmp = w_alloc(W, twist_temp_bytes(W->n, (int)W->plan.views.size()), ok);
+  if (W->G > 1) {
+    W->grad2d_g = (float*)w_alloc(W, sizeof(float) * kPartials * std::max<int64_t>(W->n_rid, 1), ok);
+    W->geo_acc = (float*)w_alloc(W, sizeof(float) * 6 * std::max<int64_t>(W->n_rid, 1), ok);
+  }
   if (!ok) return fail(W->ctx, LGS_ERR_HIP, "device allocation failed (backward)");
   W->bwd_alloc = true;
   return LGS_OK;
 }
 
+int64_t view_plane(const Work* W, int v) { return (int64_t)W->plan.views[v].W * W->plan.views[v].H; }
+
+// Per-group tables, [group][view], from the callers' images: group g reads or
+// writes feature planes 16 g ... of each view's feature image.
+enum TableKind { TAB_OUT, TAB_UP, TAB_FO, TAB_TGT, TAB_UP_RGB };
+std::vector<ViewImages> group_tables(const Work* W, const lgs_images* im, TableKind kind) {
+  const int V = (int)W->plan.views.size();
+  std::vector<ViewImages> t((size_t)V * W->G);
+  for (int gi = 0; gi < W->G; ++gi)
+    for (int v = 0; v < V; ++v) {
+      const int64_t hw = view_plane(W, v), po = W->plan.views[v].pix_off;
+      float* feat = im && im[v].feat ? im[v].feat + (int64_t)kFeatGroup * gi * hw : nullptr;
+      ViewImages x{nullptr, nullptr, feat, nullptr, nullptr};
+      if (gi == 0) {
+        x = ViewImages{im[v].rgb, im[v].depth, im[v].feat, kind == TAB_TGT ? nullptr : im[v].final_T,
+                       kind == TAB_OUT ? im[v].n_contrib : nullptr};
+        if (kind == TAB_UP_RGB) x = ViewImages{im[v].rgb, nullptr, nullptr, nullptr, nullptr};
+      } else if (kind == TAB_OUT) {
+        float* sc = W->scratch_img + 5 * po;     // RGB, depth, T of this group go nowhere
+        x = ViewImages{sc, sc + 3 * hw, feat, sc + 4 * hw, nullptr};
+      } else if (kind == TAB_UP || kind == TAB_UP_RGB) {
+        float* z = W->zero_img + 4 * po;          // no colour or depth upstream in this group
+        x = ViewImages{z, z + 3 * hw, kind == TAB_UP ? feat : nullptr, nullptr, nullptr};
+      } else {                                    // TAB_FO, TAB_TGT: the residual's images
+        x = ViewImages{im[v].rgb, im[v].depth, feat, nullptr, nullptr};
+      }
+      t[(size_t)gi * V + v] = x;
+    }
+  return t;
+}
+
+// loss weights per group: colour and depth terms in group 0 only; the
+// feature term's 1/(16 HW) scale in the kernel becomes 1/(D HW)
+std::vector<float> group_lossw(const Work* W, const float loss_w[3]) {
+  std::vector<float> lw(4 * (size_t)W->G, 0.f);
+  const float wf = loss_w[2] * ((float)kFeatGroup / (float)W->D);
+  for (int gi = 0; gi < W->G; ++gi) {
+    lw[4 * gi + 0] = gi == 0 ? loss_w[0] : 0.f;
+    lw[4 * gi + 1] = gi == 0 ? loss_w[1] : 0.f;
+    lw[4 * gi + 2] = wf;
+  }
+  return lw;
+}
+
 lgs_status w_upload(Work* W, const lgs_images* out, hipStream_t stream) {
   const int V = (int)W->plan.views.size();
-  std::vector<ViewImages> himg(V);
-  for (int v = 0; v < V; ++v)
-    himg[v] = ViewImages{out[v].rgb, out[v].depth, out[v].feat, out[v].final_T, out[v].n_contrib};
+  const std::vector<ViewImages> himg = group_tables(W, out, TAB_OUT);
   HIP_TRY(W->ctx, hipMemcpyAsync(W->d_views, W->plan.views.data(), sizeof(ViewDesc) * V, hipMemcpyHostToDevice, stream));
-  HIP_TRY(W->ctx, hipMemcpyAsync(W->d_out, himg.data(), sizeof(ViewImages) * V, hipMemcpyHostToDevice, stream));
+  HIP_TRY(W->ctx, hipMemcpyAsync(W->d_out, himg.data(), sizeof(ViewImages) * himg.size(), hipMemcpyHostToDevice,
+                                 stream));
   HIP_TRY(W->ctx, hipStreamSynchronize(stream));   // host vectors go out of scope
   return LGS_OK;
 }
 
 // projection .. slot bases: everything up to the pair / slot counts
 void enqueue_front(Work* W, const lgs_gaussians* g, hipStream_t s) {
-  const Settings ds = dev_settings(&W->st, W->plan.tile_shift);
+  const Settings ds = dev_settings(&W->st, W->plan.tile_shift, W->D, 0);
   const int V = (int)W->plan.views.size();
   const int64_t n_rid = W->n_rid;
   launch_reset_counters(W->counters, s);
@@ -492,6 +570,10 @@ void enqueue_front(Work* W, const lgs_gaussians* g, hipStream_t s) {
   launch_scan(SCAN_GATHER, W->cnt_b, W->ent, W->slot_off, &W->counters->n_slots, &W->counters->n_visible, n_rid,
               W->scan_tmp, s);
   launch_slot_bases(W->ent, W->slot_off, W->counters, n_rid, W->slot_base, s);
+  const size_t esz = W->app_bf16 ? 2 : 4;
+  for (int gi = 1; gi < W->G; ++gi)
+    launch_pack_app_group((const char*)g->feat + esz * (size_t)kFeatGroup * gi * (size_t)W->n,
+                          group_nfeat(W->D, gi), W->app_bf16, W->n, W->app_g[gi - 1], s);
 }
 
 // emission, tile sort, tile ranges, work order (capacity-bounded)
@@ -514,35 +596,61 @@ void enqueue_pairs(Work* W, hipStream_t s) {
     W->items = W->items_static;
 }
 
+// group 0 (RGB, depth, features 0..15), then each further feature group
+// over the same lists (its RGB / depth / T outputs go to scratch)
 void enqueue_raster_fwd(Work* W, hipStream_t s) {
-  const Settings ds = dev_settings(&W->st, W->plan.tile_shift);
-  launch_raster_fwd(ds, W->d_views, W->d_out, W->ranges, W->pvals, W->geom, W->app, W->app_bf16,
-                    (uint32_t)((1ull << W->npad_shift) - 1), W->items, W->items_static + W->plan.n_items,
-                    W->plan.n_items, W->counters, W->st.chunk,
-                    W->last_idx, W->T_state, s);
+  const int V = (int)W->plan.views.size();
+  for (int gi = 0; gi < W->G; ++gi) {
+    const Settings ds = dev_settings(&W->st, W->plan.tile_shift, W->D, gi);
+    if (gi > 0) launch_fill_u32(W->counters->work_q, 0u, kQueues * kLineWords, s);
+    launch_raster_fwd(ds, W->d_views, W->d_out + (size_t)gi * V, W->ranges, W->pvals, W->geom,
+                      gi == 0 ? W->app : W->app_g[gi - 1], W->app_bf16, (uint32_t)((1ull << W->npad_shift) - 1),
+                      W->items, W->items_static + W->plan.n_items, W->plan.n_items, W->counters, W->st.chunk,
+                      W->last_idx, W->T_state, s);
+  }
 }
 
-// upstream by mode (UpMode): d_up; dL1/dY from (d_out, d_tgt, d_lossw); or
-// colour channels from d_up and depth + features from the L1 residual
-void enqueue_backward_raster(Work* W, int mode, hipStream_t s) {
+// Backward compositing of one feature group; upstream by mode (UpMode):
+// d_up; dL1/dY from (d_fo, d_tgt, d_lossw); or colour channels from d_up and
+// depth + features from the L1 residual.
+void launch_group_bwd(Work* W, int gi, int mode, hipStream_t s) {
+  const int V = (int)W->plan.views.size();
   const bool sign = mode != UP_EXPLICIT;
-  const Settings ds = dev_settings(&W->st, W->plan.tile_shift);
+  const Settings ds = dev_settings(&W->st, W->plan.tile_shift, W->D, gi);
   launch_fill_u8(W->mask, 0, &W->counters->n_slots_eff, std::max<int64_t>(W->cap_slots, 1), s);
   launch_fill_u32(W->counters->work_qb, 0u, kQueues * kLineWords, s);
-  launch_fill_u32((uint32_t*)&W->counters->bwd_evals, 0u, 4, s);   // bwd_evals, bwd_contrib
-  w_mark(W, 5, s);
-  launch_raster_bwd(mode, ds, W->d_views, W->d_up, sign ? W->d_out : nullptr, sign ? W->d_tgt : nullptr,
-                    sign ? W->d_lossw : nullptr, W->ranges, W->pvals, W->geom, W->app, W->app_bf16,
+  launch_raster_bwd(mode, ds, W->d_views, W->d_up + (size_t)gi * V, sign ? W->d_fo + (size_t)gi * V : nullptr,
+                    sign ? W->d_tgt + (size_t)gi * V : nullptr, sign ? W->d_lossw + 4 * gi : nullptr, W->ranges,
+                    W->pvals, W->geom, gi == 0 ? W->app : W->app_g[gi - 1], W->app_bf16,
                     (uint32_t)((1ull << W->npad_shift) - 1), W->items, W->items_static + W->plan.n_items,
                     W->plan.n_items, W->counters, W->st.chunk,
                     W->last_idx, W->T_state, W->slot_base, W->partials, W->mask, s);
+}
+
+// Feature groups 1 .. first (each: compositing backward, per-Gaussian
+// reduction, its geometric partials accumulated, its feature gradients
+// written), then group 0's compositing backward; its reduction and the
+// projection backward follow in enqueue_backward_reduce.
+void enqueue_backward_raster(Work* W, const lgs_grads* gr, int mode, hipStream_t s) {
+  const int V = (int)W->plan.views.size();
+  launch_fill_u32((uint32_t*)&W->counters->bwd_evals, 0u, 4, s);   // bwd_evals, bwd_contrib
+  w_mark(W, 5, s);
+  for (int gi = 1; gi < W->G; ++gi) {
+    launch_group_bwd(W, gi, mode, s);
+    launch_seg_reduce(W->slot_off, W->partials, W->mask, W->counters, W->n_rid, W->grad2d_g, s);
+    launch_group_geo_acc(W->grad2d_g, W->counters, W->n_rid, W->geo_acc, gi == 1, s);
+    launch_group_feat_grad(V, W->n, (uint32_t)W->npad_shift, W->counters, W->cnt_t, W->cidx, W->grad2d_g,
+                           group_nfeat(W->D, gi), gr->feat + (size_t)kFeatGroup * gi * (size_t)W->n, s);
+  }
+  launch_group_bwd(W, 0, mode, s);
   w_mark(W, 6, s);
 }
 
 void enqueue_backward_reduce(Work* W, const lgs_gaussians* g, const lgs_grads* gr, hipStream_t s) {
-  const Settings ds = dev_settings(&W->st, W->plan.tile_shift);
+  const Settings ds = dev_settings(&W->st, W->plan.tile_shift, W->D, 0);
   const int V = (int)W->plan.views.size();
   launch_seg_reduce(W->slot_off, W->partials, W->mask, W->counters, W->n_rid, W->grad2d, s);
+  if (W->G > 1) launch_group_geo_add(W->grad2d, W->counters, W->n_rid, W->geo_acc, s);
   launch_project_bwd(ds, W->d_views, V, g->means, g->log_scales, g->quats, g->opacity_logits, W->n,
                      W->npad_shift, W->counters, W->cnt_t, W->cidx, W->grad2d, gr->means, gr->log_scales,
                      gr->quats, gr->opacity_logits, gr->rgb, gr->feat, gr->twist, W->ttmp, s);
@@ -550,7 +658,7 @@ void enqueue_backward_reduce(Work* W, const lgs_gaussians* g, const lgs_grads* g
 }
 
 void enqueue_backward(Work* W, const lgs_gaussians* g, const lgs_grads* gr, int mode, hipStream_t s) {
-  enqueue_backward_raster(W, mode, s);
+  enqueue_backward_raster(W, gr, mode, s);
   enqueue_backward_reduce(W, g, gr, s);
 }
 
@@ -744,16 +852,15 @@ lgs_status lgs_backward(lgs_context* ctx, const lgs_fwd_state* Sc, const lgs_gau
   lgs_status rc;
   if ((rc = check_gaussians(ctx, g)) != LGS_OK) return rc;
   if (g->n != W->n) return fail(ctx, LGS_ERR_INVALID_ARG, "n differs from the forward's");
+  if (feat_dim_of(g) != W->D) return fail(ctx, LGS_ERR_INVALID_ARG, "feat_dim differs from the forward's");
   const int V = (int)W->plan.views.size();
   if ((rc = check_images(ctx, V, grad_out, false, "grad_out")) != LGS_OK) return rc;
   if ((rc = check_grads(ctx, g, grads)) != LGS_OK) return rc;
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   (void)hipGetLastError();   // launch checks below see only this call's errors
   if ((rc = w_alloc_bwd(W)) != LGS_OK) return rc;
-  std::vector<ViewImages> hup(V);
-  for (int v = 0; v < V; ++v)
-    hup[v] = ViewImages{grad_out[v].rgb, grad_out[v].depth, grad_out[v].feat, grad_out[v].final_T, nullptr};
-  HIP_TRY(ctx, hipMemcpyAsync(W->d_up, hup.data(), sizeof(ViewImages) * V, hipMemcpyHostToDevice, stream));
+  const std::vector<ViewImages> hup = group_tables(W, grad_out, TAB_UP);
+  HIP_TRY(ctx, hipMemcpyAsync(W->d_up, hup.data(), sizeof(ViewImages) * hup.size(), hipMemcpyHostToDevice, stream));
   enqueue_backward(W, g, grads, UP_EXPLICIT, stream);
   HIP_TRY(ctx, hipGetLastError());
   Counters hc;   // synchronises: hup goes out of scope
@@ -772,6 +879,7 @@ lgs_status lgs_backward_l1(lgs_context* ctx, const lgs_fwd_state* Sc, const lgs_
   lgs_status rc;
   if ((rc = check_gaussians(ctx, g)) != LGS_OK) return rc;
   if (g->n != W->n) return fail(ctx, LGS_ERR_INVALID_ARG, "n differs from the forward's");
+  if (feat_dim_of(g) != W->D) return fail(ctx, LGS_ERR_INVALID_ARG, "feat_dim differs from the forward's");
   const int V = (int)W->plan.views.size();
   if ((rc = check_images(ctx, V, out, true, "out")) != LGS_OK) return rc;
   if ((rc = check_images(ctx, V, targets, false, "targets")) != LGS_OK) return rc;
@@ -780,28 +888,27 @@ lgs_status lgs_backward_l1(lgs_context* ctx, const lgs_fwd_state* Sc, const lgs_
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   (void)hipGetLastError();   // launch checks below see only this call's errors
   if ((rc = w_alloc_bwd(W)) != LGS_OK) return rc;
-  std::vector<ViewImages> ho(V), ht(V);
-  for (int v = 0; v < V; ++v) {
-    ho[v] = ViewImages{out[v].rgb, out[v].depth, out[v].feat, out[v].final_T, nullptr};
-    ht[v] = ViewImages{targets[v].rgb, targets[v].depth, targets[v].feat, nullptr, nullptr};
-  }
-  const float lw[4] = {loss_w[0], loss_w[1], loss_w[2], 0.f};
-  HIP_TRY(ctx, hipMemcpyAsync(W->d_out, ho.data(), sizeof(ViewImages) * V, hipMemcpyHostToDevice, stream));
-  HIP_TRY(ctx, hipMemcpyAsync(W->d_tgt, ht.data(), sizeof(ViewImages) * V, hipMemcpyHostToDevice, stream));
-  HIP_TRY(ctx, hipMemcpyAsync(W->d_lossw, lw, sizeof lw, hipMemcpyHostToDevice, stream));
+  const std::vector<ViewImages> ho = group_tables(W, out, TAB_FO), ht = group_tables(W, targets, TAB_TGT);
+  const std::vector<float> lw = group_lossw(W, loss_w);
+  HIP_TRY(ctx, hipMemcpyAsync(W->d_fo, ho.data(), sizeof(ViewImages) * ho.size(), hipMemcpyHostToDevice, stream));
+  HIP_TRY(ctx, hipMemcpyAsync(W->d_tgt, ht.data(), sizeof(ViewImages) * ht.size(), hipMemcpyHostToDevice, stream));
+  HIP_TRY(ctx, hipMemcpyAsync(W->d_lossw, lw.data(), sizeof(float) * lw.size(), hipMemcpyHostToDevice, stream));
   enqueue_backward(W, g, grads, UP_L1, stream);
   HIP_TRY(ctx, hipGetLastError());
   Counters hc;   // synchronises: the host arrays go out of scope
   return read_counts(W, stream, &hc);
 }
 
-lgs_status lgs_loss(lgs_context* ctx, int32_t n_views, const lgs_camera* cams, const lgs_images* out,
-                    const lgs_images* targets, const float loss_w[3], float ssim_lambda, const lgs_images* grad,
-                    float* terms, hipStream_t stream) {
+lgs_status lgs_loss(lgs_context* ctx, int32_t n_views, const lgs_camera* cams, int32_t feat_dim,
+                    const lgs_images* out, const lgs_images* targets, const float loss_w[3], float ssim_lambda,
+                    const lgs_images* grad, float* terms, hipStream_t stream) {
   if (!ctx) return LGS_ERR_INVALID_ARG;
   ctx->err.clear();
   lgs_status rc;
   if ((rc = check_cams(ctx, n_views, cams)) != LGS_OK) return rc;
+  if (feat_dim == 0) feat_dim = kFeatGroup;
+  if (!(feat_dim == 8 || (feat_dim % kFeatGroup == 0 && feat_dim >= 16 && feat_dim <= 128)))
+    return fail(ctx, LGS_ERR_INVALID_ARG, "feat_dim must be 8 or a multiple of 16 up to 128 (0: 16)");
   if ((rc = check_images(ctx, n_views, out, false, "out")) != LGS_OK) return rc;
   if ((rc = check_images(ctx, n_views, targets, false, "targets")) != LGS_OK) return rc;
   if ((rc = check_images(ctx, n_views, grad, false, "grad")) != LGS_OK) return rc;
@@ -837,7 +944,7 @@ lgs_status lgs_loss(lgs_context* ctx, int32_t n_views, const lgs_camera* cams, c
       ctx->loss_part_cap = np;
     }
   }
-  make_loss_views(n_views, cams, out, targets, grad, loss_w, ssim_lambda, ctx->loss_host, &nd);
+  make_loss_views(n_views, cams, feat_dim, out, targets, grad, loss_w, ssim_lambda, ctx->loss_host, &nd);
   HIP_TRY(ctx, hipMemcpyAsync(ctx->loss_tab, ctx->loss_host, sizeof(LossView) * n_views, hipMemcpyHostToDevice,
                               stream));
   HIP_TRY(ctx, hipEventRecord(ctx->loss_copied, stream));
@@ -1052,12 +1159,11 @@ lgs_status lgs_graph_create(lgs_context* ctx, const lgs_settings* st, const lgs_
   if ((rc = w_alloc_bwd(W)) != LGS_OK) return bail(rc);
   if ((rc = w_upload(W, out, stream)) != LGS_OK) return bail(rc);
   {
-    std::vector<ViewImages> ht(n_views);
-    for (int v = 0; v < n_views; ++v)
-      ht[v] = ViewImages{targets[v].rgb, targets[v].depth, targets[v].feat, nullptr, nullptr};
-    float lw[4] = {loss_w[0], loss_w[1], loss_w[2], 0.f};
-    if (hipMemcpy(W->d_tgt, ht.data(), sizeof(ViewImages) * n_views, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(W->d_lossw, lw, sizeof lw, hipMemcpyHostToDevice) != hipSuccess)
+    const std::vector<ViewImages> ho = group_tables(W, out, TAB_FO), ht = group_tables(W, targets, TAB_TGT);
+    const std::vector<float> lw = group_lossw(W, loss_w);
+    if (hipMemcpy(W->d_fo, ho.data(), sizeof(ViewImages) * ho.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(W->d_tgt, ht.data(), sizeof(ViewImages) * ht.size(), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(W->d_lossw, lw.data(), sizeof(float) * lw.size(), hipMemcpyHostToDevice) != hipSuccess)
       return bail(fail(ctx, LGS_ERR_HIP, "upload failed"));
   }
   if (ssim_lambda != 0.f) {
@@ -1068,21 +1174,20 @@ lgs_status lgs_graph_create(lgs_context* ctx, const lgs_settings* st, const lgs_
     W->up_buf = (float*)w_alloc(W, sizeof(float) * 3 * std::max<int64_t>(W->plan.n_pix, 1), ok);
     W->loss_tab = (LossView*)w_alloc(W, sizeof(LossView) * n_views, ok);
     std::vector<lgs_images> gi(n_views);
-    std::vector<ViewImages> hu(n_views);
     for (int v = 0; v < n_views; ++v) {
       float* base = W->up_buf + 3 * (int64_t)W->plan.views[v].pix_off;
       gi[v] = lgs_images{base, nullptr, nullptr, nullptr, nullptr};
-      hu[v] = ViewImages{base, nullptr, nullptr, nullptr, nullptr};
     }
+    const std::vector<ViewImages> hu = group_tables(W, gi.data(), TAB_UP_RGB);
     std::vector<LossView> lv(n_views);
     int64_t n_df = 0;
-    W->loss_blocks = make_loss_views(n_views, cams, out, targets, gi.data(), loss_w, ssim_lambda, lv.data(),
-                                     &n_df);
+    W->loss_blocks = make_loss_views(n_views, cams, W->D, out, targets, gi.data(), loss_w, ssim_lambda,
+                                     lv.data(), &n_df);
     W->loss_part = (float2*)w_alloc(W, sizeof(float2) * std::max<int64_t>(W->loss_blocks, 1), ok);
     W->loss_k = loss_consts(ssim_lambda, n_views);
     if (!ok) return bail(fail(ctx, LGS_ERR_HIP, "device allocation failed (loss)"));
     if (hipMemcpy(W->loss_tab, lv.data(), sizeof(LossView) * n_views, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(W->d_up, hu.data(), sizeof(ViewImages) * n_views, hipMemcpyHostToDevice) != hipSuccess)
+        hipMemcpy(W->d_up, hu.data(), sizeof(ViewImages) * hu.size(), hipMemcpyHostToDevice) != hipSuccess)
       return bail(fail(ctx, LGS_ERR_HIP, "upload failed"));
   }
   if (hipStreamCreateWithFlags(&G->cap_stream, hipStreamNonBlocking) != hipSuccess)
@@ -1101,9 +1206,9 @@ lgs_status lgs_graph_create(lgs_context* ctx, const lgs_settings* st, const lgs_
           // the colour gradient (L1 + D-SSIM) into up_buf; depth and feature
           // L1 gradients are formed inside the backward
           launch_loss_rgb(W->loss_tab, W->loss_k, W->loss_blocks, W->loss_part, G->cap_stream);
-          enqueue_backward_raster(W, UP_RGB, G->cap_stream);
+          enqueue_backward_raster(W, &G->grads, UP_RGB, G->cap_stream);
         } else {
-          enqueue_backward_raster(W, UP_L1, G->cap_stream);
+          enqueue_backward_raster(W, &G->grads, UP_L1, G->cap_stream);
         }
         break;
       default: enqueue_backward_reduce(W, &G->g, &G->grads, G->cap_stream); break;

@@ -42,12 +42,13 @@ class GraphRun:
         self.ssim_lambda = ssim_lambda
         self.params = gpu_params(wl.scene, dev)
         V = len(wl.cams)
+        D = wl.scene.feat.shape[1]
         self.outs, self.tg = [], []
         self.imgs, self.tgts = (B.lgs_images * V)(), (B.lgs_images * V)()
         for v, c in enumerate(wl.cams):
             H, W = c.height, c.width
             o = {"rgb": torch.full((3, H, W), np.nan, device=dev), "depth": torch.full((H, W), np.nan, device=dev),
-                 "feat": torch.full((16, H, W), np.nan, device=dev), "T": torch.full((H, W), np.nan, device=dev)}
+                 "feat": torch.full((D, H, W), np.nan, device=dev), "T": torch.full((H, W), np.nan, device=dev)}
             self.outs.append(o)
             self.imgs[v] = B.lgs_images(o["rgb"].data_ptr(), o["depth"].data_ptr(), o["feat"].data_ptr(),
                                         o["T"].data_ptr(), None)
@@ -61,7 +62,7 @@ class GraphRun:
         self.grads = {"means": torch.full((3, n), np.nan, device=dev),
                       "log_scales": torch.full((3, n), np.nan, device=dev),
                       "quats": torch.full((4, n), np.nan, device=dev), "logits": torch.full((n,), np.nan, device=dev),
-                      "rgb": torch.full((3, n), np.nan, device=dev), "feat": torch.full((16, n), np.nan, device=dev),
+                      "rgb": torch.full((3, n), np.nan, device=dev), "feat": torch.full((D, n), np.nan, device=dev),
                       "twist": torch.full((V, 6), np.nan, device=dev)}
         self.gr = B.lgs_grads(*[self.grads[k].data_ptr() for k in
                                 ("means", "log_scales", "quats", "logits", "rgb", "feat", "twist")])

@@ -131,8 +131,9 @@ def test_loss_deterministic_and_rejects_bad_arguments(ctx):
     cc = (B.lgs_camera * V)(*[B.camera_c(c) for c in cams])
     im = B._images_c(_dev(outs), [(H, W) for (W, H) in sizes], False)
     lw = (C.c_float * 3)(1.0, 1.0, 1.0)
-    assert B.lib().lgs_loss(ctx._h, V, cc, im, im, lw, C.c_float(0.2), None, None, None) == B.LGS_ERR_INVALID_ARG
-    assert B.lib().lgs_loss(ctx._h, V, cc, im, im, None, C.c_float(0.2), im, None, None) == B.LGS_ERR_INVALID_ARG
+    assert B.lib().lgs_loss(ctx._h, V, cc, 16, im, im, lw, C.c_float(0.2), None, None, None) == B.LGS_ERR_INVALID_ARG
+    assert B.lib().lgs_loss(ctx._h, V, cc, 16, im, im, None, C.c_float(0.2), im, None, None) == B.LGS_ERR_INVALID_ARG
+    assert B.lib().lgs_loss(ctx._h, V, cc, 24, im, im, lw, C.c_float(0.2), im, None, None) == B.LGS_ERR_INVALID_ARG
 
 
 def test_step_with_dssim_graph_eager_and_oracle(ctx):
