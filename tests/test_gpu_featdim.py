@@ -155,3 +155,43 @@ def test_bf16_batched_reduced_at_32(ctx):
     say("  backward:", fmt(err))
     for k, (l2, mx) in err.items():
         assert l2 <= TOL_F32 and mx <= TOL_F32, (k, l2, mx)
+
+
+def test_dssim_step_at_32(ctx):
+    """The captured step with the D-SSIM loss at D = 32 (colour gradient from
+    the loss kernel, depth and the two feature groups' L1 gradients formed in
+    the backward) equals the eager forward + lgs_loss + lgs_backward to
+    rounding, and lgs_loss's feature term is a mean over the 32 planes."""
+    import paper_2511_16144_amd as P
+    from oracle import loss_fp64 as LF
+    from test_gpu_graph import GraphRun
+    D = 32
+    wl = scenes.make_workload(1, feat_dim=D)
+    ref = R.render(wl.scene, wl.cams, R.Settings())
+    wl.targets = separate_targets(ref, wl.targets)
+    say("[case] D = 32 with D-SSIM: graph vs eager, loss terms vs oracle")
+    st_ = P.Settings(tile=16)
+    run = GraphRun(ctx, wl, st_, ssim_lambda=0.2)
+    assert run.rc == 0
+    run.launch()
+    assert run.status() == 0
+    outs_g, gg = run.snapshot()
+    run.destroy()
+    prm = gpu_params(wl.scene)
+    outs, st = ctx.forward(prm, wl.cams, st_)
+    tg = [{"rgb": torch.as_tensor(t.rgb).cuda(), "depth": torch.as_tensor(t.depth).cuda(),
+           "feat": torch.as_tensor(t.feat).cuda()} for t in wl.targets]
+    ups, terms = ctx.loss(wl.cams, [{k: o[k] for k in ("rgb", "depth", "feat")} for o in outs], tg, wl.loss_w, 0.2)
+    ge = grads_np(ctx.backward(st, prm, ups))
+    torch.cuda.synchronize()
+    st.release()
+    for k in ge:
+        l2, mx = rel_err(ge[k], gg[k])
+        assert l2 <= 1e-5 and mx <= 1e-5, (k, l2, mx)
+    o = to_np(outs)
+    _, ref_terms, _ = LF.loss_and_upstream([{k: o[0][k] for k in ("rgb", "depth", "feat")}], wl.targets,
+                                           wl.loss_w, 0.2)
+    t = terms.cpu().numpy()[0]
+    say("  terms gpu", t, "oracle (on the GPU's images)", np.round(ref_terms[0], 7))
+    for i in range(4):
+        assert abs(t[i] - ref_terms[0][i]) <= 1e-5 * max(1.0, abs(ref_terms[0][i]))
