@@ -125,30 +125,6 @@ __device__ __forceinline__ void y_from_words(const uint32_t u[20], float y[20]) 
   }
 }
 
-// Appearance of a Gaussian as the 20-vector [r, g, b, (z), f0..f15]; slot 3
-// is filled by the caller with the view's depth.
-template <bool BF16>
-__device__ __forceinline__ void load_y(const void* __restrict__ app, uint32_t g, float y[20]) {
-  if (BF16) {
-    const uint32_t* a = (const uint32_t*)app + (size_t)g * 10;
-    uint32_t w[10];
-#pragma unroll
-    for (int k = 0; k < 10; ++k) w[k] = a[k];
-    y[0] = __uint_as_float(w[0] << 16);
-    y[1] = __uint_as_float(w[0] & 0xffff0000u);
-    y[2] = __uint_as_float(w[1] << 16);
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      y[4 + 2 * k] = __uint_as_float(w[2 + k] << 16);
-      y[5 + 2 * k] = __uint_as_float(w[2 + k] & 0xffff0000u);
-    }
-  } else {
-    const float* a = (const float*)app + (size_t)g * 20;
-#pragma unroll
-    for (int k = 0; k < 20; ++k) y[k] = a[k];
-  }
-}
-
 // Pop one work item for the whole wave.  Every active lane executes the
 // atomic (no lane-dependent branch around it): the first active lane adds 1,
 // the others 0, and the first active lane's return value is broadcast.  A
@@ -338,6 +314,15 @@ __device__ __forceinline__ int wave_max_i32(int x) {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 constexpr int kZRow = 72;                  // bf16 per LDS row (64 pixels + pad; 144 B, 16-B aligned)
+// Staging of up to 8 partial records before they are written out: 36 floats
+// per record (the 32 of a slot + pad: 16-B aligned rows whose banks differ),
+// then the 8 slot indices.
+constexpr int kRecLds = 36;
+constexpr int kStageBytes = (8 * kRecLds + 8) * 4;
+// LDS bytes of one backward wave: upstream rows, blend-weight rows, staging
+__host__ __device__ constexpr int bwd_wave_lds_bytes(int up_mode) {
+  return (bwd_upstream_rows(up_mode) + 16) * kZRow * 2 + kStageBytes;
+}
 // FP32 -> BF16 bits, round to nearest even (finite inputs)
 __device__ __forceinline__ unsigned short bf16_rne(float x) {
   const uint32_t u = __float_as_uint(x);
@@ -391,8 +376,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
   // channels), and the blend weights of up to 8 batched entries, hi (8) and
   // lo (8)
   constexpr int kGRows = bwd_upstream_rows(UPM);
-  unsigned short* lz = lds_z + (threadIdx.x >> 6) * ((kGRows + 16) * kZRow);
+  unsigned short* lz = lds_z + (threadIdx.x >> 6) * (bwd_wave_lds_bytes(UPM) / 2);
   unsigned short* wz = lz + kGRows * kZRow;
+  float* stage = (float*)(wz + 16 * kZRow);         // 8 records of kRecLds floats
+  uint32_t* sslot = (uint32_t*)(stage + 8 * kRecLds);   // their slot indices
   const int grp = lane >> 4, col = lane & 15;
   if (cnt->overflow) return;
   uint64_t n_eval = 0, n_con = 0;   // this wave's work, added to the counters once at the end
@@ -483,7 +470,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
       }
     }
     int nb = 0;
-    uint32_t slotv = 0;
+    // Write the batch's nb partial records: the colour partials join the
+    // geometric ones in the staged records, then every lane stores one
+    // 16-byte quarter of a record (one full 128-byte slot per 8 lanes) and
+    // the first lane of each record sets the slot's mask byte.
     auto flush = [&]() {
       f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
       const int er = col & 7;
@@ -515,14 +505,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
       }
       const float s0 = col < 3 ? gscale[0] : (col == 3 ? gscale[1] : gscale[2]);
       const float s1 = gscale[2];
+      if (grp < 2) {   // output rows 8..15 repeat rows 0..7
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int e = 4 * grp + i;
-        const uint32_t se = (uint32_t)__builtin_amdgcn_ds_bpermute((e & 7) * 4, (int)slotv);
-        if (e < nb) {
-          partials[(size_t)se * kPartials + 6 + col] = c0[i] * s0;
-          if (col < 4) partials[(size_t)se * kPartials + 22 + col] = c1[i] * s1;
+        for (int i = 0; i < 4; ++i) {
+          float* rec = stage + (4 * grp + i) * kRecLds;
+          rec[6 + col] = c0[i] * s0;
+          if (col < 4) rec[22 + col] = c1[i] * s1;
         }
+      }
+      const int er4 = lane >> 3, q4 = lane & 7;
+      const float4 v4 = *(const float4*)(stage + er4 * kRecLds + 4 * q4);
+      const uint32_t sl = sslot[er4];
+      if (er4 < nb) {
+        *(float4*)(partials + (size_t)sl * kSlotFloats + 4 * q4) = v4;
+        if (q4 == 0) mask[sl] = 1;
       }
       nb = 0;
     };
@@ -543,7 +539,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
         hm &= hm - 1ull;
         const int k = top - (int)j;
         const uint32_t rid = __builtin_amdgcn_readlane(rid_l, j);
+        // the entry's three records are requested together, before the
+        // evaluation, so their latencies overlap (the appearance and the slot
+        // base are not needed when no lane contributes, but loading them
+        // anyway costs less than a second round trip when one does)
         const GeomRec gr = geom[rid];
+        uint32_t yw[BF16 ? 10 : 20];
+        load_app_words<BF16>(app, rid & npad_mask, yw);
+        const uint32_t sbase = slot_base[rid];
         n_eval += (uint64_t)__popcll(__builtin_amdgcn_ballot_w64(k <= last));
         const int bx0 = (int)(gr.bbox & 255u), by0 = (int)((gr.bbox >> 16) & 255u);
         const float dx = (float)(px - 8 * bx0) - gr.mx;
@@ -554,7 +557,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
         if (cmask == 0ull) continue;
         n_con += (uint64_t)__popcll(cmask);
         float y[20];
-        load_y<BF16>(app, rid & npad_mask, y);
+        y_from_words<BF16>(yw, y);
         y[3] = gr.z;
         float vv[8];
         {
@@ -584,13 +587,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
         }
         const uint32_t bb = gr.bbox;
         const uint32_t bw = ((bb >> 8) & 255u) - (bb & 255u) + 1u;
-        const uint32_t slot = slot_base[rid] + (by - (uint32_t)by0) * bw + (bx - (uint32_t)bx0);
+        const uint32_t slot = sbase + (by - (uint32_t)by0) * bw + (bx - (uint32_t)bx0);
         const float s8 = transpose_reduce8(vv, lane);
-        if ((lane & 7) == 0 && (lane >> 3) < 6) partials[(size_t)slot * kPartials + (lane >> 3)] = s8;
-        slotv = lane == nb ? slot : slotv;
+        if ((lane & 7) == 0 && (lane >> 3) < 6) stage[nb * kRecLds + (lane >> 3)] = s8;
+        if (lane == 0) sslot[nb] = slot;
         ++nb;
         if (nb == 8) flush();
-        if (lane == 0) mask[slot] = 1;
       }
     }
     if (nb > 0) flush();
@@ -627,9 +629,21 @@ __global__ void __launch_bounds__(256) k_seg_reduce(const uint32_t* __restrict__
     for (int i = 0; i < 32; ++i) vv[i] = 0.f;
     for (uint32_t sl = base + (uint32_t)lane; sl < end; sl += 64) {
       if (mask[sl]) {
-        const float* pp = partials + (size_t)sl * kPartials;
+        // the record's seven 16-byte quarters are all requested before the
+        // first is added, so one memory round trip covers the slot
+        const f32x4* pp = (const f32x4*)(partials + (size_t)sl * kSlotFloats);
+        constexpr int kQ = (kPartials + 3) / 4;
+        f32x4 t[kQ];
 #pragma unroll
-        for (int i = 0; i < kPartials; ++i) vv[i] += pp[i];
+        for (int i = 0; i < kQ; ++i) t[i] = pp[i];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int i = 0; i < kQ; ++i) {
+          vv[4 * i] += t[i][0];
+          vv[4 * i + 1] += t[i][1];
+          if (4 * i + 2 < kPartials) vv[4 * i + 2] += t[i][2];
+          if (4 * i + 3 < kPartials) vv[4 * i + 3] += t[i][3];
+        }
       }
     }
     const float tot = transpose_reduce32(vv, lane);
@@ -676,7 +690,7 @@ static void launch_bwd_t(const Settings& st, const ViewDesc* views, const ViewIm
                          Counters* cnt, int waves_per_group, const int32_t* last_idx, const float* T_state,
                          const uint32_t* slot_base, float* partials, uint8_t* mask, hipStream_t s) {
   const int threads = 64 * waves_per_group;
-  const size_t lds = (size_t)waves_per_group * (bwd_upstream_rows(UPM) + 16) * kZRow * sizeof(unsigned short);
+  const size_t lds = (size_t)waves_per_group * bwd_wave_lds_bytes(UPM);
   int dev = 0, cus = 256;
   hipGetDevice(&dev);
   hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);

@@ -482,7 +482,7 @@ lgs_status w_alloc_bwd(Work* W) {
   if (W->bwd_alloc) return LGS_OK;
   bool ok = true;
   const int64_t S = std::max<int64_t>(W->cap_slots, 1);
-  W->partials = (float*)w_alloc(W, sizeof(float) * kPartials * S, ok);
+  W->partials = (float*)w_alloc(W, sizeof(float) * kSlotFloats * S, ok);
   W->mask = (uint8_t*)w_alloc(W, S + 8, ok);
   W->grad2d = (float*)w_alloc(W, sizeof(float) * kPartials * std::max<int64_t>(W->n_rid, 1), ok);
   W->ttmp = w_alloc(W, twist_temp_bytes(W->n, (int)W->plan.views.size()), ok);
