@@ -254,13 +254,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))
   }
 }
 
-// Butterfly transpose-reduction of 32 values over the wave.  On entry every
-// lane holds v[0..31]; on exit lanes 2i and 2i+1 hold the wave sum of value i.
-// Each step pairs every lane with a partner, each keeps one half of its
-// values and adds the partner's copy of that half: the two cross-row steps
-// use the gfx950 permlane swaps (no selects: the swap itself hands each half
-// to the lane that keeps it), the four in-row steps a bit-select and a DPP
-// read of the partner.
+// Butterfly transpose-reductions: every lane holds a vector of values and
+// the lanes' vectors are summed value by value, each lane ending with one of
+// the sums.  Each step pairs every lane with a partner, each keeps one half
+// of its values and adds the partner's copy of that half: cross-row steps use
+// the gfx950 permlane swaps (no selects: the swap itself hands each half to
+// the lane that keeps it), in-row steps a bit-select and a DPP read of the
+// partner.
 __device__ __forceinline__ float bsel(bool hi, float a, float b) {   // hi ? b : a
   const uint32_t m = hi ? 0xffffffffu : 0u;
   return __uint_as_float((__float_as_uint(a) & ~m) | (__float_as_uint(b) & m));
@@ -271,38 +271,33 @@ __device__ __forceinline__ float dpp(float x) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
 }
 
-__device__ __forceinline__ float transpose_reduce32(float v[32], int lane) {
-  float s[8];
+// Transpose-reduction of 32 values over each half of the wave separately:
+// on entry the lanes of a half hold v[0..31]; on exit lane l holds the sum
+// over its half of value l & 31.  Partners: l ^ 16 (permlane16 swap), l ^ 8
+// (row_ror:8), 7 - (l & 7) within the half row (row_half_mirror), l ^ 2 and
+// l ^ 1 (quad_perm).
+__device__ __forceinline__ float transpose_reduce_half32(const float v[32], int lane) {
+  float s[16];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
-    // lanes 0-31 keep value i / 8+i, lanes 32-63 keep 16+i / 24+i (sum over l, l^32)
-    auto r0 = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]), __float_as_uint(v[16 + i]), false, false);
-    auto r1 = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[8 + i]), __float_as_uint(v[24 + i]), false, false);
-    const float a = __uint_as_float(r0[0]) + __uint_as_float(r0[1]);
-    const float b = __uint_as_float(r1[0]) + __uint_as_float(r1[1]);
-    // rows 0, 2 keep a, rows 1, 3 keep b (sum over l, l^16)
-    auto r2 = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
-    s[i] = __uint_as_float(r2[0]) + __uint_as_float(r2[1]);
+  for (int i = 0; i < 16; ++i) {
+    // rows 0, 2 keep value i, rows 1, 3 keep 16 + i (sum over l, l^16)
+    auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[i]), __float_as_uint(v[16 + i]), false, false);
+    s[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
   }
-  float t[4];
+  float t[8];
   const bool h8 = (lane & 8) != 0;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {   // partner lane ^ 8 (row_ror:8)
-    const float keep = bsel(h8, s[i], s[4 + i]);
-    const float send = bsel(h8, s[4 + i], s[i]);
-    t[i] = keep + dpp<0x128>(send);
-  }
-  float u[2];
+  for (int i = 0; i < 8; ++i) t[i] = bsel(h8, s[i], s[8 + i]) + dpp<0x128>(bsel(h8, s[8 + i], s[i]));
+  float u[4];
   const bool h4 = (lane & 4) != 0;
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {   // partner 7 - (lane & 7) within the half row (row_half_mirror)
-    const float keep = bsel(h4, t[i], t[2 + i]);
-    const float send = bsel(h4, t[2 + i], t[i]);
-    u[i] = keep + dpp<0x141>(send);
-  }
-  const bool h2 = (lane & 2) != 0;   // partner lane ^ 2 (quad_perm 2,3,0,1)
-  const float w = bsel(h2, u[0], u[1]) + dpp<0x4E>(bsel(h2, u[1], u[0]));
-  return w + dpp<0xB1>(w);           // partner lane ^ 1 (quad_perm 1,0,3,2)
+  for (int i = 0; i < 4; ++i) u[i] = bsel(h4, t[i], t[4 + i]) + dpp<0x141>(bsel(h4, t[4 + i], t[i]));
+  float w[2];
+  const bool h2 = (lane & 2) != 0;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) w[i] = bsel(h2, u[i], u[2 + i]) + dpp<0x4E>(bsel(h2, u[2 + i], u[i]));
+  const bool h1 = (lane & 1) != 0;
+  return bsel(h1, w[0], w[1]) + dpp<0xB1>(bsel(h1, w[1], w[0]));
 }
 
 __device__ __forceinline__ int wave_max_i32(int x) {
@@ -330,7 +325,7 @@ __device__ __forceinline__ unsigned short bf16_rne(float x) {
 }
 __device__ __forceinline__ float bf16_to_f(unsigned short h) { return __uint_as_float((uint32_t)h << 16); }
 
-// Transpose-reduction of 8 values over the wave (as transpose_reduce32): on
+// Transpose-reduction of 8 values over the whole wave: on
 // exit lane l holds the wave sum of value l >> 3.
 __device__ __forceinline__ float transpose_reduce8(const float v[8], int lane) {
   float a[4];
@@ -608,9 +603,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
 // Per-Gaussian sum of the backward's partials.  Visible (view, Gaussian) c
 // owns the slot range [slot_off[c], slot_off[c + 1]) (the last one ends at
 // n_slots); a slot holds a partial only where the backward set its mask byte.
-// Waves loop over c (grid-stride, persistent grid); lane l sums slots
-// base + l, base + l + 64, ... in order, then the wave sums its lanes with the
-// butterfly transpose-reduction: a fixed order, so results are deterministic.
+// Each half of a wave takes one c (waves loop over pairs of c, grid-stride,
+// persistent grid), so a wave keeps two chains of dependent loads in flight;
+// lane l of a half sums slots base + l, base + l + 32, ... in order, then
+// the half sums its lanes with the butterfly transpose-reduction: a fixed
+// order, so results are deterministic.
 __global__ void __launch_bounds__(256) k_seg_reduce(const uint32_t* __restrict__ slot_off,
                                                     const float* __restrict__ partials,
                                                     const uint8_t* __restrict__ mask,
@@ -621,14 +618,21 @@ __global__ void __launch_bounds__(256) k_seg_reduce(const uint32_t* __restrict__
   const uint32_t nv = cnt->n_visible, ns = cnt->n_slots;
   const uint32_t n_waves = (gridDim.x * blockDim.x) >> 6;
   const uint32_t w0 = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-  for (uint32_t c = w0; c < nv; c += n_waves) {
-    const uint32_t base = slot_off[c];
-    const uint32_t end = c + 1 < nv ? slot_off[c + 1] : ns;
+  const uint32_t half = (uint32_t)lane >> 5, hl = (uint32_t)lane & 31u;
+  for (uint32_t c0 = 2 * w0; c0 < nv; c0 += 2 * n_waves) {
+    const uint32_t c = c0 + half;
+    uint32_t base = 0, len = 0;
+    if (c < nv) {
+      base = slot_off[c];
+      len = (c + 1 < nv ? slot_off[c + 1] : ns) - base;
+    }
+    const uint32_t maxlen = __builtin_amdgcn_readfirstlane(max(len, (uint32_t)__shfl_xor((int)len, 32, 64)));
     float vv[32];
 #pragma unroll
     for (int i = 0; i < 32; ++i) vv[i] = 0.f;
-    for (uint32_t sl = base + (uint32_t)lane; sl < end; sl += 64) {
-      if (mask[sl]) {
+    for (uint32_t o = hl; o < maxlen; o += 32) {
+      const uint32_t sl = base + o;
+      if (o < len && mask[sl]) {
         // the record's seven 16-byte quarters are all requested before the
         // first is added, so one memory round trip covers the slot
         const f32x4* pp = (const f32x4*)(partials + (size_t)sl * kSlotFloats);
@@ -646,9 +650,8 @@ __global__ void __launch_bounds__(256) k_seg_reduce(const uint32_t* __restrict__
         }
       }
     }
-    const float tot = transpose_reduce32(vv, lane);
-    const int idx = lane >> 1;
-    if ((lane & 1) == 0 && idx < kPartials) grad2d[(size_t)c * kPartials + idx] = tot;
+    const float tot = transpose_reduce_half32(vv, lane);
+    if (c < nv && hl < (uint32_t)kPartials) grad2d[(size_t)c * kPartials + hl] = tot;
   }
 }
 
@@ -737,7 +740,7 @@ void launch_seg_reduce(const uint32_t* slot_off, const float* partials, const ui
   hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_seg_reduce, 256, 0);
   int64_t grid = (int64_t)cus * (occ > 0 ? occ : 1);
-  const int64_t need = (n_max + 3) / 4;
+  const int64_t need = (n_max + 7) / 8;   // two visible ids per wave
   if (grid > need) grid = need;
   hipLaunchKernelGGL(k_seg_reduce, dim3((unsigned)grid), dim3(256), 0, s, slot_off, partials, mask, cnt, grad2d);
 }
