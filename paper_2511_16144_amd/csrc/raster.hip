@@ -148,6 +148,26 @@ __device__ __forceinline__ uint32_t next_item(uint32_t* ctr, const uint32_t* __r
   return k < e - b ? b + k : n_items;
 }
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+
+// Forward accumulation on the matrix cores (BF16 appearance).  The 20 sums
+// acc[p][s] = sum_e w[p][e] y[e][s] of a batch of 8 entries form one
+// v_mfma_f32_16x16x32_bf16 per group of 4 channel slots s and per term of
+// the weights: the K index runs over (pixel group g' = lane / 16, entry e),
+// the weights w (the B operand) are each lane's own, and the A operand is
+// block diagonal (the appearance y in the rows of the lane's own pixel group,
+// zero elsewhere), so the result lands in the lane of its pixel: lane l holds
+// acc[l][4 j + i] in register i of block j.  The weights are split exactly
+// into three BF16 terms (8 significant bits each) and the BF16 appearance is
+// exact, so every product is exact and only the FP32 accumulation rounds.
+// The depth slot is accumulated separately in FP32.
+// LDS of one wave: the batch's appearance [20 slots][8 entries], a zero block
+// of the same size, and the weights [3 terms][64 pixels][8 entries] (BF16).
+constexpr int kFwdY = 20 * 8;
+constexpr int kFwdW = 64 * 8;
+constexpr int kFwdWaveLds = (2 * kFwdY + 3 * kFwdW) * 2;
+
 // Eight waves per SIMD (64 VGPRs): measured faster than the compiler's own
 // register choice, which leaves room for only seven.
 template <bool BF16>
@@ -159,6 +179,18 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))
     Counters* __restrict__ cnt, int32_t* __restrict__ last_idx, float* __restrict__ T_state) {
   const int lane = threadIdx.x & 63;
   if (cnt->overflow) return;
+  extern __shared__ unsigned short lds_f[];
+  unsigned short* ys = lds_f + (threadIdx.x >> 6) * (kFwdWaveLds / 2);
+  unsigned short* yz = ys + kFwdY;
+  unsigned short* ws = yz + kFwdY;
+  // A-operand rows: lane l reads slot 4 j + (l & 3) when its row group
+  // (l & 15) / 4 equals its k-block l / 16, else the zero block
+  const unsigned short* abase = (((lane & 15) >> 2) == (lane >> 4) ? ys : yz) + (lane & 3) * 8;
+  const unsigned short* __restrict__ app16 = (const unsigned short*)app;
+  if (BF16) {
+    ((uint32_t*)yz)[lane] = 0u;
+    if (lane < kFwdY / 2 - 64) ((uint32_t*)yz)[64 + lane] = 0u;
+  }
   uint64_t n_eval = 0, n_con = 0;   // this wave's work, added to the counters once at the end
   const uint32_t q = blockIdx.x % (uint32_t)kQueues;
   for (;;) {
@@ -174,9 +206,31 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))
                           (bx >> st.tile_shift);
     const uint2 r = ranges[tile];
     float T = 1.f;
-    float acc[20];
+    float acc[20];   // FP32 appearance
 #pragma unroll
     for (int c = 0; c < 20; ++c) acc[c] = 0.f;
+    f32x4 D[5];      // BF16 appearance: slots 4 j .. 4 j + 3 of this lane's pixel
+#pragma unroll
+    for (int jb = 0; jb < 5; ++jb) D[jb] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    float accz = 0.f;
+    int nb = 0;
+    auto flush = [&]() {
+      if (nb < 8 && lane < 20)
+        for (int e = nb; e < 8; ++e) ys[lane * 8 + e] = 0;
+      // operands are read where they are used (the LDS reads are cheap;
+      // registers are not: they bound the waves per SIMD)
+#pragma unroll
+      for (int jb = 0; jb < 5; ++jb) {
+        const bf16x8_t a = *(const bf16x8_t*)(abase + 32 * jb);
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+          const bf16x8_t bw = *(const bf16x8_t*)(ws + t * kFwdW + lane * 8);
+          D[jb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw, D[jb], 0, 0, 0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      nb = 0;
+    };
     int32_t last = -1, ncon = 0;
     bool done = !inside;
     bool finished = __builtin_amdgcn_ballot_w64(!done) == 0ull;
@@ -196,7 +250,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))
       // the current one, so its latency overlaps that entry's evaluation
       uint32_t j = hm ? (uint32_t)__builtin_ctzll(hm) : 0u;
       uint32_t aw[20];
-      if (hm) load_app_words<BF16>(app, __builtin_amdgcn_readlane(rid_l, j) & npad_mask, aw);
+      unsigned short yh = 0;   // BF16: this lane's channel slot of the entry's appearance
+      if (hm) {
+        const uint32_t g0 = __builtin_amdgcn_readlane(rid_l, j) & npad_mask;
+        if (BF16) {
+          if (lane < 20) yh = app16[(size_t)g0 * 20 + lane];
+        } else {
+          load_app_words<BF16>(app, g0, aw);
+        }
+      }
       while (hm) {
         hm &= hm - 1ull;
         const uint32_t bb = __builtin_amdgcn_readlane(g_l.bbox, j);
@@ -213,15 +275,30 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))
         const uint64_t cmask = __builtin_amdgcn_ballot_w64(con);
         if (cmask != 0ull) {
           n_con += (uint64_t)__popcll(cmask);
-          float y[20];
-          y_from_words<BF16>(aw, y);
-          y[3] = bcast(g_l.z, j);
           const float w = con ? e.alpha * T : 0.f;
+          if (BF16) {
+            accz = __builtin_fmaf(w, bcast(g_l.z, j), accz);
+            // w = hi + mid + lo exactly: each term keeps the top 8 significant
+            // bits of what is left (truncation), so each is a BF16 value
+            const float whi = __uint_as_float(__float_as_uint(w) & 0xffff0000u);
+            const float r1 = w - whi;
+            const float wmid = __uint_as_float(__float_as_uint(r1) & 0xffff0000u);
+            const float wlo = r1 - wmid;
+            ws[lane * 8 + nb] = (unsigned short)(__float_as_uint(whi) >> 16);
+            ws[kFwdW + lane * 8 + nb] = (unsigned short)(__float_as_uint(wmid) >> 16);
+            ws[2 * kFwdW + lane * 8 + nb] = (unsigned short)(__float_as_uint(wlo) >> 16);
+            if (lane < 20) ys[lane * 8 + nb] = yh;
+          } else {
+            float y[20];
+            y_from_words<BF16>(aw, y);
+            y[3] = bcast(g_l.z, j);
 #pragma unroll
-          for (int c = 0; c < 20; ++c) acc[c] = __builtin_fmaf(w, y[c], acc[c]);
+            for (int c = 0; c < 20; ++c) acc[c] = __builtin_fmaf(w, y[c], acc[c]);
+          }
           T = con ? Tn : T;
           last = con ? (int32_t)(base + j) : last;
           ncon += con ? 1 : 0;
+          if (BF16 && ++nb == 8) flush();
         }
         if (__builtin_amdgcn_ballot_w64(!done) == 0ull) {
           finished = true;
@@ -229,9 +306,22 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))
         }
         if (hm) {
           j = (uint32_t)__builtin_ctzll(hm);
-          load_app_words<BF16>(app, __builtin_amdgcn_readlane(rid_l, j) & npad_mask, aw);
+          const uint32_t g0 = __builtin_amdgcn_readlane(rid_l, j) & npad_mask;
+          if (BF16) {
+            if (lane < 20) yh = app16[(size_t)g0 * 20 + lane];
+          } else {
+            load_app_words<BF16>(app, g0, aw);
+          }
         }
       }
+    }
+    if (BF16) {
+      if (nb > 0) flush();
+#pragma unroll
+      for (int jb = 0; jb < 5; ++jb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[4 * jb + i] = D[jb][i];
+      acc[3] = accz;
     }
     if (inside) {
       const ViewImages o = out[v];
@@ -306,8 +396,6 @@ __device__ __forceinline__ int wave_max_i32(int x) {
   return x;
 }
 
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 constexpr int kZRow = 72;                  // bf16 per LDS row (64 pixels + pad; 144 B, 16-B aligned)
 // Staging of up to 8 partial records before they are written out: 36 floats
 // per record (the 32 of a slot + pad: 16-B aligned rows whose banks differ),
@@ -667,8 +755,9 @@ void launch_raster_fwd(const Settings& st, const ViewDesc* views, const ViewImag
   hipGetDevice(&dev);
   hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   int occ = 1;
+  const size_t lds = app_bf16 ? (size_t)waves_per_group * kFwdWaveLds : 0;
   if (app_bf16)
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_raster_fwd<true>, threads, 0);
+    hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_raster_fwd<true>, threads, lds);
   else
     hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_raster_fwd<false>, threads, 0);
   int64_t grid = (int64_t)cus * (occ > 0 ? occ : 1);
@@ -676,7 +765,7 @@ void launch_raster_fwd(const Settings& st, const ViewDesc* views, const ViewImag
   if (grid > need) grid = need;
   if (grid < kQueues) grid = kQueues;   // every queue needs a workgroup (index mod kQueues) to drain it
   if (app_bf16)
-    hipLaunchKernelGGL(k_raster_fwd<true>, dim3((unsigned)grid), dim3(threads), 0, s, st, views, out,
+    hipLaunchKernelGGL(k_raster_fwd<true>, dim3((unsigned)grid), dim3(threads), lds, s, st, views, out,
                        ranges, vals, geom, app, npad_mask, items, qoff, (uint32_t)n_items, cnt, last_idx,
                        T_state);
   else
