@@ -188,8 +188,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))
   const unsigned short* abase = (((lane & 15) >> 2) == (lane >> 4) ? ys : yz) + (lane & 3) * 8;
   const unsigned short* __restrict__ app16 = (const unsigned short*)app;
   if (BF16) {
+    // the zero block, and the weights: a partial batch leaves the weights of
+    // its unused entries as they were (their appearance is zeroed instead),
+    // so they must never hold a NaN or infinity from whatever LDS held before
     ((uint32_t*)yz)[lane] = 0u;
     if (lane < kFwdY / 2 - 64) ((uint32_t*)yz)[64 + lane] = 0u;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) *(uint4*)(ws + t * kFwdW + lane * 8) = make_uint4(0u, 0u, 0u, 0u);
   }
   uint64_t n_eval = 0, n_con = 0;   // this wave's work, added to the counters once at the end
   const uint32_t q = blockIdx.x % (uint32_t)kQueues;

@@ -137,3 +137,35 @@ def test_backward_run_to_run_bitwise(ctx, c1):
         res.append(g)
     for k in res[0]:
         assert np.array_equal(res[0][k], res[1][k]), k
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_tiny_bf16_after_other_kernels(ctx, seed):
+    """BF16-appearance forward on sparse scenes (most 8x8 blocks see fewer
+    than 8 contributing entries, so the first batch a wave composites on the
+    matrix cores is partial), run right after a batched forward + backward
+    has left arbitrary data in LDS: every output finite and equal to the
+    brute-force render of the BF16-rounded scene."""
+    import paper_2511_16144_amd as P
+    big = scenes.make_workload(4, n=60000, res_scale=0.25)
+    say(f"[case] tiny BF16 seed={seed} after a batched step ({big.scene.n} Gaussians)")
+    prm = gpu_params(big.scene)
+    outs, st = ctx.forward(prm, big.cams, P.Settings(tile=16))
+    ctx.backward(st, prm, upstream_tensors(scenes.random_upstream(7, big.cams)))
+    torch.cuda.synchronize()
+    st.release()
+    wl = scenes.tiny_scene(seed, 10 + 5 * seed, 61, 45)
+    sc = wl.scene
+    s16 = scenes.Scene(sc.means, sc.log_scales, sc.quats, sc.logits, scenes.round_bf16(sc.rgb),
+                       scenes.round_bf16(sc.feat), "bf16")
+    wl16 = scenes.Workload(wl.name, s16, wl.cams, wl.targets)
+    Yb, Tb, nb, _ = brute.render_view(s16, wl.cams[0], R.Settings())
+    Yb = np.array(Yb).transpose(2, 0, 1)
+    for tile in (8, 16):
+        _, out, state = run_fwd(ctx, wl16, tile=tile)
+        state.release()
+        got = np.concatenate([out[0]["rgb"], out[0]["depth"][None], out[0]["feat"]], 0)
+        assert np.isfinite(got).all()
+        assert np.allclose(got, Yb, rtol=1e-4, atol=1e-5)
+        assert np.allclose(out[0]["T"], np.array(Tb), rtol=1e-4, atol=1e-6)
+        assert np.array_equal(out[0]["n"], np.array(nb))
