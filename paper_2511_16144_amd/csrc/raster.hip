@@ -150,6 +150,7 @@ __device__ __forceinline__ uint32_t next_item(uint32_t* ctr, const uint32_t* __r
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 
 // Forward accumulation on the matrix cores (BF16 appearance).  The 20 sums
 // acc[p][s] = sum_e w[p][e] y[e][s] of a batch of 8 entries form one
@@ -196,7 +197,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))
 #pragma unroll
     for (int t = 0; t < 3; ++t) *(uint4*)(ws + t * kFwdW + lane * 8) = make_uint4(0u, 0u, 0u, 0u);
   }
-  uint64_t n_eval = 0, n_con = 0;   // this wave's work, added to the counters once at the end
+  // this wave's work, added to the 64-bit counters once at the end (a wave's
+  // own count stays far below 2^32)
+  uint32_t n_eval = 0, n_con = 0;
   const uint32_t q = blockIdx.x % (uint32_t)kQueues;
   for (;;) {
     const uint32_t it = next_item(cnt->work_q, qoff, q, n_items);
@@ -267,7 +270,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))
       while (hm) {
         hm &= hm - 1ull;
         const uint32_t bb = __builtin_amdgcn_readlane(g_l.bbox, j);
-        n_eval += (uint64_t)__popcll(__builtin_amdgcn_ballot_w64(!done));
+        n_eval += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(!done));
         const float dx = (float)(px - 8 * (int)(bb & 255u)) - bcast(g_l.mx, j);
         const float dy = (float)(py - 8 * (int)((bb >> 16) & 255u)) - bcast(g_l.my, j);
         const Eval e = eval_entry(dx, dy, bcast(g_l.qa, j), bcast(g_l.qb2, j), bcast(g_l.qc, j),
@@ -279,7 +282,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))
         con = con && !term;
         const uint64_t cmask = __builtin_amdgcn_ballot_w64(con);
         if (cmask != 0ull) {
-          n_con += (uint64_t)__popcll(cmask);
+          n_con += (uint32_t)__popcll(cmask);
           const float w = con ? e.alpha * T : 0.f;
           if (BF16) {
             accz = __builtin_fmaf(w, bcast(g_l.z, j), accz);
@@ -470,7 +473,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
   uint32_t* sslot = (uint32_t*)(stage + 8 * kRecLds);   // their slot indices
   const int grp = lane >> 4, col = lane & 15;
   if (cnt->overflow) return;
-  uint64_t n_eval = 0, n_con = 0;   // this wave's work, added to the counters once at the end
+  // this wave's work, added to the 64-bit counters once at the end (a wave's
+  // own count stays far below 2^32)
+  uint32_t n_eval = 0, n_con = 0;
   const uint32_t q = blockIdx.x % (uint32_t)kQueues;
   for (;;) {
     const uint32_t it = next_item(cnt->work_qb, qoff, q, n_items);
@@ -557,6 +562,21 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
         lz[(20 + c) * kZRow + lane] = bf16_rne(g[c] - bf16_to_f(hi));
       }
     }
+    // Feature part of gy = sum_c g[c] y[c] with BF16 appearance and the sign
+    // upstream: s_f sum_f sign_f y_f, the sum by packed BF16 dot products of
+    // the appearance words (two features each, used as they are stored) with
+    // the signs packed the same way; every product is exact.
+    constexpr bool kDotGy = BF16 && kSignDF;
+    uint32_t sg2[8];
+    if (kDotGy) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const float a = g[4 + 2 * k], b = g[5 + 2 * k];
+        const uint32_t lo = a > 0.f ? 0x3f80u : (a < 0.f ? 0xbf80u : 0u);
+        const uint32_t hi = b > 0.f ? 0x3f80u : (b < 0.f ? 0xbf80u : 0u);
+        sg2[k] = lo | (hi << 16);
+      }
+    }
     int nb = 0;
     // Write the batch's nb partial records: the colour partials join the
     // geometric ones in the staged records, then every lane stores one
@@ -635,7 +655,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
         uint32_t yw[BF16 ? 10 : 20];
         load_app_words<BF16>(app, rid & npad_mask, yw);
         const uint32_t sbase = slot_base[rid];
-        n_eval += (uint64_t)__popcll(__builtin_amdgcn_ballot_w64(k <= last));
+        n_eval += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(k <= last));
         const int bx0 = (int)(gr.bbox & 255u), by0 = (int)((gr.bbox >> 16) & 255u);
         const float dx = (float)(px - 8 * bx0) - gr.mx;
         const float dy = (float)(py - 8 * by0) - gr.my;
@@ -643,7 +663,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
         const bool con = (k <= last) && e.pass;
         const uint64_t cmask = __builtin_amdgcn_ballot_w64(con);
         if (cmask == 0ull) continue;
-        n_con += (uint64_t)__popcll(cmask);
+        n_con += (uint32_t)__popcll(cmask);
         float y[20];
         y_from_words<BF16>(yw, y);
         y[3] = gr.z;
@@ -653,8 +673,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
           const float Tp = Tc * rinv;
           const float w = e.alpha * Tp;
           float gy = 0.f;
+          if (kDotGy) {
+            float fs = 0.f;
 #pragma unroll
-          for (int c = 0; c < 20; ++c) gy = __builtin_fmaf(g[c], y[c], gy);
+            for (int k = 0; k < 8; ++k)
+              fs = __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, yw[2 + k]),
+                                                   __builtin_bit_cast(bf16x2_t, sg2[k]), fs, false);
+            gy = gscale[2] * fs;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) gy = __builtin_fmaf(g[c], y[c], gy);
+          } else {
+#pragma unroll
+            for (int c = 0; c < 20; ++c) gy = __builtin_fmaf(g[c], y[c], gy);
+          }
           const float dal = Tp * gy - (sB + gTT) * rinv;
           const float wc = con ? w : 0.f;
           sB = con ? __builtin_fmaf(w, gy, sB) : sB;
@@ -669,9 +700,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
           vv[5] = dgeo * e.G;
           vv[6] = 0.f;
           vv[7] = 0.f;
-          const unsigned short wh = bf16_rne(wc);
-          wz[nb * kZRow + lane] = wh;
-          wz[(8 + nb) * kZRow + lane] = bf16_rne(wc - bf16_to_f(wh));
+          // hi = RNE(wc), lo = RNE(wc - hi): the hardware conversion
+          const __bf16 wh = (__bf16)wc;
+          wz[nb * kZRow + lane] = __builtin_bit_cast(unsigned short, wh);
+          wz[(8 + nb) * kZRow + lane] = __builtin_bit_cast(unsigned short, (__bf16)(wc - (float)wh));
         }
         const uint32_t bb = gr.bbox;
         const uint32_t bw = ((bb >> 8) & 255u) - (bb & 255u) + 1u;
