@@ -39,12 +39,15 @@ PEAK_HBM_GBS = 8000.0
 #                 alpha 2, the two cut tests 2                      = 16
 #   forward contribution : T' 2, stop test 1, weight 1, 20 FMAs 40   = 44
 #   backward contribution: 1 - alpha, 1/(1-alpha), T_prev, weight 4,
-#                 g.y 40, dL/dalpha 5, running sum 2, chain to
-#                 mean'/conic/opacity 14, 20 colour partials 20,
-#                 sum of the 26 partials over pixels 26              = 111
+#                 g.y 40, dL/dalpha 5, running sum 2, dL/dm2 2, its
+#                 five moments over the pixel offsets 5, opacity 1,
+#                 20 colour partials 20, sum of the 26 partials over
+#                 pixels 26                                         = 105
+#   (the conic's entries multiply the summed moments once per Gaussian, in
+#   the projection backward, not per pixel)
 FLOPS_EVAL = 16
 FLOPS_FWD_CONTRIB = 44
-FLOPS_BWD_CONTRIB = 111
+FLOPS_BWD_CONTRIB = 105
 
 
 def measured_traffic(kernel, settings, workload):

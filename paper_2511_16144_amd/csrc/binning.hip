@@ -249,8 +249,22 @@ __global__ void __launch_bounds__(kOrderThreads) k_order_items(const ViewDesc* _
   __shared__ uint32_t wsum[kOrderThreads / 64];
   for (int i = threadIdx.x; i < kOrderBins; i += kOrderThreads) hist[i] = 0u;
   __syncthreads();
-  for (int64_t i = threadIdx.x; i < n_items; i += kOrderThreads)
-    atomicAdd(&hist[item_key(views, ranges, tile_shift, items[i])], 1u);
+  // keys are computed 8 items at a time per thread, without branches (an
+  // index past the end reads the last item and is dropped afterwards), so
+  // that the 8 chains of dependent loads (item, view, tile range) are in
+  // flight together
+  constexpr int kU = 8;
+  for (int64_t b = threadIdx.x; b < n_items; b += (int64_t)kOrderThreads * kU) {
+    uint32_t key[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int64_t i = b + (int64_t)u * kOrderThreads;
+      key[u] = item_key(views, ranges, tile_shift, items[i < n_items ? i : n_items - 1]);
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (b + (int64_t)u * kOrderThreads < n_items) atomicAdd(&hist[key[u]], 1u);
+  }
   __syncthreads();
   // exclusive scan of the bins, two per thread
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -268,9 +282,17 @@ __global__ void __launch_bounds__(kOrderThreads) k_order_items(const ViewDesc* _
   hist[2 * threadIdx.x] = ex;
   hist[2 * threadIdx.x + 1] = ex + a;
   __syncthreads();
-  for (int64_t i = threadIdx.x; i < n_items; i += kOrderThreads) {
-    const uint32_t it = items[i];
-    out[atomicAdd(&hist[item_key(views, ranges, tile_shift, it)], 1u)] = it;
+  for (int64_t b = threadIdx.x; b < n_items; b += (int64_t)kOrderThreads * kU) {
+    uint32_t it[kU], key[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int64_t i = b + (int64_t)u * kOrderThreads;
+      it[u] = items[i < n_items ? i : n_items - 1];
+      key[u] = item_key(views, ranges, tile_shift, it[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (b + (int64_t)u * kOrderThreads < n_items) out[atomicAdd(&hist[key[u]], 1u)] = it[u];
   }
 }
 

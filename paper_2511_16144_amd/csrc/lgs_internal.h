@@ -11,7 +11,7 @@ namespace lgs {
 constexpr int kBlock = 8;
 constexpr int kMaxSide = 2048;          // 8-bit block coordinates in records
 constexpr int kChannels = 20;           // RGB 3 + depth 1 + feature 16
-constexpr int kPartials = 26;           // mu' 2, conic 3, opacity 1, y 20
+constexpr int kPartials = 26;           // geometric moments 5, opacity 1, y 20
 constexpr int kSlotFloats = 32;         // a backward slot record: the kPartials floats padded to 128 bytes
 
 // Per-view constants, shared by every stage (device array of n_views).

@@ -25,7 +25,8 @@
 // Backward.  Each wave restarts from the last contributor of its pixels and
 // walks the list backwards, recovering T before each entry as T / (1 - alpha)
 // and the weighted sum of what lies behind as a single running scalar.  Per
-// entry, the 6 geometric partial derivatives (mean' 2, conic 3, opacity 1) are
+// entry, the 6 geometric sums (the moments of dL/dm2 over the pixel offsets
+// dx, dy, dx^2, dx dy, dy^2, and dL/dalpha-weighted G for the opacity) are
 // summed over the wave by a butterfly transpose-reduction; the 20 colour /
 // depth / feature partials, sum_p w_p g_p, are collected for batches of 8
 // entries as a (entries x pixels) x (pixels x channels) product on the matrix
@@ -691,12 +692,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
           sB = con ? __builtin_fmaf(w, gy, sB) : sB;
           Tc = con ? Tp : Tc;
           const float dgeo = (con && !(e.araw > st.alpha_max)) ? dal : 0.f;
+          // dL/dm2 per pixel; the slot keeps its moments over the pixel
+          // offsets (the conic's entries are per Gaussian, so they are
+          // applied once to the summed moments in the projection backward)
           const float dm2 = dgeo * (-0.5f * e.alpha);
-          vv[0] = -dm2 * (2.f * gr.qa * dx + gr.qb2 * dy);
-          vv[1] = -dm2 * (gr.qb2 * dx + 2.f * gr.qc * dy);
-          vv[2] = dm2 * dx * dx;
-          vv[3] = dm2 * 2.f * dx * dy;
-          vv[4] = dm2 * dy * dy;
+          const float mxd = dm2 * dx, myd = dm2 * dy;
+          vv[0] = mxd;
+          vv[1] = myd;
+          vv[2] = mxd * dx;
+          vv[3] = mxd * dy;
+          vv[4] = myd * dy;
           vv[5] = dgeo * e.G;
           vv[6] = 0.f;
           vv[7] = 0.f;
