@@ -276,21 +276,42 @@ __global__ void __launch_bounds__(256) k_project_bwd(
   }
   Proj P;
   bool any = false;
+  // views are taken 8 at a time with branch-free (clamped) loads, so that
+  // their visibility and record index loads are in flight together
+  constexpr int kVB = 8;
   if (active && cnt->overflow == 0u) {
-    for (int v = 0; v < n_views && !any; ++v)
-      any = cnt_t[((uint64_t)v << npad_shift) | (uint64_t)g] != 0;
+    for (int v0 = 0; v0 < n_views && !any; v0 += kVB) {
+      uint32_t c[kVB];
+#pragma unroll
+      for (int u = 0; u < kVB; ++u)
+        c[u] = cnt_t[((uint64_t)min(v0 + u, n_views - 1) << npad_shift) | (uint64_t)g];
+#pragma unroll
+      for (int u = 0; u < kVB; ++u) any = any || (v0 + u < n_views && c[u] != 0u);
+    }
   }
   if (any) activate(p, ls, q, logit, P);
   double gp[3] = {0, 0, 0}, gM[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, glogit = 0.0;
   float gy[20];
   for (int k = 0; k < 20; ++k) gy[k] = 0.f;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t cix[kVB];   // record index of views v0 .. v0 + 7 (~0 where not visible)
   for (int v = 0; v < n_views; ++v) {
+    if ((v & (kVB - 1)) == 0) {
+#pragma unroll
+      for (int u = 0; u < kVB; ++u) {
+        cix[u] = ~0u;
+        if (any) {
+          const uint64_t r = ((uint64_t)min(v + u, n_views - 1) << npad_shift) | (uint64_t)g;
+          const uint32_t c = cnt_t[r], ci = cidx[r];
+          cix[u] = (v + u < n_views && c != 0u) ? ci : ~0u;
+        }
+      }
+    }
     double tw[6] = {0, 0, 0, 0, 0, 0};
-    const uint64_t rid = ((uint64_t)v << npad_shift) | (uint64_t)g;
-    if (any && cnt_t[rid] != 0) {
+    const uint32_t ci = cix[v & (kVB - 1)];
+    if (ci != ~0u) {
       const ViewDesc V = views[v];
-      const float* G = grad2d + (size_t)cidx[rid] * kPartials;
+      const float* G = grad2d + (size_t)ci * kPartials;
       Screen S;
       to_screen(V, p, P, (double)st.eps2d, S);
       const double z = S.xc[2], iz = 1.0 / z;
