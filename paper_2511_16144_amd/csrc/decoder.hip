@@ -16,7 +16,9 @@
 // Work-group = 8 waves (two per SIMD: one wave's target loads overlap the
 // other's matrix products); a work-group walks a contiguous run of 32-pixel
 // chunks of the image (a fixed assignment, so its partial sums are
-// deterministic), loading the next chunk's inputs while it works on one.  Wave w owns the channels [C/8 w, C/8 (w+1)): per chunk it
+// deterministic), loading the next chunk's inputs while it works on one,
+// with one work-group barrier per chunk.  Wave w owns the channels
+// [C/8 w, C/8 (w+1)): per chunk it
 // forms its Z^T tiles (16 pixels x 16 channels; the pixel order of the rows
 // gives lane l 8 consecutive pixels of one channel over the chunk's two
 // column groups, so its targets are one 16-byte load per channel), the
@@ -102,13 +104,14 @@ __global__ __launch_bounds__(kDecThreads) void k_decoder(DecArgs a, const TT* __
   constexpr int Cw = 16 * NT;             // channels per wave
   constexpr int KS = Cw / 32;             // 32-channel steps of the dF product
   static_assert(KS >= 1, "at least 32 channels per wave");
-  __shared__ __attribute__((aligned(16))) unsigned short fA[kChunk * kFA];     // [pixel][F_hi 16 | F_lo 16]
-  __shared__ __attribute__((aligned(16))) unsigned short fT[2 * 16 * kFT];     // [hi/lo][feature][pixel]
+  // F rows and the waves' dF partials are double-buffered by chunk parity,
+  // so that one work-group barrier per chunk suffices (see the loop)
+  __shared__ __attribute__((aligned(16))) unsigned short fA[2][kChunk * kFA];     // [pixel][F_hi 16 | F_lo 16]
+  __shared__ __attribute__((aligned(16))) unsigned short fT[2][2 * 16 * kFT];     // [hi/lo][feature][pixel]
   __shared__ __attribute__((aligned(16))) unsigned short rC[kDecWaves][Cw * kRC];      // [channel][pixel] signs
   __shared__ __attribute__((aligned(16))) unsigned short rP[kDecWaves][kChunk * Cw];   // [pixel][channel] signs
+  __shared__ __attribute__((aligned(16))) float dfr[2][kDecWaves * 16 * kChunk];      // [wave][feature][pixel]
   __shared__ float red[kDecWaves];
-  static_assert(Cw * kRC * 2 >= 16 * kChunk * 4, "dF partials fit over the sign rows");
-  float* dfr = (float*)&rC[0][0];                      // [wave][feature][pixel] dF partials (after the MFMAs)
 
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int r16 = lane & 15, q4 = lane >> 4;
@@ -195,27 +198,46 @@ __global__ __launch_bounds__(kDecThreads) void k_decoder(DecArgs a, const TT* __
   const int64_t per = (n_chunks + gridDim.x - 1) / gridDim.x;
   const int64_t ck0 = (int64_t)blockIdx.x * per;
   const int64_t ck1 = ck0 + per < n_chunks ? ck0 + per : n_chunks;
+  // chunk pc's dL/dF: the 8 waves' partials (buffer par) summed in a fixed order
+  auto store_df = [&](int64_t pc, int par) {
+    const int64_t q0 = pc * kChunk;
+    for (int e = t; e < 16 * kChunk; e += kDecThreads) {
+      const int k = e >> 5, px = e & 31;
+      float v = 0.f;
+#pragma unroll
+      for (int u = 0; u < kDecWaves; ++u) v += dfr[par][(u * 16 + k) * kChunk + px];
+      if (q0 + px < n) a.grad_feat[(size_t)k * n + q0 + px] = a.scale * v;
+    }
+  };
   if (ck0 < ck1) fetch(ck0);
   for (int64_t ck = ck0; ck < ck1; ++ck) {
     const int64_t p0 = ck * kChunk;
+    const int par = (int)((ck - ck0) & 1);
+    const unsigned short* fAc = fA[par];
+    const unsigned short* fTc = fT[par];
     // (1) F chunk -> LDS: [pixel][F_hi | F_lo] and [hi/lo][feature][pixel]
     {
       const unsigned short hi = to_bf16(fr), lo = to_bf16(fr - from_bf16(hi));
-      fA[fpx * kFA + fk] = hi;
-      fA[fpx * kFA + 16 + fk] = lo;
-      fT[fk * kFT + fpx] = hi;
-      fT[16 * kFT + fk * kFT + fpx] = lo;
+      fA[par][fpx * kFA + fk] = hi;
+      fA[par][fpx * kFA + 16 + fk] = lo;
+      fT[par][fk * kFT + fpx] = hi;
+      fT[par][16 * kFT + fk * kFT + fpx] = lo;
     }
     RawT cur[NT];
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) cur[nt] = tr[nt];
     if (ck + 1 < ck1) fetch(ck + 1);
-    lds_barrier();   // also: every thread has read the previous chunk's dF partials
+    // The one barrier of the chunk: the F rows of this chunk are complete, and
+    // every wave has finished the previous chunk (its dF partials are in the
+    // other buffer, and it no longer reads this buffer's F rows from two
+    // chunks ago).  The sign rows are per wave and need no barrier.
+    lds_barrier();
+    if (ck > ck0) store_df(ck - 1, par ^ 1);
     // (2) Z^T tiles, signs, loss, db; signs to LDS in both layouts
 #pragma unroll
     for (int cg = 0; cg < 2; ++cg) {
       // A row r16 of column group cg is pixel 8 (r16 / 4) + 4 cg + r16 % 4
-      const bf16x8_t af = as_bf16x8(*(const u16x8*)(fA + (8 * (r16 >> 2) + 4 * cg + (r16 & 3)) * kFA + 8 * q4));
+      const bf16x8_t af = as_bf16x8(*(const u16x8*)(fAc + (8 * (r16 >> 2) + 4 * cg + (r16 & 3)) * kFA + 8 * q4));
       const int pl = 8 * q4 + 4 * cg;    // first of this lane's 4 pixels of this column group
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
@@ -243,8 +265,8 @@ __global__ __launch_bounds__(kDecThreads) void k_decoder(DecArgs a, const TT* __
     }
     // (3) dW^T += F R^T over the chunk's 32 pixels (A = F hi/lo, B = signs)
     {
-      const bf16x8_t fh = as_bf16x8(*(const u16x8*)(fT + r16 * kFT + 8 * q4));
-      const bf16x8_t fl = as_bf16x8(*(const u16x8*)(fT + 16 * kFT + r16 * kFT + 8 * q4));
+      const bf16x8_t fh = as_bf16x8(*(const u16x8*)(fTc + r16 * kFT + 8 * q4));
+      const bf16x8_t fl = as_bf16x8(*(const u16x8*)(fTc + 16 * kFT + r16 * kFT + 8 * q4));
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
         const bf16x8_t rb = as_bf16x8(*(const u16x8*)(&rC[w][(16 * nt + r16) * kRC + 8 * q4]));
@@ -264,22 +286,13 @@ __global__ __launch_bounds__(kDecThreads) void k_decoder(DecArgs a, const TT* __
         dfa[cg] = mfma(wt_l[ks], rb, dfa[cg]);
       }
     }
-    lds_barrier();   // every wave is done with rC / rP: the dF partials take their place
 #pragma unroll
     for (int cg = 0; cg < 2; ++cg)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) dfr[(w * 16 + 4 * q4 + i) * kChunk + 16 * cg + r16] = dfa[cg][i];
-    lds_barrier();
-    for (int e = t; e < 16 * kChunk; e += kDecThreads) {
-      const int k = e >> 5, px = e & 31;
-      float v = 0.f;
-#pragma unroll
-      for (int u = 0; u < kDecWaves; ++u) v += dfr[(u * 16 + k) * kChunk + px];
-      if (p0 + px < n) a.grad_feat[(size_t)k * n + p0 + px] = a.scale * v;
-    }
-    // no barrier here: the next chunk writes fA / fT (free since the last
-    // barrier) before its first barrier, and rC / rP only after it
+      for (int i = 0; i < 4; ++i) dfr[par][(w * 16 + 4 * q4 + i) * kChunk + 16 * cg + r16] = dfa[cg][i];
   }
+  lds_barrier();
+  if (ck1 > ck0) store_df(ck1 - 1, (int)((ck1 - 1 - ck0) & 1));
 
   // partials of this work-group: dW [C][16], db [C], loss
   float* pb = part + (size_t)blockIdx.x * a.part_stride;
