@@ -109,7 +109,11 @@ __global__ __launch_bounds__(kDecThreads) void k_decoder(DecArgs a, const TT* __
   __shared__ __attribute__((aligned(16))) unsigned short fA[2][kChunk * kFA];     // [pixel][F_hi 16 | F_lo 16]
   __shared__ __attribute__((aligned(16))) unsigned short fT[2][2 * 16 * kFT];     // [hi/lo][feature][pixel]
   __shared__ __attribute__((aligned(16))) unsigned short rC[kDecWaves][Cw * kRC];      // [channel][pixel] signs
-  __shared__ __attribute__((aligned(16))) unsigned short rP[kDecWaves][kChunk * Cw];   // [pixel][channel] signs
+  // [pixel][channel] signs; the row pitch is padded by 16 bytes so that the
+  // 2-byte sign stores of a wave's four lane groups (rows 8 apart) do not
+  // all fall on the same banks
+  constexpr int kRP = Cw + 8;
+  __shared__ __attribute__((aligned(16))) unsigned short rP[kDecWaves][kChunk * kRP];
   __shared__ __attribute__((aligned(16))) float dfr[2][kDecWaves * 16 * kChunk];      // [wave][feature][pixel]
   __shared__ float red[kDecWaves];
 
@@ -234,6 +238,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decoder(DecArgs a, const TT* __
     lds_barrier();
     if (ck > ck0) store_df(ck - 1, par ^ 1);
     // (2) Z^T tiles, signs, loss, db; signs to LDS in both layouts
+    const int lim = n - p0 < kChunk ? (int)(n - p0) : kChunk;   // valid pixels of the chunk
 #pragma unroll
     for (int cg = 0; cg < 2; ++cg) {
       // A row r16 of column group cg is pixel 8 (r16 / 4) + 4 cg + r16 % 4
@@ -249,13 +254,13 @@ __global__ __launch_bounds__(kDecThreads) void k_decoder(DecArgs a, const TT* __
         unsigned short sg[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const bool valid = p0 + pl + i < n;
+          const bool valid = pl + i < lim;
           const float d = z[i] - tv[i];
           const float s = !valid ? 0.f : (d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f));
           lsum += valid ? fabsf(d) : 0.f;
           db[nt] += s;
-          sg[i] = to_bf16(s);
-          rP[w][(pl + i) * Cw + 16 * nt + r16] = sg[i];
+          sg[i] = (unsigned short)(__float_as_uint(s) >> 16);   // -1, 0, 1: exact in BF16
+          rP[w][(pl + i) * kRP + 16 * nt + r16] = sg[i];
         }
         uint2 packed;
         packed.x = (uint32_t)sg[0] | ((uint32_t)sg[1] << 16);
@@ -281,7 +286,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decoder(DecArgs a, const TT* __
       dfa[cg] = (f32x4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
-        const bf16x8_t rb = as_bf16x8(*(const u16x8*)(&rP[w][(16 * cg + r16) * Cw + 32 * ks + 8 * q4]));
+        const bf16x8_t rb = as_bf16x8(*(const u16x8*)(&rP[w][(16 * cg + r16) * kRP + 32 * ks + 8 * q4]));
         dfa[cg] = mfma(wt_h[ks], rb, dfa[cg]);
         dfa[cg] = mfma(wt_l[ks], rb, dfa[cg]);
       }
