@@ -422,23 +422,25 @@ __device__ __forceinline__ unsigned short bf16_rne(float x) {
 }
 __device__ __forceinline__ float bf16_to_f(unsigned short h) { return __uint_as_float((uint32_t)h << 16); }
 
-// Transpose-reduction of 8 values over the whole wave: on
-// exit lane l holds the wave sum of value l >> 3.
-__device__ __forceinline__ float transpose_reduce8(const float v[8], int lane) {
-  float a[4];
+// Transpose-reduction of 6 values over the whole wave: on exit lane l holds
+// the wave sum of value red6_index(l).  Partners: l ^ 32 (permlane32 swap:
+// lanes below 32 keep values 0..2, the others 3..5), l ^ 16 (permlane16
+// swap: values 0 / 1 split by row parity, value 2 summed in every row), l ^ 8
+// (row_ror:8: bit 3 chooses between the two), then 7 - (l & 7), l ^ 2, l ^ 1.
+__device__ __forceinline__ int red6_index(int l) { return 3 * (l >> 5) + ((l & 8) ? 2 : (l >> 4) & 1); }
+__device__ __forceinline__ float transpose_reduce6(const float v[6], int lane) {
+  float a[3];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]), __float_as_uint(v[4 + i]), false, false);
+  for (int i = 0; i < 3; ++i) {
+    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]), __float_as_uint(v[3 + i]), false, false);
     a[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
   }
-  float b[2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a[i]), __float_as_uint(a[2 + i]), false, false);
-    b[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
-  }
+  auto r01 = __builtin_amdgcn_permlane16_swap(__float_as_uint(a[0]), __float_as_uint(a[1]), false, false);
+  const float b = __uint_as_float(r01[0]) + __uint_as_float(r01[1]);
+  auto r22 = __builtin_amdgcn_permlane16_swap(__float_as_uint(a[2]), __float_as_uint(a[2]), false, false);
+  const float b2 = __uint_as_float(r22[0]) + __uint_as_float(r22[1]);
   const bool h8 = (lane & 8) != 0;
-  float c = bsel(h8, b[0], b[1]) + dpp<0x128>(bsel(h8, b[1], b[0]));
+  float c = bsel(h8, b, b2) + dpp<0x128>(bsel(h8, b2, b));
   c = c + dpp<0x141>(c);
   c = c + dpp<0x4E>(c);
   return c + dpp<0xB1>(c);
@@ -668,7 +670,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
         float y[20];
         y_from_words<BF16>(yw, y);
         y[3] = gr.z;
-        float vv[8];
+        float vv[6];
         {
           const float rinv = __builtin_amdgcn_rcpf(1.f - e.alpha);
           const float Tp = Tc * rinv;
@@ -703,8 +705,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
           vv[3] = mxd * dy;
           vv[4] = myd * dy;
           vv[5] = dgeo * e.G;
-          vv[6] = 0.f;
-          vv[7] = 0.f;
           // hi = RNE(wc), lo = RNE(wc - hi): the hardware conversion
           const __bf16 wh = (__bf16)wc;
           wz[nb * kZRow + lane] = __builtin_bit_cast(unsigned short, wh);
@@ -713,8 +713,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
         const uint32_t bb = gr.bbox;
         const uint32_t bw = ((bb >> 8) & 255u) - (bb & 255u) + 1u;
         const uint32_t slot = sbase + (by - (uint32_t)by0) * bw + (bx - (uint32_t)bx0);
-        const float s8 = transpose_reduce8(vv, lane);
-        if ((lane & 7) == 0 && (lane >> 3) < 6) stage[nb * kRecLds + (lane >> 3)] = s8;
+        const float s6 = transpose_reduce6(vv, lane);
+        // one lane per value: 0, 8, 16, 32, 40, 48 (24 and 56 repeat 8 and 40)
+        if ((lane & 7) == 0 && (lane & 24) != 24) stage[nb * kRecLds + red6_index(lane)] = s6;
         if (lane == 0) sslot[nb] = slot;
         ++nb;
         if (nb == 8) flush();
