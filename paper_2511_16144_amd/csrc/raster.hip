@@ -260,7 +260,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))
       uint32_t j = hm ? (uint32_t)__builtin_ctzll(hm) : 0u;
       uint32_t aw[20];
       unsigned short yh = 0;   // BF16: this lane's channel slot of the entry's appearance
+      // the next entry's geometry: with BF16 appearance a scalar load issued
+      // one entry ahead (the appearance goes through vector loads, so the
+      // SGPRs are free for it); with FP32 appearance (20 scalar appearance
+      // words) broadcast from the lane that loaded it
+      GeomRec gn{};
       if (hm) {
+        if (BF16) gn = geom[__builtin_amdgcn_readlane(rid_l, j)];
         const uint32_t g0 = __builtin_amdgcn_readlane(rid_l, j) & npad_mask;
         if (BF16) {
           if (lane < 20) yh = app16[(size_t)g0 * 20 + lane];
@@ -270,12 +276,24 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))
       }
       while (hm) {
         hm &= hm - 1ull;
-        const uint32_t bb = __builtin_amdgcn_readlane(g_l.bbox, j);
+        GeomRec gr;
+        if (BF16) {
+          gr = gn;
+        } else {
+          gr.mx = bcast(g_l.mx, j);
+          gr.my = bcast(g_l.my, j);
+          gr.qa = bcast(g_l.qa, j);
+          gr.qb2 = bcast(g_l.qb2, j);
+          gr.qc = bcast(g_l.qc, j);
+          gr.o = bcast(g_l.o, j);
+          gr.z = bcast(g_l.z, j);
+          gr.bbox = __builtin_amdgcn_readlane(g_l.bbox, j);
+        }
+        const uint32_t bb = gr.bbox;
         n_eval += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(!done));
-        const float dx = (float)(px - 8 * (int)(bb & 255u)) - bcast(g_l.mx, j);
-        const float dy = (float)(py - 8 * (int)((bb >> 16) & 255u)) - bcast(g_l.my, j);
-        const Eval e = eval_entry(dx, dy, bcast(g_l.qa, j), bcast(g_l.qb2, j), bcast(g_l.qc, j),
-                                  bcast(g_l.o, j), st.cutoff2, st.alpha_max, st.alpha_min);
+        const float dx = (float)(px - 8 * (int)(bb & 255u)) - gr.mx;
+        const float dy = (float)(py - 8 * (int)((bb >> 16) & 255u)) - gr.my;
+        const Eval e = eval_entry(dx, dy, gr.qa, gr.qb2, gr.qc, gr.o, st.cutoff2, st.alpha_max, st.alpha_min);
         bool con = !done && e.pass;
         const float Tn = T * (1.f - e.alpha);
         const bool term = con && (Tn < st.T_eps);
@@ -286,7 +304,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))
           n_con += (uint32_t)__popcll(cmask);
           const float w = con ? e.alpha * T : 0.f;
           if (BF16) {
-            accz = __builtin_fmaf(w, bcast(g_l.z, j), accz);
+            accz = __builtin_fmaf(w, gr.z, accz);
             // w = hi + mid + lo exactly: each term keeps the top 8 significant
             // bits of what is left (truncation), so each is a BF16 value
             const float whi = __uint_as_float(__float_as_uint(w) & 0xffff0000u);
@@ -300,7 +318,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))
           } else {
             float y[20];
             y_from_words<BF16>(aw, y);
-            y[3] = bcast(g_l.z, j);
+            y[3] = gr.z;
 #pragma unroll
             for (int c = 0; c < 20; ++c) acc[c] = __builtin_fmaf(w, y[c], acc[c]);
           }
@@ -315,6 +333,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))
         }
         if (hm) {
           j = (uint32_t)__builtin_ctzll(hm);
+          if (BF16) gn = geom[__builtin_amdgcn_readlane(rid_l, j)];
           const uint32_t g0 = __builtin_amdgcn_readlane(rid_l, j) & npad_mask;
           if (BF16) {
             if (lane < 20) yh = app16[(size_t)g0 * 20 + lane];
