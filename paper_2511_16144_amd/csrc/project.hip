@@ -251,10 +251,10 @@ __device__ __forceinline__ double wave_sum_d(double x) {
 
 // grad2d layout per visible (view, Gaussian): [Sx, Sy, Sxx, Sxy, Syy,
 // opacity, r, g, b, z, f0..f15] (26 FP32), where S_* = sum over pixels of
-// dL/dm2 times dx, dy, dx^2, dx dy, dy^2 (m2 = Q_xx dx^2 + 2 Q_xy dx dy +
-// Q_yy dy^2, dx = pixel - mean): so dL/dQ_xx = Sxx, dL/dQ_xy (the symmetric
-// off-diagonal entry, counted twice in m2) = 2 Sxy, dL/dQ_yy = Syy, and
-// dL/dmean = -2 Q (Sx, Sy).
+// dL/dalpha * alpha times dx, dy, dx^2, dx dy, dy^2 (m2 = Q_xx dx^2 +
+// 2 Q_xy dx dy + Q_yy dy^2, dx = pixel - mean, dL/dm2 = -1/2 dL/dalpha alpha):
+// so dL/dQ_xx = -1/2 Sxx, dL/dQ_xy (the symmetric off-diagonal entry,
+// counted twice in m2) = -Sxy, dL/dQ_yy = -1/2 Syy, and dL/dmean = Q (Sx, Sy).
 __global__ void __launch_bounds__(256) k_project_bwd(
     Settings st, const ViewDesc* __restrict__ views, int n_views,
     const float* __restrict__ means, const float* __restrict__ log_scales,
@@ -318,7 +318,7 @@ __global__ void __launch_bounds__(256) k_project_bwd(
       // conic -> Sigma':  G_Sigma' = -Q Gq Q  (symmetric representation)
       const double inv = 1.0 / S.det;
       const double Qa = S.c * inv, Qb = -S.b * inv, Qc = S.a * inv;
-      const double ga_q = G[2], gb_q = G[3], gc_q = G[4];
+      const double ga_q = -0.5 * (double)G[2], gb_q = -0.5 * (double)G[3], gc_q = -0.5 * (double)G[4];
       // T1 = Gq Q
       const double t00 = ga_q * Qa + gb_q * Qb, t01 = ga_q * Qb + gb_q * Qc;
       const double t10 = gb_q * Qa + gc_q * Qb, t11 = gb_q * Qb + gc_q * Qc;
@@ -351,8 +351,8 @@ __global__ void __launch_bounds__(256) k_project_bwd(
         for (int j = 0; j < 3; ++j)
           gM[3 * i + j] += 2.0 * (GS[3 * i] * P.M[j] + GS[3 * i + 1] * P.M[3 + j] + GS[3 * i + 2] * P.M[6 + j]);
       // camera-space mean gradient: mean', Jacobian, depth channel
-      const double gmx = -2.0 * (Qa * (double)G[0] + Qb * (double)G[1]);
-      const double gmy = -2.0 * (Qb * (double)G[0] + Qc * (double)G[1]);
+      const double gmx = Qa * (double)G[0] + Qb * (double)G[1];
+      const double gmy = Qb * (double)G[0] + Qc * (double)G[1];
       double gx[3];
       gx[0] = gmx * V.fx * iz;
       gx[1] = gmy * V.fy * iz;

@@ -426,10 +426,9 @@ __device__ __forceinline__ int wave_max_i32(int x) {
 
 constexpr int kZRow = 72;                  // bf16 per LDS row (64 pixels + pad; 144 B, 16-B aligned)
 // Staging of up to 8 partial records before they are written out: 36 floats
-// per record (the 32 of a slot + pad: 16-B aligned rows whose banks differ),
-// then the 8 slot indices.
+// per record (the 32 of a slot + pad: 16-B aligned rows whose banks differ).
 constexpr int kRecLds = 36;
-constexpr int kStageBytes = (8 * kRecLds + 8) * 4;
+constexpr int kStageBytes = 8 * kRecLds * 4;
 // LDS bytes of one backward wave: upstream rows, blend-weight rows, staging
 __host__ __device__ constexpr int bwd_wave_lds_bytes(int up_mode) {
   return (bwd_upstream_rows(up_mode) + 16) * kZRow * 2 + kStageBytes;
@@ -492,7 +491,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
   unsigned short* lz = lds_z + (threadIdx.x >> 6) * (bwd_wave_lds_bytes(UPM) / 2);
   unsigned short* wz = lz + kGRows * kZRow;
   float* stage = (float*)(wz + 16 * kZRow);         // 8 records of kRecLds floats
-  uint32_t* sslot = (uint32_t*)(stage + 8 * kRecLds);   // their slot indices
   const int grp = lane >> 4, col = lane & 15;
   if (cnt->overflow) return;
   // this wave's work, added to the 64-bit counters once at the end (a wave's
@@ -600,6 +598,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
       }
     }
     int nb = 0;
+    uint32_t slotv = 0;   // lane e: the slot of the batch's entry e
     // Write the batch's nb partial records: the colour partials join the
     // geometric ones in the staged records, then every lane stores one
     // 16-byte quarter of a record (one full 128-byte slot per 8 lanes) and
@@ -645,7 +644,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
       }
       const int er4 = lane >> 3, q4 = lane & 7;
       const float4 v4 = *(const float4*)(stage + er4 * kRecLds + 4 * q4);
-      const uint32_t sl = sslot[er4];
+      const uint32_t sl = (uint32_t)__builtin_amdgcn_ds_bpermute(er4 * 4, (int)slotv);
       if (er4 < nb) {
         *(float4*)(partials + (size_t)sl * kSlotFloats + 4 * q4) = v4;
         if (q4 == 0) mask[sl] = 1;
@@ -708,15 +707,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
 #pragma unroll
             for (int c = 0; c < 20; ++c) gy = __builtin_fmaf(g[c], y[c], gy);
           }
-          const float dal = Tp * gy - (sB + gTT) * rinv;
+          const float dal = Tp * gy - (UPM == UP_EXPLICIT ? sB + gTT : sB) * rinv;   // gT = 0 otherwise
           const float wc = con ? w : 0.f;
           sB = con ? __builtin_fmaf(w, gy, sB) : sB;
           Tc = con ? Tp : Tc;
           const float dgeo = (con && !(e.araw > st.alpha_max)) ? dal : 0.f;
-          // dL/dm2 per pixel; the slot keeps its moments over the pixel
-          // offsets (the conic's entries are per Gaussian, so they are
-          // applied once to the summed moments in the projection backward)
-          const float dm2 = dgeo * (-0.5f * e.alpha);
+          // dL/dm2 per pixel is -1/2 dgeo alpha; the slot keeps the moments
+          // of dgeo alpha over the pixel offsets (the factor -1/2 and the
+          // conic's entries are per Gaussian, so they are applied once to
+          // the summed moments in the projection backward)
+          const float dm2 = dgeo * e.alpha;
           const float mxd = dm2 * dx, myd = dm2 * dy;
           vv[0] = mxd;
           vv[1] = myd;
@@ -735,7 +735,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
         const float s6 = transpose_reduce6(vv, lane);
         // one lane per value: 0, 8, 16, 32, 40, 48 (24 and 56 repeat 8 and 40)
         if ((lane & 7) == 0 && (lane & 24) != 24) stage[nb * kRecLds + red6_index(lane)] = s6;
-        if (lane == 0) sslot[nb] = slot;
+        slotv = lane == nb ? slot : slotv;   // lane nb: this entry's slot
         ++nb;
         if (nb == 8) flush();
       }
