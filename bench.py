@@ -39,15 +39,16 @@ PEAK_HBM_GBS = 8000.0
 #                 alpha 2, the two cut tests 2                      = 16
 #   forward contribution : T' 2, stop test 1, weight 1, 20 FMAs 40   = 44
 #   backward contribution: 1 - alpha, 1/(1-alpha), T_prev, weight 4,
-#                 g.y 40, dL/dalpha 5, running sum 2, dL/dm2 2, its
-#                 five moments over the pixel offsets 5, opacity 1,
+#                 g.y 40, dL/dalpha 4, running sum 2, dL/dalpha alpha 1,
+#                 its five moments over the pixel offsets 5, opacity 1,
 #                 20 colour partials 20, sum of the 26 partials over
-#                 pixels 26                                         = 105
-#   (the conic's entries multiply the summed moments once per Gaussian, in
-#   the projection backward, not per pixel)
+#                 pixels 26                                         = 103
+#   (the factor -1/2 of dL/dm2 and the conic's entries multiply the summed
+#   moments once per Gaussian, in the projection backward, not per pixel;
+#   dL/dalpha has no transmittance-upstream term in the fused L1 step)
 FLOPS_EVAL = 16
 FLOPS_FWD_CONTRIB = 44
-FLOPS_BWD_CONTRIB = 105
+FLOPS_BWD_CONTRIB = 103
 
 
 def measured_traffic(kernel, settings, workload):
