@@ -57,7 +57,10 @@ __device__ __forceinline__ Eval eval_entry(float dx, float dy, float qa, float q
   e.m2 = __builtin_fmaf(t5, dx, t4);
   e.G = __builtin_amdgcn_exp2f(e.m2 * -0.72134752044448170f);   // exp(-m2/2)
   e.araw = o * e.G;
-  e.alpha = fminf(e.araw, alpha_max);
+  // min(araw, alpha_max) as a single v_min_f32 (equal to fminf here: araw
+  // is a product, never a signalling NaN); fminf would first canonicalise
+  // the setting with an instruction of its own at every entry
+  asm("v_min_f32 %0, %1, %2" : "=v"(e.alpha) : "s"(alpha_max), "v"(e.araw));
   e.pass = (e.m2 <= cutoff2) && (e.alpha >= alpha_min);
   return e;
 }
@@ -241,8 +244,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))
       nb = 0;
     };
     int32_t last = -1, ncon = 0;
-    bool done = !inside;
-    bool finished = __builtin_amdgcn_ballot_w64(!done) == 0ull;
+    // the lanes still compositing, as a wave mask in SGPRs: per-lane tests
+    // enter it through ballots of single comparisons and leave it through
+    // inverse ballots, so the bookkeeping costs scalar instructions only
+    uint64_t live = __builtin_amdgcn_ballot_w64(inside);
+    bool finished = live == 0ull;
     for (uint32_t base = r.x; base < r.y && !finished; base += 64) {
       // lane l loads entry base + l and decides whether the wave visits it
       const uint32_t kl = base + (uint32_t)lane;
@@ -290,17 +296,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))
           gr.bbox = __builtin_amdgcn_readlane(g_l.bbox, j);
         }
         const uint32_t bb = gr.bbox;
-        n_eval += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(!done));
+        n_eval += (uint32_t)__popcll(live);
         const float dx = (float)(px - 8 * (int)(bb & 255u)) - gr.mx;
         const float dy = (float)(py - 8 * (int)((bb >> 16) & 255u)) - gr.my;
         const Eval e = eval_entry(dx, dy, gr.qa, gr.qb2, gr.qc, gr.o, st.cutoff2, st.alpha_max, st.alpha_min);
-        bool con = !done && e.pass;
         const float Tn = T * (1.f - e.alpha);
-        const bool term = con && (Tn < st.T_eps);
-        done = done || term;
-        con = con && !term;
-        const uint64_t cmask = __builtin_amdgcn_ballot_w64(con);
+        // e.pass, as a mask
+        const uint64_t pm = live & __builtin_amdgcn_ballot_w64(e.m2 <= st.cutoff2) &
+                            __builtin_amdgcn_ballot_w64(e.alpha >= st.alpha_min);
+        const uint64_t tm = pm & __builtin_amdgcn_ballot_w64(Tn < st.T_eps);   // terminates here
+        live &= ~tm;
+        const uint64_t cmask = pm & ~tm;
         if (cmask != 0ull) {
+          const bool con = __builtin_amdgcn_inverse_ballot_w64(cmask);
           n_con += (uint32_t)__popcll(cmask);
           const float w = con ? e.alpha * T : 0.f;
           if (BF16) {
@@ -327,7 +335,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))
           ncon += con ? 1 : 0;
           if (BF16 && ++nb == 8) flush();
         }
-        if (__builtin_amdgcn_ballot_w64(!done) == 0ull) {
+        if (live == 0ull) {
           finished = true;
           break;
         }
@@ -676,14 +684,18 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
         uint32_t yw[BF16 ? 10 : 20];
         load_app_words<BF16>(app, rid & npad_mask, yw);
         const uint32_t sbase = slot_base[rid];
-        n_eval += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(k <= last));
+        const uint64_t lm = __builtin_amdgcn_ballot_w64(k <= last);   // lanes this entry can reach
+        n_eval += (uint32_t)__popcll(lm);
         const int bx0 = (int)(gr.bbox & 255u), by0 = (int)((gr.bbox >> 16) & 255u);
         const float dx = (float)(px - 8 * bx0) - gr.mx;
         const float dy = (float)(py - 8 * by0) - gr.my;
         const Eval e = eval_entry(dx, dy, gr.qa, gr.qb2, gr.qc, gr.o, st.cutoff2, st.alpha_max, st.alpha_min);
-        const bool con = (k <= last) && e.pass;
-        const uint64_t cmask = __builtin_amdgcn_ballot_w64(con);
+        // (k <= last) && e.pass, as a mask of single-comparison ballots and
+        // back as a lane predicate (no VALU spent on the conversion)
+        const uint64_t cmask = lm & __builtin_amdgcn_ballot_w64(e.m2 <= st.cutoff2) &
+                               __builtin_amdgcn_ballot_w64(e.alpha >= st.alpha_min);
         if (cmask == 0ull) continue;
+        const bool con = __builtin_amdgcn_inverse_ballot_w64(cmask);
         n_con += (uint32_t)__popcll(cmask);
         float y[20];
         y_from_words<BF16>(yw, y);
