@@ -130,11 +130,29 @@ constexpr int kEmitThreads = 256;
 constexpr int kEmitPerThread = 4;
 constexpr int kEmitTile = kEmitThreads * kEmitPerThread;   // 1024 pairs per block
 
-__device__ __forceinline__ int64_t upper_bound_u32(const uint32_t* a, int64_t n, uint32_t x) {
+// The first index i with a[i] > x (n if none) of a non-decreasing array,
+// found by one wave: each step the 64 lanes probe 64 evenly
+// spaced positions of the remaining range [lo, hi) and a ballot keeps the
+// part holding the first element > x (hi stays a candidate: a[hi] > x or
+// hi == n): about log64(n) dependent loads, where a one-thread binary
+// search takes log2(n).
+__device__ __forceinline__ int64_t wave_upper_bound_u32(const uint32_t* a, int64_t n, uint32_t x) {
+  const int lane = threadIdx.x & 63;
   int64_t lo = 0, hi = n;
   while (lo < hi) {
-    int64_t mid = (lo + hi) >> 1;
-    if (a[mid] <= x) lo = mid + 1; else hi = mid;
+    const int64_t step = (hi - lo + 63) / 64;
+    const int64_t i = lo + (int64_t)lane * step;
+    const bool valid = i < hi;
+    const bool gt = valid && a[i] > x;
+    const uint64_t m = __builtin_amdgcn_ballot_w64(gt);
+    if (m != 0ull) {
+      const int f = __builtin_ctzll(m);
+      hi = lo + (int64_t)f * step;
+      if (f > 0) lo += (int64_t)(f - 1) * step + 1;
+    } else {
+      const int last = 63 - __builtin_clzll(__builtin_amdgcn_ballot_w64(valid));
+      lo += (int64_t)last * step + 1;
+    }
   }
   return lo;
 }
@@ -153,9 +171,11 @@ __global__ void __launch_bounds__(kEmitThreads) k_emit(
   const int64_t p0 = (int64_t)blockIdx.x * kEmitTile;
   if (p0 >= P) return;
   const int64_t p1 = (p0 + kEmitTile < P ? p0 + kEmitTile : P) - 1;   // last pair of the block
-  if (threadIdx.x < 2) {
-    const uint32_t x = (uint32_t)(threadIdx.x == 0 ? p0 : p1);
-    s_j[threadIdx.x] = upper_bound_u32(off_t, M, x) - 1;
+  // the entries owning the block's first and last pair: wave 0 and wave 1
+  if (threadIdx.x < 128) {
+    const int w = threadIdx.x >> 6;
+    const int64_t j = wave_upper_bound_u32(off_t, M, (uint32_t)(w == 0 ? p0 : p1)) - 1;
+    if ((threadIdx.x & 63) == 0) s_j[w] = j;
   }
   __syncthreads();
   const int64_t j0 = s_j[0], j1 = s_j[1];
