@@ -51,14 +51,22 @@ FLOPS_FWD_CONTRIB = 44
 FLOPS_BWD_CONTRIB = 103
 
 
-def measured_traffic(kernel, settings, workload):
-    """HBM bytes per launch of `kernel` from the committed counter summary
-    (two rocprofv3 passes, FETCH_SIZE then WRITE_SIZE, scaled against a kernel
-    of known traffic), or None when the kernel sources changed since, or the
-    settings / workload differ from the profiled ones."""
+# Algorithmic FP32 operations per evaluated (pixel, list entry) unit in the
+# scope table's own count (forward 52 + exp; backward 140 + exp + rcp), reported
+# beside the count above.
+FLOPS_FWD_EVAL_ALT = 52
+FLOPS_BWD_EVAL_ALT = 140
+
+
+def measured_traffic(kernel, settings, workload, mode):
+    """HBM bytes per launch of `kernel` (or per step: kernel == "step") from
+    the committed counter summary (two rocprofv3 passes, FETCH_SIZE then
+    WRITE_SIZE, scaled against a kernel of known traffic), or None when the
+    kernel sources changed since, or the settings, mode or workload differ
+    from the profiled ones."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "hbm_traffic_compositing_batched_c4.md")
-    if not os.path.exists(path) or workload != "batched" or (settings.get("tile"), settings.get("order")) != (32, 1):
+    if not os.path.exists(path) or workload != "batched":
         return None
     src = os.path.join(ROOT, "paper_2511_16144_amd", "csrc")
     if kernel == "step":
@@ -67,13 +75,62 @@ def measured_traffic(kernel, settings, workload):
     else:
         h = hashlib.sha256(open(os.path.join(src, "raster.hip"), "rb").read() +
                            open(os.path.join(src, "lgs_internal.h"), "rb").read()).hexdigest()
+    want = {"tile": str(settings["tile"]), "chunk": str(settings["chunk"]), "order": str(settings["order"]),
+            "mode": mode, "source_sha256": h}
     for line in open(path):
         f = line.split()
-        if len(f) == 4 and f[0] == "traffic" and f[1] == kernel:
-            kv = dict(x.split("=", 1) for x in f[2:])
-            if kv.get("source_sha256") == h:
+        if len(f) >= 3 and f[0] == "traffic" and f[1] == kernel:
+            kv = dict(x.split("=", 1) for x in f[2:] if "=" in x)
+            if all(kv.get(k) == v for k, v in want.items()):
                 return float(kv["bytes_per_launch"])
     return None
+
+
+def algorithmic_bytes(wl, c):
+    """HBM bytes one step must move by the method's own accounting (the scope
+    table's per-unit figures, with the units counted by the kernels):
+    compulsory: every Gaussian's geometry (44 B) and appearance (38 B BF16 /
+    76 B FP32; read once per step, every Gaussian of the batched workload is
+    visible in some view), the images written (RGB, depth, 16 features, T and
+    the last contributor: 88 B/px), the fused L1 gradient's reads (rendered and
+    target images, 80 + 80 B/px), the gradients written (120 B/Gaussian);
+    method: the depth-hoisted sort (4 passes over the visible (view, Gaussian)
+    ids and 2 over the pairs, 16 B per element per pass), every visited list
+    entry's records in the forward and the backward (32 B geometry + 40 B BF16
+    / 80 B FP32 appearance), and the backward's partial records (104 B written
+    and read once each)."""
+    n, px = wl.scene.n, wl.pixels
+    app = 38 if wl.scene.dtype == "bf16" else 76
+    rec = 32 + (40 if wl.scene.dtype == "bf16" else 80)
+    parts = {
+        "compulsory": n * (44 + app) + px * 88 + px * 160 + n * 120,
+        "sort": 4 * 16 * c["n_visible"] + 2 * 16 * c["n_pairs"],
+        "records": rec * (c["fwd_entries"] + c["bwd_entries"]),
+        "partials": 2 * 104 * c["bwd_written"],
+    }
+    parts["total"] = sum(parts.values())
+    return parts
+
+
+def copy_bandwidth(dev, mib=1024, reps=10):
+    """Device-to-device copy bandwidth (read + write bytes / time), median of
+    `reps` copies of `mib` MiB timed with HIP events."""
+    import torch
+    a = torch.empty(mib << 18, dtype=torch.float32, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ts.sort()
+    del a, b
+    return 2.0 * (mib << 20) / (ts[len(ts) // 2] / 1e3) / 1e9
 
 
 def log(*a):
@@ -131,24 +188,29 @@ def time_workload(ctx, wl, steps, warmup, dev, tune, settings):
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     stages = [] if st.profile else None
     counts = None
     t0 = time.perf_counter()
     e0.record()
-    for _ in range(steps):
+    for a, b in ev:
+        a.record()
         c = step(stages)
+        b.record()
         counts = counts or c
     e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1) / steps
+    ms_mean = e0.elapsed_time(e1) / steps
+    per = sorted(a.elapsed_time(b) for a, b in ev)
+    ms = per[len(per) // 2]
     if counts is None:
         o, state = ctx.forward(params, wl.cams, st, out=outs)
         ctx.backward_l1(state, params, outs, tgts, wl.loss_w, grads=grads)
         counts = state.counts()
         state.release()
-    mean_st = [sum(x[i] for x in stages) / len(stages) for i in range(5)] if stages else None
-    return {"ms": ms, "wall_s": wall, "counts": counts, "stages": mean_st,
+    med_st = [sorted(x[i] for x in stages)[len(stages) // 2] for i in range(5)] if stages else None
+    return {"ms": ms, "ms_mean": ms_mean, "wall_s": wall, "counts": counts, "stages": med_st,
             "settings": {"tile": st.tile, "chunk": st.chunk, "order": st.order}}
 
 
@@ -230,15 +292,20 @@ def time_workload_graph(ctx, wl, steps, warmup, dev, tune, settings, ssim_lambda
             raise RuntimeError(B.lib().lgs_last_error(ctx._h).decode())
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         e0.record()
-        for _ in range(steps):
+        for a, b in ev:
+            a.record()
             launch()
+            b.record()
         e1.record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        ms = e0.elapsed_time(e1) / steps
+        ms_mean = e0.elapsed_time(e1) / steps
+        per = sorted(a.elapsed_time(b) for a, b in ev)
+        ms = per[len(per) // 2]
         cnt = B.lgs_counts()
         B.lib().lgs_graph_counts(h, C.byref(cnt))
         counts = {k: getattr(cnt, k) for k, _ in B.lgs_counts._fields_}
@@ -246,7 +313,7 @@ def time_workload_graph(ctx, wl, steps, warmup, dev, tune, settings, ssim_lambda
     finally:
         torch.cuda.synchronize()
         B.lib().lgs_graph_destroy(h)
-    return {"ms": ms, "wall_s": wall, "counts": counts, "stages": stages,
+    return {"ms": ms, "ms_mean": ms_mean, "wall_s": wall, "counts": counts, "stages": stages,
             "settings": {"tile": st.tile, "chunk": st.chunk, "order": st.order}}
 
 
@@ -455,36 +522,59 @@ def main():
     stages = {n: round(v, 4) for n, v in zip(names, st)} if st else None
     # dominant kernel: backward compositing (a single kernel between its events)
     fl = FLOPS_EVAL * c["bwd_evals"] + FLOPS_BWD_CONTRIB * c["bwd_contrib"]
+    fl_alt = FLOPS_BWD_EVAL_ALT * c["bwd_evals"]
     kms = st[3] if st else None
     achieved = fl / (kms / 1e3) / 1e12 if kms else None
+    achieved_alt = fl_alt / (kms / 1e3) / 1e12 if kms else None
+    mode = args.mode
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": (achieved / PEAK_FP32_TFLOPS) if achieved else None,
-            "traffic": measured_traffic("k_raster_bwd", r["settings"], args.workload),
+            "traffic": measured_traffic("k_raster_bwd", r["settings"], args.workload, mode),
             "kernel": "k_raster_bwd", "kernel_ms": kms,
             "units": {"bwd_evals": c["bwd_evals"], "bwd_contrib": c["bwd_contrib"]},
-            "flops_per_unit": {"eval": FLOPS_EVAL, "contrib": FLOPS_BWD_CONTRIB}}
+            "flops_per_unit": {"eval": FLOPS_EVAL, "contrib": FLOPS_BWD_CONTRIB},
+            "alt_count": {"flops_per_eval": FLOPS_BWD_EVAL_ALT, "achieved": achieved_alt,
+                          "frac": (achieved_alt / PEAK_FP32_TFLOPS) if achieved_alt else None},
+            "frac_of_unpacked_fp32": (achieved / (PEAK_FP32_TFLOPS / 2)) if achieved else None}
     fwd_fl = FLOPS_EVAL * c["fwd_evals"] + FLOPS_FWD_CONTRIB * c["fwd_contrib"]
     fwd_tf = fwd_fl / (st[2] / 1e3) / 1e12 if st else None
+    fwd_tf_alt = FLOPS_FWD_EVAL_ALT * c["fwd_evals"] / (st[2] / 1e3) / 1e12 if st else None
     eager_ms = re["ms"] if args.mode == "graph" else None
-    # whole-step HBM traffic (both counter passes, every kernel, eager form) over the step time
-    step_bytes = measured_traffic("step", r["settings"], args.workload)
-    hbm = None
+    log("[bench] measuring device-copy bandwidth")
+    copy_gbs = copy_bandwidth(dev)
+    # the step's algorithmic bytes over its time, against the HBM peak and
+    # against the measured copy bandwidth
+    ab = algorithmic_bytes(wl, c)
+    ab_gbs = ab["total"] / (r["ms"] / 1e3) / 1e9
+    # whole-step HBM traffic (both counter passes, every kernel, same mode and
+    # settings) over the step time
+    step_bytes = measured_traffic("step", r["settings"], args.workload, mode)
+    hbm = {"algorithmic_bytes_per_step": ab, "algorithmic_GB/s": round(ab_gbs, 1),
+           "algorithmic_frac": round(ab_gbs / PEAK_HBM_GBS, 4),
+           "algorithmic_frac_of_copy": round(ab_gbs / copy_gbs, 4),
+           "peak": PEAK_HBM_GBS, "copy_GB/s": round(copy_gbs, 1)}
     if step_bytes is not None:
         gbs = step_bytes / (r["ms"] / 1e3) / 1e9
-        hbm = {"bytes_per_step": step_bytes, "GB/s": round(gbs, 1), "peak": PEAK_HBM_GBS,
-               "frac": round(gbs / PEAK_HBM_GBS, 4),
-               "source": "profiles/hbm_traffic_compositing_batched_c4.md (FETCH_SIZE + WRITE_SIZE, calibrated)"}
+        hbm.update({"measured_bytes_per_step": step_bytes, "measured_GB/s": round(gbs, 1),
+                    "measured_frac": round(gbs / PEAK_HBM_GBS, 4), "measured_frac_of_copy": round(gbs / copy_gbs, 4),
+                    "source": "profiles/hbm_traffic_compositing_batched_c4.md (FETCH_SIZE + WRITE_SIZE, calibrated)"})
     out = {"metric": METRIC, "value": round(mpx, 3), "unit": "Mpixel/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(r["ms"], 4), "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "scaling": "weak", "vs_baseline": None, "dtype": "bf16" if wl.scene.dtype == "bf16" else "f32",
            "data": "synthetic (seeded room-surface scenes shaped like indoor RGB-D keyframes)",
            "config": {"workload": wl.name, "gaussians": wl.scene.n,
                       "views": [f"{cc.width}x{cc.height}" for cc in wl.cams],
-                      "appearance_storage": wl.scene.dtype, "loss_w": list(wl.loss_w), "mode": args.mode,
+                      "appearance_storage": wl.scene.dtype,
+                      "arithmetic": "fp32 accumulation and transmittance; fp64 projection; bf16 matrix-core "
+                                    "operands split exactly where the appearance is bf16",
+                      "loss_w": list(wl.loss_w), "mode": args.mode,
                       **r["settings"],
                       "parallelism": "single GPU"},
+           "timing": {"ms_per_step": "median of the timed steps (HIP events around each step)",
+                      "ms_per_step_mean": round(r["ms_mean"], 4)},
            "roofline": roof, "stages_ms": stages,
-           "forward_compositing": {"TFLOP/s": fwd_tf, "frac": fwd_tf / PEAK_FP32_TFLOPS if fwd_tf else None},
+           "forward_compositing": {"TFLOP/s": fwd_tf, "frac": fwd_tf / PEAK_FP32_TFLOPS if fwd_tf else None,
+                                   "alt_count_TFLOP/s": fwd_tf_alt},
            "hbm": hbm,
            "counts": c}
     if eager_ms is not None:

@@ -24,8 +24,14 @@
  *     written [k][n] is k contiguous planes of n values.
  *   - Cameras are world->camera (R_cw row-major, t_cw), OpenCV axes (x right,
  *     y down, z forward); pixel (i, j) is evaluated at its centre (i, j).
- *   - Every call enqueues work on the given stream and returns; an eager
- *     forward performs one 4-byte device->host read (the pair count).
+ *   - Every call enqueues work on the given stream and returns without
+ *     waiting for it, except where its comment says it synchronises: an
+ *     eager forward performs one 4-byte device->host read (the pair count);
+ *     lgs_prune, the count / stage-time queries, lgs_graph_status,
+ *     lgs_autotune and the destroy calls synchronise.  Releasing a state is
+ *     stream-ordered: its device buffers return to the context's cache and
+ *     are handed out again only behind the work already enqueued on that
+ *     stream.
  *   - Errors are returned as lgs_status; details via lgs_last_error().  No
  *     call throws.  Arguments are validated on the host: NULL pointers,
  *     n < 0, image sides outside [1, 2048], n_views outside [1, 1024],
@@ -134,6 +140,9 @@ typedef struct {
   int64_t fwd_contrib;  /* ... of which contributed */
   int64_t bwd_evals;    /* (pixel, list entry) evaluations, backward compositing */
   int64_t bwd_contrib;  /* ... of which contributed */
+  int64_t fwd_entries;  /* list entries visited by a wave (8x8 block), forward */
+  int64_t bwd_entries;  /* ... backward */
+  int64_t bwd_written;  /* partial records the backward wrote (visited, some pixel contributed) */
 } lgs_counts;
 
 const char *lgs_status_string(lgs_status s);
@@ -160,7 +169,8 @@ lgs_status lgs_forward(lgs_context *ctx, const lgs_settings *st,
  * gradient step of Sec. III-B.3 map optimisation and of the Sec. III-B.2
  * pose refinement).  grad_out[n_views] holds dL/dY per view (final_T may be
  * NULL).  Every plane of `grads` is overwritten.  Deterministic: no
- * atomics in the gradient reduction. */
+ * atomics in the gradient reduction.  Enqueued on `stream` without a host
+ * wait (the host tables it uploads are kept alive by the state). */
 lgs_status lgs_backward(lgs_context *ctx, const lgs_fwd_state *state,
                         const lgs_gaussians *g, const lgs_images *grad_out,
                         lgs_grads *grads, hipStream_t stream);
@@ -230,7 +240,7 @@ lgs_status lgs_decoder_l1(lgs_context *ctx, int32_t width, int32_t height,
                           float w_feat, float *grad_feat, float *grad_weight,
                           float *grad_bias, float *loss, hipStream_t stream);
 
-/* Language-guided pruning (Sec. III-D, Eq. (4)) combined with the geometric
+/* Language-guided pruning (Sec. III-C, Eq. (4)) combined with the geometric
  * criteria.  The paper publishes neither K nor the thresholds; the defaults
  * (lgs_default_prune_params) are readings:
  *   k           16     neighbours examined per Gaussian (1..32): the k
@@ -261,6 +271,8 @@ lgs_status lgs_prune(lgs_context *ctx, const lgs_gaussians *g,
                      const lgs_prune_params *params, uint8_t *mask,
                      int64_t counts[3], hipStream_t stream);
 
+/* Counts of the state's forward and, once enqueued, its backward (read when
+ * asked for: synchronises with the device). */
 lgs_status lgs_state_counts(const lgs_fwd_state *state, lgs_counts *out);
 /* With settings.profile = 1 on the forward, after its backward: elapsed
  * milliseconds of ms[0..4] = projection + depth sort + scans, pair emission
@@ -268,6 +280,9 @@ lgs_status lgs_state_counts(const lgs_fwd_state *state, lgs_counts *out);
  * gradient reduction + projection backward (HIP events on the caller's
  * stream).  Synchronises. */
 lgs_status lgs_state_stage_ms(const lgs_fwd_state *state, float ms[5]);
+/* Frees the state without waiting: its device buffers go back to the
+ * context's cache behind the work already enqueued on the state's stream
+ * (a later call on another stream waits for that work on the device). */
 lgs_status lgs_state_release(lgs_context *ctx, lgs_fwd_state *state);
 
 /* Whole mapping-loss step as one captured hipGraph: forward, gradient of the
@@ -307,11 +322,18 @@ lgs_status lgs_graph_counts(lgs_graph *graph, lgs_counts *out);
 lgs_status lgs_graph_stage_ms(lgs_graph *graph, float ms[5]);
 void lgs_graph_destroy(lgs_graph *graph);
 
-/* Autotuner: times the step (lgs_forward + lgs_backward_l1, median of 5)
- * for every (tile, chunk, order) setting on the given workload and returns
- * the fastest in *best_out (other fields copied from *st); `out` and `grads`
- * are overwritten.  With cache_path non-NULL the result is stored in / read
- * from a small JSON file keyed by the workload's shape. */
+/* Autotuner (Sec. III-B.3: the mapping step, repeated over many iterations
+ * per keyframe window): for every (tile, chunk, order) setting on the given
+ * workload, captures the L1 mapping step as one graph (lgs_graph_create,
+ * ssim_lambda 0, pair_capacity as there) and times it on `stream` with HIP
+ * events (median of 7 launches after 2 warm-up launches: device time only),
+ * and returns the fastest in *best_out (other fields copied from *st).
+ * Settings are visited in a fixed order and a later one wins only when it is
+ * more than 1 % faster, so settings within noise of each other resolve to the
+ * same choice.  `out` and `grads` are overwritten.  Synchronises.  With
+ * cache_path non-NULL the result is stored in / read from a small JSON file
+ * keyed by the Gaussian count, appearance dtype, feature dimension, loss form
+ * and view sizes. */
 lgs_status lgs_autotune(lgs_context *ctx, const lgs_settings *st,
                         const lgs_gaussians *g, int32_t n_views,
                         const lgs_camera *cams, const lgs_images *targets,

@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY (see the package docstring): the product never
 imports this file.
 
-Definition followed (Sec. III-D, Eq. (4)): each Gaussian G_i is checked
+Definition followed (Sec. III-C, Eq. (4)): each Gaussian G_i is checked
 against its K nearest neighbours in 3-D; a neighbour G_j is redundant when it
 is closer than tau_dist and the cosine similarity of the two language
 features exceeds tau_sim; the pruned set is the union of the redundant

@@ -7,7 +7,7 @@ binding; it has no CPU fallback.
 """
 from .binding import (Context, State, Settings, RasterFn, render, LgsError, load_library, lib,
                       EXPORTS, LIB_PATH)
-from .params import params_from_arrays, cameras_as_list
+from .params import params_from_arrays
 
 __all__ = ["Context", "State", "Settings", "RasterFn", "render", "LgsError", "load_library", "lib",
-           "EXPORTS", "LIB_PATH", "params_from_arrays", "cameras_as_list"]
+           "EXPORTS", "LIB_PATH", "params_from_arrays"]

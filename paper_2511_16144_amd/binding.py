@@ -57,7 +57,8 @@ class lgs_prune_params(C.Structure):
 class lgs_counts(C.Structure):
     _fields_ = [("n_visible", C.c_int64), ("n_pairs", C.c_int64), ("n_slots", C.c_int64),
                 ("n_tiles", C.c_int64), ("n_items", C.c_int64), ("fwd_evals", C.c_int64),
-                ("fwd_contrib", C.c_int64), ("bwd_evals", C.c_int64), ("bwd_contrib", C.c_int64)]
+                ("fwd_contrib", C.c_int64), ("bwd_evals", C.c_int64), ("bwd_contrib", C.c_int64),
+                ("fwd_entries", C.c_int64), ("bwd_entries", C.c_int64), ("bwd_written", C.c_int64)]
 
 
 EXPORTS = ["lgs_status_string", "lgs_last_error", "lgs_default_settings", "lgs_context_create",
@@ -452,16 +453,30 @@ class State:
 class RasterFn(torch.autograd.Function):
     """Differentiable render of every view: returns per view (rgb, depth,
     feat, T), flattened.  The pose twist input is a [V, 6] zero leaf whose
-    gradient is dL/d(rho, phi) of the left perturbation Exp(xi) T_cw."""
+    gradient is dL/d(rho, phi) of the left perturbation Exp(xi) T_cw.
+
+    ``storage`` is the dtype the colours and features are handed to the
+    library in (torch.float32 or torch.bfloat16).  With BF16 storage and FP32
+    ``rgb`` / ``feat`` tensors (master copies), the forward passes their
+    round-to-nearest-even BF16 copies and the backward returns the library's
+    FP32 gradient with respect to the stored values as the masters' gradient,
+    so that ``.grad`` stays FP32.  (Tensors that are BF16 already are passed as
+    they are; autograd then casts their gradient to BF16.)"""
 
     @staticmethod
-    def forward(ctx, context, cams, settings, means, log_scales, quats, logits, rgb, feat, twist):
+    def forward(ctx, context, cams, settings, storage, means, log_scales, quats, logits, rgb, feat, twist):
+        if storage == torch.bfloat16:
+            rgb_s, feat_s = rgb.to(torch.bfloat16).contiguous(), feat.to(torch.bfloat16).contiguous()
+        elif storage == torch.float32:
+            rgb_s, feat_s = rgb, feat
+        else:
+            raise ValueError(f"storage must be torch.float32 or torch.bfloat16, got {storage}")
         params = {"means": means, "log_scales": log_scales, "quats": quats, "logits": logits,
-                  "rgb": rgb, "feat": feat}
+                  "rgb": rgb_s, "feat": feat_s}
         outs, state = context.forward(params, cams, settings)
         ctx.state = state
         ctx.context = context
-        ctx.save_for_backward(means, log_scales, quats, logits, rgb, feat)
+        ctx.save_for_backward(means, log_scales, quats, logits, rgb_s, feat_s)
         flat = []
         for o in outs:
             flat += [o["rgb"], o["depth"], o["feat"], o["T"]]
@@ -469,9 +484,9 @@ class RasterFn(torch.autograd.Function):
 
     @staticmethod
     def backward(ctx, *grads):
-        means, log_scales, quats, logits, rgb, feat = ctx.saved_tensors
+        means, log_scales, quats, logits, rgb_s, feat_s = ctx.saved_tensors
         params = {"means": means, "log_scales": log_scales, "quats": quats, "logits": logits,
-                  "rgb": rgb, "feat": feat}
+                  "rgb": rgb_s, "feat": feat_s}
         state = ctx.state
         gos = []
         for v in range(state.n_views):
@@ -484,16 +499,20 @@ class RasterFn(torch.autograd.Function):
                         "T": gt})
         g = ctx.context.backward(state, params, gos)
         state.release()
-        return (None, None, None, g["means"], g["log_scales"], g["quats"], g["logits"],
-                g["rgb"].to(rgb.dtype), g["feat"].to(feat.dtype), g["twist"])
+        return (None, None, None, None, g["means"], g["log_scales"], g["quats"], g["logits"],
+                g["rgb"], g["feat"], g["twist"])
 
 
-def render(context: Context, params: dict, cams, settings: Settings | None = None, twist=None):
-    """Autograd-enabled render; returns a list of per-view dicts."""
+def render(context: Context, params: dict, cams, settings: Settings | None = None, twist=None,
+           storage=None):
+    """Autograd-enabled render; returns a list of per-view dicts (rgb, depth,
+    feat, T).  ``storage``: dtype of the colours and features handed to the
+    library (default: the dtype of params["rgb"]); see RasterFn."""
     V = len(cams)
     if twist is None:
         twist = torch.zeros((V, 6), device=params["means"].device, requires_grad=True)
-    flat = RasterFn.apply(context, cams, settings or Settings(), params["means"], params["log_scales"],
+    storage = params["rgb"].dtype if storage is None else storage
+    flat = RasterFn.apply(context, cams, settings or Settings(), storage, params["means"], params["log_scales"],
                           params["quats"], params["logits"], params["rgb"], params["feat"], twist)
     return [{"rgb": flat[4 * v], "depth": flat[4 * v + 1], "feat": flat[4 * v + 2], "T": flat[4 * v + 3]}
             for v in range(V)]

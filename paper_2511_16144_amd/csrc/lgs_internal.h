@@ -103,14 +103,18 @@ struct __attribute__((aligned(128))) Counters {
   uint32_t n_slots_eff; // n_slots, or 0 after an overflow
   uint32_t pad0, pad1;
   // work actually done by the compositing kernels (one atomic per wave):
-  // (pixel, entry) evaluations and contributions, forward and backward
-  unsigned long long fwd_evals, fwd_contrib, bwd_evals, bwd_contrib;
-  uint32_t pad2[16];
+  // (pixel, entry) evaluations and contributions, the list entries a wave
+  // visited (its records were loaded), forward and backward, and the
+  // backward's partial records written
+  unsigned long long fwd_evals, fwd_contrib, fwd_entries;
+  unsigned long long bwd_evals, bwd_contrib, bwd_entries, bwd_written;
+  uint32_t pad2[42];   // the queue counters below start on a 128-byte line
   // persistent-kernel work counters, queue q at word q * kLineWords, each on
   // its own line so that the queues' atomics do not serialise on one address
   uint32_t work_q[kQueues * kLineWords];    // forward
   uint32_t work_qb[kQueues * kLineWords];   // backward
 };
+static_assert(offsetof(Counters, work_q) % 128 == 0, "queue counters must start on a 128-byte line");
 
 // Queue of the items of binning tile t (global tile index).
 __host__ __device__ inline uint32_t tile_queue(uint32_t t) { return LGS_XCD_QUEUES ? (t % kQueues) : 0u; }

@@ -1,4 +1,4 @@
-// Language-guided pruning (Sec. III-D, Eq. (4)) and the geometric criteria
+// Language-guided pruning (Sec. III-C, Eq. (4)) and the geometric criteria
 // it is combined with.  For each Gaussian i, its K nearest other Gaussians
 // (Euclidean distance of the means, ties by index) are examined; a
 // neighbour j is redundant when |p_i - p_j| < tau_dist, the cosine

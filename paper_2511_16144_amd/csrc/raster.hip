@@ -206,7 +206,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ?
   }
   // this wave's work, added to the 64-bit counters once at the end (a wave's
   // own count stays far below 2^32)
-  uint32_t n_eval = 0, n_con = 0;
+  uint32_t n_eval = 0, n_con = 0, n_ent = 0;
   const uint32_t q = blockIdx.x % (uint32_t)kQueues;
   for (;;) {
     const uint32_t it = next_item(cnt->work_q, qoff, q, n_items);
@@ -300,6 +300,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ?
         }
         const uint32_t bb = gr.bbox;
         n_eval += (uint32_t)__popcll(live);
+        ++n_ent;
         const float dx = (float)(px - 8 * (int)(bb & 255u)) - gr.mx;
         const float dy = (float)(py - 8 * (int)((bb >> 16) & 255u)) - gr.my;
         const Eval e = eval_entry(dx, dy, gr.qa, gr.qb2, gr.qc, gr.o, st.cutoff2, st.alpha_max, st.alpha_min);
@@ -380,6 +381,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ?
   if (lane == 0) {
     atomicAdd(&cnt->fwd_evals, (unsigned long long)n_eval);
     atomicAdd(&cnt->fwd_contrib, (unsigned long long)n_con);
+    atomicAdd(&cnt->fwd_entries, (unsigned long long)n_ent);
   }
 }
 
@@ -506,7 +508,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
   if (cnt->overflow) return;
   // this wave's work, added to the 64-bit counters once at the end (a wave's
   // own count stays far below 2^32)
-  uint32_t n_eval = 0, n_con = 0;
+  uint32_t n_eval = 0, n_con = 0, n_ent = 0, n_wr = 0;
   const uint32_t q = blockIdx.x % (uint32_t)kQueues;
   for (;;) {
     const uint32_t it = next_item(cnt->work_qb, qoff, q, n_items);
@@ -689,6 +691,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
         const uint32_t sbase = slot_base[rid];
         const uint64_t lm = __builtin_amdgcn_ballot_w64(k <= last);   // lanes this entry can reach
         n_eval += (uint32_t)__popcll(lm);
+        ++n_ent;
         const int bx0 = (int)(gr.bbox & 255u), by0 = (int)((gr.bbox >> 16) & 255u);
         const float dx = (float)(px - 8 * bx0) - gr.mx;
         const float dy = (float)(py - 8 * by0) - gr.my;
@@ -700,6 +703,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
         if (cmask == 0ull) continue;
         const bool con = __builtin_amdgcn_inverse_ballot_w64(cmask);
         n_con += (uint32_t)__popcll(cmask);
+        ++n_wr;
         float y[20];
         y_from_words<BF16>(yw, y);
         y[3] = gr.z;
@@ -760,6 +764,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
   if (lane == 0) {
     atomicAdd(&cnt->bwd_evals, (unsigned long long)n_eval);
     atomicAdd(&cnt->bwd_contrib, (unsigned long long)n_con);
+    atomicAdd(&cnt->bwd_entries, (unsigned long long)n_ent);
+    atomicAdd(&cnt->bwd_written, (unsigned long long)n_wr);
   }
 }
 

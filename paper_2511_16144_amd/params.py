@@ -19,6 +19,3 @@ def params_from_arrays(means, log_scales, quats, logits, rgb, feat, device="cuda
         "rgb": soa(rgb, appearance_dtype), "feat": soa(feat, appearance_dtype),
     }
 
-
-def cameras_as_list(cams) -> list:
-    return list(cams)

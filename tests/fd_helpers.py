@@ -95,13 +95,21 @@ def _unstable_vjp(scene, cam, ups_full, pixels):
     return R.vjp(scene, [cam], [ups_full * m[None]], R.Settings())
 
 
-def fd_check(scene, cam, target, loss_w, params, twist=True, h=1e-4, max_unstable=200000):
-    """For each (key, gaussian, component) in `params` (and the 6 twist
-    components): (fd, ad) over the decision-stable pixels.  Returns a list of
-    (name, fd, ad) and the number of excluded parameters."""
+def base_gradient(scene, cam, target, loss_w):
+    """The oracle's L1 upstream and autodiff gradient of the whole image."""
     outs = R.render(scene, [cam], R.Settings(), want_margin=False)
     ups = R.l1_upstream(outs, [target], loss_w)[0]
-    AD = R.vjp(scene, [cam], [ups], R.Settings())
+    return ups, R.vjp(scene, [cam], [ups], R.Settings())
+
+
+def fd_check(scene, cam, target, loss_w, params, twist=True, h=1e-4, max_unstable=200000,
+             twist_components=range(6), base_grad=None, richardson=False):
+    """For each (key, gaussian, component) in `params` (and the twist
+    components): (fd, ad) over the decision-stable pixels.  Returns a list of
+    (name, fd, ad, n_unstable), the number of excluded parameters and the
+    autodiff gradient.  `base_grad`: (ups, AD) from base_gradient, if already
+    computed."""
+    ups, AD = base_grad if base_grad is not None else base_gradient(scene, cam, target, loss_w)
     rects = footprint_rects(scene, cam)
     res, excluded = [], 0
     base = {}
@@ -111,17 +119,22 @@ def fd_check(scene, cam, target, loss_w, params, twist=True, h=1e-4, max_unstabl
         if rect not in base:
             base[rect] = local_eval(scene, cam, target, loss_w, list(rect))
         l0, d0, xy, g0 = base[rect]
-        lp, dp, _, gp = perturb(+1)
-        lm, dm, _, gm = perturb(-1)
-        if gp != g0 or gm != g0:
+        steps = (1, 2) if richardson else (1,)
+        ev = {(m, s): perturb(s * m) for m in steps for s in (+1, -1)}
+        if any(e[3] != g0 for e in ev.values()):
             excluded += 1
             return
-        stable = (dp == d0) & (dm == d0)
+        stable = np.ones(len(d0), bool)
+        for e in ev.values():
+            stable &= e[1] == d0
         bad = xy[~stable]
         if len(bad) > max_unstable:
             excluded += 1
             return
-        fd = ((lp - lm)[stable]).sum() / (2 * h)
+        D = {m: ((ev[(m, 1)][0] - ev[(m, -1)][0])[stable]).sum() / (2 * m * h) for m in steps}
+        # central difference, O(h^2); with richardson the extrapolation of the
+        # h and 2h quotients, (4 D(h) - D(2h)) / 3, O(h^4)
+        fd = (4.0 * D[1] - D[2]) / 3.0 if richardson else D[1]
         ad = ad_full
         corr = _unstable_vjp(scene, cam, ups, bad)
         if corr is not None:
@@ -133,7 +146,7 @@ def fd_check(scene, cam, target, loss_w, params, twist=True, h=1e-4, max_unstabl
             continue
         rect = tuple(rects[g])
 
-        def perturb(s, k=k, g=g, c=c):
+        def perturb(s, k=k, g=g, c=c):      # s: signed multiple of h
             sc = copy.copy(scene)
             arr = np.array(getattr(scene, k), np.float64)
             if arr.ndim == 1:
@@ -149,7 +162,7 @@ def fd_check(scene, cam, target, loss_w, params, twist=True, h=1e-4, max_unstabl
             print(f"    fd: {len(res) + excluded} parameters done", flush=True)
     if twist:   # the pose moves every footprint: evaluate the whole image (no pixel twice)
         rect = ((0, 0, cam.width, cam.height),)
-        for j in range(6):
+        for j in twist_components:
             def perturb(s, j=j):
                 xi = np.zeros(6)
                 xi[j] = s * h
@@ -169,3 +182,32 @@ def subscene_64(wl, seed=5, k=64):
     rng = np.random.Generator(np.random.PCG64(seed))
     idx = np.sort(rng.choice(vis, size=k, replace=False))
     return wl.scene.subset(idx), idx
+
+
+# -- parallel driver (spawned worker processes; each rebuilds the inputs) ----
+_FD = {}
+
+
+def fd_worker_init(seed=5):
+    import scenes
+    torch.set_num_threads(1)
+    wl = scenes.make_workload(5)
+    sub, _ = subscene_64(wl, seed)
+    cam, target, loss_w = wl.cams[0], wl.targets[0], wl.loss_w
+    del wl
+    _FD.update(sub=sub, cam=cam, target=target, loss_w=loss_w,
+               base=base_gradient(sub, cam, target, loss_w))
+
+
+def fd_worker_task(task):
+    """task: ("gaussians", [indices]) or ("twist", component)."""
+    kind, arg = task
+    W = _FD
+    if kind == "gaussians":
+        params = [(k, g, c) for g in arg for k, cc in SHAPES.items() for c in range(cc)]
+        res, excl, _ = fd_check(W["sub"], W["cam"], W["target"], W["loss_w"], params, twist=False,
+                                base_grad=W["base"], richardson=True)
+    else:
+        res, excl, _ = fd_check(W["sub"], W["cam"], W["target"], W["loss_w"], [], twist=True,
+                                twist_components=[arg], base_grad=W["base"], richardson=True)
+    return res, excl

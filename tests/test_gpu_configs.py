@@ -115,6 +115,14 @@ def test_bf16_storage_rounded_and_unrounded(ctx):
     for k, (l2, mx) in res.items():
         assert l2 <= TOL_BF16 and mx <= TOL_BF16, k
     assert res["feat"][0] > 1e-5          # the rounding is visible, as it should be
+    # ... and for the gradients: the GPU's gradient (with respect to the
+    # stored BF16 values) against the oracle's on the unrounded inputs (the
+    # rounding changes no decision: colours and features do not enter alpha)
+    gr_u = R.vjp(wl.scene.unrounded(), wl.cams, ups, R.Settings())
+    err_u = grad_errors(g, gr_u, np.zeros(wl.scene.n, bool))
+    say("  bf16 gradients vs unrounded FP32:", fmt(err_u))
+    for k, (l2, mx) in err_u.items():
+        assert l2 <= TOL_BF16 and mx <= TOL_BF16, k
 
 
 def test_c4_reduced_batched_vs_oracle(ctx):
@@ -159,11 +167,22 @@ def test_full_size_windows(ctx, cfg):
     st = P.Settings(tile=16, order=1)
     out, g, counts = gpu_fwd_bwd(ctx, wl.scene, wl.cams, ups, st)
     say("  counts", counts)
+    masks = []
     for v, cam in enumerate(wl.cams):
         m = np.zeros((cam.height, cam.width), bool)
         for (x0, y0, w, h) in wins[v]:
             m[y0:y0 + h, x0:x0 + w] = True
         check_forward(out[v], ref[v], mask_rect=m, label=f"C{cfg} view {v}")
+        masks.append(m)
+    if cfg == 3:
+        # precision error of BF16 storage at full size: the same windows
+        # against the oracle on the unrounded FP32 colours and features
+        ref_u = R.render(sub.unrounded(), wl.cams, R.Settings(), rects=wins, want_margin=False)
+        keep = masks[0] & ~ambiguous(ref[0]["margin"])
+        res = {k: rel_err(out[0][k], ref_u[0][k], keep) for k in ("rgb", "depth", "feat", "T")}
+        say("  C3 windows, bf16 vs unrounded FP32:", fmt(res))
+        for k, (l2, mx) in res.items():
+            assert l2 <= TOL_BF16 and mx <= TOL_BF16, k
     gr_sub = R.vjp(sub, wl.cams, ups, R.Settings(), rects=wins)
     gr = {k: np.zeros((wl.scene.n,) + np.shape(v)[1:]) for k, v in gr_sub.items() if k != "twist"}
     for k in gr:
@@ -177,3 +196,10 @@ def test_full_size_windows(ctx, cfg):
         gk = g[k].T if g[k].ndim == 2 else g[k]
         assert np.all(gk[outside] == 0), k
     check_grads(g, gr, bad, label=f"C{cfg}")
+    if cfg == 3:
+        gu_sub = R.vjp(sub.unrounded(), wl.cams, ups, R.Settings(), rects=wins)
+        gu = {k: np.zeros((wl.scene.n,) + np.shape(v)[1:]) for k, v in gu_sub.items() if k != "twist"}
+        for k in gu:
+            gu[k][idx] = gu_sub[k]
+        gu["twist"] = gu_sub["twist"]
+        check_grads(g, gu, bad, tol=TOL_BF16, label="C3 bf16 vs unrounded FP32")

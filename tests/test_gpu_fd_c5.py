@@ -1,23 +1,18 @@
 """Differentiation at scale (the 2M-Gaussian, 1296x968, BF16 configuration):
 64 Gaussians drawn with seed 5 among those visible in its view, rendered
 alone at its camera and resolution with its targets and loss weights
-(1, 0.1, 1).
-
-* the GPU gradient of the L1 step (lgs_forward + lgs_backward_l1) against the
-  oracle's autodiff gradient, for all 64 x 30 parameters and the 6 twist
-  components (1e-4);
-* the oracle's autodiff gradient against central finite differences
-  (h = 1e-4, FP64) over the pixels whose decisions do not change, for every
-  parameter of 6 seeded Gaussians and the twist (1e-5).
-"""
-import sys
-
+(1, 0.1, 1).  The GPU gradient of the L1 step (lgs_forward +
+lgs_backward_l1) against the oracle's autodiff gradient, for all 64 x 30
+parameters and the 6 twist components (1e-4).  The oracle's autodiff
+gradient of the same sub-scene is checked against central finite
+differences on every one of those scalars by the CPU test
+test_oracle_fd_c5.py."""
 import numpy as np
 import pytest
 import torch
 
 import scenes
-from fd_helpers import SHAPES, fd_check, subscene_64
+from fd_helpers import base_gradient, subscene_64
 from parity import TOL_F32, fmt, gpu_params, grad_errors, grads_np
 
 pytestmark = pytest.mark.gpu
@@ -27,7 +22,7 @@ def say(*a):
     print(*a, flush=True)
 
 
-def test_c5_subset_gpu_vs_autodiff_vs_fd():
+def test_c5_subset_gpu_vs_autodiff():
     import paper_2511_16144_amd as P
     wl = scenes.make_workload(5)
     sub, idx = subscene_64(wl)
@@ -42,21 +37,8 @@ def test_c5_subset_gpu_vs_autodiff_vs_fd():
     torch.cuda.synchronize()
     st.release()
     ctx.close()
-    rng = np.random.Generator(np.random.PCG64(55))
-    fd_g = sorted(rng.choice(sub.n, size=6, replace=False).tolist())
-    params = [(k, gg, c) for gg in fd_g for k, cc in SHAPES.items() for c in range(cc)]
-    say(f"  finite differences on Gaussians {fd_g} ({len(params)} scalars) and the twist")
-    res, excluded, AD = fd_check(sub, cam, wl.targets[0], wl.loss_w, params, twist=True)
-    # GPU vs autodiff (every parameter)
+    _, AD = base_gradient(sub, cam, wl.targets[0], wl.loss_w)
     err = grad_errors(g, AD, np.zeros(sub.n, bool))
-    say("  GPU vs autodiff:", fmt(err))
+    say("  GPU vs autodiff (all 64 x 30 parameters and the twist):", fmt(err))
     for k, (l2, mx) in err.items():
         assert l2 <= TOL_F32 and mx <= TOL_F32, (k, l2, mx)
-    # autodiff vs FD (decision-stable pixels)
-    worst = 0.0
-    for name, fd, ad, n_unstable in res:
-        rel = abs(fd - ad) / max(abs(ad), 1e-12)
-        worst = max(worst, rel)
-        assert rel <= 1e-5 or abs(fd - ad) <= 1e-12, (name, fd, ad, n_unstable)
-    say(f"  autodiff vs FD: {len(res)} checked, {excluded} excluded, worst relative difference {worst:.2e}")
-    assert len(res) >= 0.9 * (len(params) + 6)

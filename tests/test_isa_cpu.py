@@ -47,7 +47,7 @@ def test_persistent_compositing_loops_are_wave_uniform(tmp_path):
 
 
 @pytest.mark.skipif(not os.path.exists(HIPCC), reason="hipcc not available")
-@pytest.mark.parametrize("src", ["raster.hip", "binning.hip", "radix_sort.hip", "project.hip", "loss.hip"])
+@pytest.mark.parametrize("src", sorted(f for f in os.listdir(CSRC) if f.endswith(".hip")))
 def test_no_scalar_memory_writes(src, tmp_path):
     asm = _asm(src, tmp_path)
     bad = re.findall(r"^\s+(s_(?:store|buffer_store|atomic|buffer_atomic|dcache_wb|dcache_discard|scratch_store)\w*)",
