@@ -179,9 +179,7 @@ def time_workload(ctx, wl, steps, warmup, dev, tune, settings):
         ctx.backward_l1(state, params, outs, tgts, wl.loss_w, grads=grads)
         if record is not None:
             record.append(state.stage_ms())
-        c = state.counts() if record is not None and len(record) == 1 else None
         state.release()
-        return c
 
     for _ in range(warmup):
         step(None)
@@ -189,26 +187,27 @@ def time_workload(ctx, wl, steps, warmup, dev, tune, settings):
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-    stages = [] if st.profile else None
-    counts = None
+    stages = [] if st.profile & B.PROFILE_EVENTS else None
     t0 = time.perf_counter()
     e0.record()
     for a, b in ev:
         a.record()
-        c = step(stages)
+        step(stages)
         b.record()
-        counts = counts or c
     e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_mean = e0.elapsed_time(e1) / steps
     per = sorted(a.elapsed_time(b) for a, b in ev)
     ms = per[len(per) // 2]
-    if counts is None:
-        o, state = ctx.forward(params, wl.cams, st, out=outs)
-        ctx.backward_l1(state, params, outs, tgts, wl.loss_w, grads=grads)
-        counts = state.counts()
-        state.release()
+    # the work counts come from one more step with the compositing kernels'
+    # counting variants (the timed steps run the variants that do not count)
+    cs = B.Settings.from_c(st.to_c())
+    cs.profile = B.PROFILE_COUNTS
+    o, state = ctx.forward(params, wl.cams, cs, out=outs)
+    ctx.backward_l1(state, params, outs, tgts, wl.loss_w, grads=grads)
+    counts = state.counts()
+    state.release()
     med_st = [sorted(x[i] for x in stages)[len(stages) // 2] for i in range(5)] if stages else None
     return {"ms": ms, "ms_mean": ms_mean, "wall_s": wall, "counts": counts, "stages": med_st,
             "settings": {"tile": st.tile, "chunk": st.chunk, "order": st.order}}

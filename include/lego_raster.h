@@ -27,8 +27,8 @@
  *   - Every call enqueues work on the given stream and returns without
  *     waiting for it, except where its comment says it synchronises: an
  *     eager forward performs one 4-byte device->host read (the pair count);
- *     lgs_prune, the count / stage-time queries, lgs_graph_status,
- *     lgs_autotune and the destroy calls synchronise.  Releasing a state is
+ *     lgs_prune, the count / stage-time queries, lgs_graph_create,
+ *     lgs_graph_status, lgs_autotune and the destroy calls synchronise.  Releasing a state is
  *     stream-ordered: its device buffers return to the context's cache and
  *     are handed out again only behind the work already enqueued on that
  *     stream.
@@ -62,6 +62,9 @@ typedef enum {
 
 typedef enum { LGS_F32 = 0, LGS_BF16 = 1 } lgs_dtype;
 
+/* Bits of lgs_settings.profile. */
+enum { LGS_PROFILE_EVENTS = 1, LGS_PROFILE_COUNTS = 2 };
+
 /* Pinhole camera and world->camera pose (Sec. III-A: T_k in SE(3)). */
 typedef struct {
   int32_t width, height;
@@ -84,7 +87,11 @@ typedef struct {
   int32_t tile;     /* 16      binning tile side: 8, 16 or 32 */
   int32_t chunk;    /* 4       8x8 pixel blocks per work-group (1, 2, 4, 8) */
   int32_t order;    /* 0       1: work queue in descending list length, 0: raster order */
-  int32_t profile;  /* 0       1: record HIP events around each stage (lgs_state_stage_ms) */
+  int32_t profile;  /* 0       bit LGS_PROFILE_EVENTS: record HIP events around each
+                     *         stage (lgs_state_stage_ms, lgs_graph_stage_ms);
+                     *         bit LGS_PROFILE_COUNTS: run the compositing kernels'
+                     *         counting variants, which fill the work counts of
+                     *         lgs_counts (fwd_evals .. bwd_written; 0 otherwise) */
 } lgs_settings;
 
 /* Gaussians: SoA planes, n of each (Sec. III-B.1, Theta).  means [3][n],
@@ -129,7 +136,10 @@ typedef struct lgs_fwd_state lgs_fwd_state;
 typedef struct lgs_graph lgs_graph;
 
 /* Work counts of a forward (and of its backward once run), for measurement
- * and tests. */
+ * and tests.  The compositing kernels' counts (fwd_evals .. bwd_written) are
+ * collected only with the LGS_PROFILE_COUNTS bit of settings.profile (they
+ * read 0 otherwise): counting in the entry loops costs those kernels
+ * several percent, so the timed variants do not count. */
 typedef struct {
   int64_t n_visible;    /* visible (view, Gaussian) pairs */
   int64_t n_pairs;      /* (tile, Gaussian) pairs after binning */
@@ -274,11 +284,11 @@ lgs_status lgs_prune(lgs_context *ctx, const lgs_gaussians *g,
 /* Counts of the state's forward and, once enqueued, its backward (read when
  * asked for: synchronises with the device). */
 lgs_status lgs_state_counts(const lgs_fwd_state *state, lgs_counts *out);
-/* With settings.profile = 1 on the forward, after its backward: elapsed
- * milliseconds of ms[0..4] = projection + depth sort + scans, pair emission
- * + tile sort, forward compositing kernel, backward compositing kernel,
- * gradient reduction + projection backward (HIP events on the caller's
- * stream).  Synchronises. */
+/* With the LGS_PROFILE_EVENTS bit of settings.profile on the forward, after
+ * its backward: elapsed milliseconds of ms[0..4] = projection + depth sort +
+ * scans, pair emission + tile sort, forward compositing kernel, backward
+ * compositing kernel, gradient reduction + projection backward (HIP events
+ * on the caller's stream).  Synchronises. */
 lgs_status lgs_state_stage_ms(const lgs_fwd_state *state, float ms[5]);
 /* Frees the state without waiting: its device buffers go back to the
  * context's cache behind the work already enqueued on the state's stream
@@ -298,7 +308,9 @@ lgs_status lgs_state_release(lgs_context *ctx, lgs_fwd_state *state);
  * every launch recomputes them from the current contents of the Gaussian
  * arrays.  pair_capacity bounds the (tile, Gaussian) pairs; a launch that
  * would exceed it writes nothing valid and lgs_graph_status then returns
- * LGS_ERR_CAPACITY (re-create with a larger capacity). */
+ * LGS_ERR_CAPACITY (re-create with a larger capacity).  Creation waits for
+ * its own uploads on `stream` before returning, so the graph may then be
+ * launched on any stream. */
 lgs_status lgs_graph_create(lgs_context *ctx, const lgs_settings *st,
                             const lgs_gaussians *g, int32_t n_views,
                             const lgs_camera *cams, const lgs_images *targets,
@@ -312,10 +324,11 @@ lgs_status lgs_graph_launch(lgs_graph *graph, hipStream_t stream);
 lgs_status lgs_graph_status(lgs_graph *graph);
 /* Work counts of the graph's last launch (synchronises with it). */
 lgs_status lgs_graph_counts(lgs_graph *graph, lgs_counts *out);
-/* With settings.profile = 1 at creation, the step is captured as five
- * graphs, one per stage, which lgs_graph_launch launches back to back with
- * HIP events recorded between them on the launching stream (same results as
- * the one-graph form).  Elapsed milliseconds of the last launch's stages,
+/* With the LGS_PROFILE_EVENTS bit of settings.profile at creation, the step
+ * is captured as five graphs, one per stage, which lgs_graph_launch launches
+ * back to back with HIP events recorded between them on the launching stream
+ * (same results as the one-graph form).  Elapsed milliseconds of the last
+ * launch's stages,
  * ms[0..4] = projection + depth sort + scans, pair emission + tile sort,
  * forward compositing, backward compositing (with the loss gradient: fused
  * L1, or the lgs_loss kernel), gradient reduction + projection backward.  Synchronises. */

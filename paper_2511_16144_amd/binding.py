@@ -18,6 +18,8 @@ LIB_PATH = os.path.join(_HERE, "liblego_raster.so")
 
 LGS_OK, LGS_ERR_INVALID_ARG, LGS_ERR_HIP, LGS_ERR_CAPACITY, LGS_ERR_UNSUPPORTED, LGS_ERR_STATE = range(6)
 LGS_F32, LGS_BF16 = 0, 1
+# bits of lgs_settings.profile: stage events, compositing work counts
+PROFILE_EVENTS, PROFILE_COUNTS = 1, 2
 
 
 class lgs_camera(C.Structure):

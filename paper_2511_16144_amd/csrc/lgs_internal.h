@@ -79,6 +79,7 @@ struct Settings {
   int32_t tile, tile_shift;   // tile side and log2(tile / 8)
   int32_t feat_dim;           // D: feature planes of the inputs
   int32_t nfeat;              // feature channels of the group being processed (8 or 16)
+  int32_t count;              // 1: the compositing kernels' profiling variants, which count their work
 };
 
 // Device-resident counters of one forward (written by kernels, read by

@@ -178,7 +178,7 @@ constexpr int kFwdWaveLds = (2 * kFwdY + 3 * kFwdW) * 2;
 // appearance: seven (72 VGPRs), so that a batch's weight operands stay in
 // registers across its five channel blocks (faster than eight waves that
 // re-read them).
-template <bool BF16>
+template <bool BF16, bool CNT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 7 : 8, BF16 ? 7 : 8))) k_raster_fwd(
     Settings st, const ViewDesc* __restrict__ views, const ViewImages* __restrict__ out,
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ vals,
@@ -204,8 +204,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ?
 #pragma unroll
     for (int t = 0; t < 3; ++t) *(uint4*)(ws + t * kFwdW + lane * 8) = make_uint4(0u, 0u, 0u, 0u);
   }
-  // this wave's work, added to the 64-bit counters once at the end (a wave's
-  // own count stays far below 2^32)
+  // this wave's work (CNT: the profiling variant), added to the 64-bit
+  // counters once at the end (a wave's own count stays far below 2^32); the
+  // timed variant carries none of this bookkeeping in its entry loop
   uint32_t n_eval = 0, n_con = 0, n_ent = 0;
   const uint32_t q = blockIdx.x % (uint32_t)kQueues;
   for (;;) {
@@ -299,8 +300,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ?
           gr.bbox = __builtin_amdgcn_readlane(g_l.bbox, j);
         }
         const uint32_t bb = gr.bbox;
-        n_eval += (uint32_t)__popcll(live);
-        ++n_ent;
+        if (CNT) {
+          n_eval += (uint32_t)__popcll(live);
+          ++n_ent;
+        }
         const float dx = (float)(px - 8 * (int)(bb & 255u)) - gr.mx;
         const float dy = (float)(py - 8 * (int)((bb >> 16) & 255u)) - gr.my;
         const Eval e = eval_entry(dx, dy, gr.qa, gr.qb2, gr.qc, gr.o, st.cutoff2, st.alpha_max, st.alpha_min);
@@ -313,7 +316,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ?
         const uint64_t cmask = pm & ~tm;
         if (cmask != 0ull) {
           const bool con = __builtin_amdgcn_inverse_ballot_w64(cmask);
-          n_con += (uint32_t)__popcll(cmask);
+          if (CNT) n_con += (uint32_t)__popcll(cmask);
           const float w = con ? e.alpha * T : 0.f;
           if (BF16) {
             accz = __builtin_fmaf(w, gr.z, accz);
@@ -378,7 +381,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ?
       T_state[(size_t)V->pix_off + p] = T;
     }
   }
-  if (lane == 0) {
+  if (CNT && lane == 0) {
     atomicAdd(&cnt->fwd_evals, (unsigned long long)n_eval);
     atomicAdd(&cnt->fwd_contrib, (unsigned long long)n_con);
     atomicAdd(&cnt->fwd_entries, (unsigned long long)n_ent);
@@ -478,7 +481,7 @@ __device__ __forceinline__ float transpose_reduce6(const float v[6], int lane) {
 }
 
 // Six waves per SIMD (80 VGPRs; measured fastest for this kernel).
-template <bool BF16, int UPM>
+template <bool BF16, int UPM, bool CNT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))) k_raster_bwd(
     Settings st, const ViewDesc* __restrict__ views, const ViewImages* __restrict__ upstream,
     const ViewImages* __restrict__ fwd_out, const ViewImages* __restrict__ targets,
@@ -506,8 +509,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
   float* stage = (float*)(wz + 16 * kZRow);         // 8 records of kRecLds floats
   const int grp = lane >> 4, col = lane & 15;
   if (cnt->overflow) return;
-  // this wave's work, added to the 64-bit counters once at the end (a wave's
-  // own count stays far below 2^32)
+  // this wave's work (CNT: the profiling variant), added to the 64-bit
+  // counters once at the end (a wave's own count stays far below 2^32)
   uint32_t n_eval = 0, n_con = 0, n_ent = 0, n_wr = 0;
   const uint32_t q = blockIdx.x % (uint32_t)kQueues;
   for (;;) {
@@ -613,9 +616,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
     int nb = 0;
     uint32_t slotv = 0;   // lane e: the slot of the batch's entry e
     // Write the batch's nb partial records: the colour partials join the
-    // geometric ones in the staged records, then every lane stores one
-    // 16-byte quarter of a record (one full 128-byte slot per 8 lanes) and
-    // the first lane of each record sets the slot's mask byte.
+    // geometric ones in the staged records, then lanes store 16-byte
+    // quarters of the records (seven quarters, 112 bytes, of each 128-byte
+    // slot; 8 lanes per record) and the first lane of each record sets the
+    // slot's mask byte.
     auto flush = [&]() {
       f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
       const int er = col & 7;
@@ -658,7 +662,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
       const int er4 = lane >> 3, q4 = lane & 7;
       const float4 v4 = *(const float4*)(stage + er4 * kRecLds + 4 * q4);
       const uint32_t sl = (uint32_t)__builtin_amdgcn_ds_bpermute(er4 * 4, (int)slotv);
-      if (er4 < nb) {
+      // quarters 0..6 hold the kPartials values; the eighth is padding that
+      // the reduction never reads, so it is not written
+      static_assert(kPartials <= 28, "the partials fit in seven 16-byte quarters");
+      if (er4 < nb && q4 < 7) {
         *(float4*)(partials + (size_t)sl * kSlotFloats + 4 * q4) = v4;
         if (q4 == 0) mask[sl] = 1;
       }
@@ -690,8 +697,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
         load_app_words<BF16>(app, rid & npad_mask, yw);
         const uint32_t sbase = slot_base[rid];
         const uint64_t lm = __builtin_amdgcn_ballot_w64(k <= last);   // lanes this entry can reach
-        n_eval += (uint32_t)__popcll(lm);
-        ++n_ent;
+        if (CNT) {
+          n_eval += (uint32_t)__popcll(lm);
+          ++n_ent;
+        }
         const int bx0 = (int)(gr.bbox & 255u), by0 = (int)((gr.bbox >> 16) & 255u);
         const float dx = (float)(px - 8 * bx0) - gr.mx;
         const float dy = (float)(py - 8 * by0) - gr.my;
@@ -702,8 +711,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
                                __builtin_amdgcn_ballot_w64(e.alpha >= st.alpha_min);
         if (cmask == 0ull) continue;
         const bool con = __builtin_amdgcn_inverse_ballot_w64(cmask);
-        n_con += (uint32_t)__popcll(cmask);
-        ++n_wr;
+        if (CNT) {
+          n_con += (uint32_t)__popcll(cmask);
+          ++n_wr;
+        }
         float y[20];
         y_from_words<BF16>(yw, y);
         y[3] = gr.z;
@@ -761,7 +772,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
     }
     if (nb > 0) flush();
   }
-  if (lane == 0) {
+  if (CNT && lane == 0) {
     atomicAdd(&cnt->bwd_evals, (unsigned long long)n_eval);
     atomicAdd(&cnt->bwd_contrib, (unsigned long long)n_con);
     atomicAdd(&cnt->bwd_entries, (unsigned long long)n_ent);
@@ -828,36 +839,45 @@ __global__ void __launch_bounds__(256) k_seg_reduce(const uint32_t* __restrict__
 
 }  // namespace
 
-void launch_raster_fwd(const Settings& st, const ViewDesc* views, const ViewImages* out, const uint2* ranges,
-                       const uint32_t* vals, const GeomRec* geom, const void* app, int app_bf16,
-                       uint32_t npad_mask, const uint32_t* items, const uint32_t* qoff, int64_t n_items,
-                       Counters* cnt, int waves_per_group, int32_t* last_idx, float* T_state, hipStream_t s) {
-  if (n_items <= 0) return;
+template <bool BF16, bool CNT>
+static void launch_fwd_t(const Settings& st, const ViewDesc* views, const ViewImages* out, const uint2* ranges,
+                         const uint32_t* vals, const GeomRec* geom, const void* app, uint32_t npad_mask,
+                         const uint32_t* items, const uint32_t* qoff, int64_t n_items, Counters* cnt,
+                         int waves_per_group, int32_t* last_idx, float* T_state, hipStream_t s) {
   const int threads = 64 * waves_per_group;
   int dev = 0, cus = 256;
   hipGetDevice(&dev);
   hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   int occ = 1;
-  const size_t lds = app_bf16 ? (size_t)waves_per_group * kFwdWaveLds : 0;
-  if (app_bf16)
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_raster_fwd<true>, threads, lds);
-  else
-    hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_raster_fwd<false>, threads, 0);
+  const size_t lds = BF16 ? (size_t)waves_per_group * kFwdWaveLds : 0;
+  hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_raster_fwd<BF16, CNT>, threads, lds);
   int64_t grid = (int64_t)cus * (occ > 0 ? occ : 1);
   const int64_t need = (n_items + waves_per_group - 1) / waves_per_group;
   if (grid > need) grid = need;
   if (grid < kQueues) grid = kQueues;   // every queue needs a workgroup (index mod kQueues) to drain it
-  if (app_bf16)
-    hipLaunchKernelGGL(k_raster_fwd<true>, dim3((unsigned)grid), dim3(threads), lds, s, st, views, out,
-                       ranges, vals, geom, app, npad_mask, items, qoff, (uint32_t)n_items, cnt, last_idx,
-                       T_state);
-  else
-    hipLaunchKernelGGL(k_raster_fwd<false>, dim3((unsigned)grid), dim3(threads), 0, s, st, views, out,
-                       ranges, vals, geom, app, npad_mask, items, qoff, (uint32_t)n_items, cnt, last_idx,
-                       T_state);
+  hipLaunchKernelGGL((k_raster_fwd<BF16, CNT>), dim3((unsigned)grid), dim3(threads), lds, s, st, views, out,
+                     ranges, vals, geom, app, npad_mask, items, qoff, (uint32_t)n_items, cnt, last_idx, T_state);
 }
 
-template <bool BF16, int UPM>
+void launch_raster_fwd(const Settings& st, const ViewDesc* views, const ViewImages* out, const uint2* ranges,
+                       const uint32_t* vals, const GeomRec* geom, const void* app, int app_bf16,
+                       uint32_t npad_mask, const uint32_t* items, const uint32_t* qoff, int64_t n_items,
+                       Counters* cnt, int waves_per_group, int32_t* last_idx, float* T_state, hipStream_t s) {
+  if (n_items <= 0) return;
+#define LGS_FWD(B, K)                                                                                        \
+  launch_fwd_t<B, K>(st, views, out, ranges, vals, geom, app, npad_mask, items, qoff, n_items, cnt,          \
+                     waves_per_group, last_idx, T_state, s)
+  if (app_bf16) {
+    if (st.count) LGS_FWD(true, true);
+    else LGS_FWD(true, false);
+  } else {
+    if (st.count) LGS_FWD(false, true);
+    else LGS_FWD(false, false);
+  }
+#undef LGS_FWD
+}
+
+template <bool BF16, int UPM, bool CNT>
 static void launch_bwd_t(const Settings& st, const ViewDesc* views, const ViewImages* upstream,
                          const ViewImages* fwd_out, const ViewImages* targets, const float* loss_w,
                          const uint2* ranges, const uint32_t* vals, const GeomRec* geom, const void* app,
@@ -870,12 +890,12 @@ static void launch_bwd_t(const Settings& st, const ViewDesc* views, const ViewIm
   hipGetDevice(&dev);
   hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   int occ = 1;
-  hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_raster_bwd<BF16, UPM>, threads, lds);
+  hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_raster_bwd<BF16, UPM, CNT>, threads, lds);
   int64_t grid = (int64_t)cus * (occ > 0 ? occ : 1);
   const int64_t need = (n_items + waves_per_group - 1) / waves_per_group;
   if (grid > need) grid = need;
   if (grid < kQueues) grid = kQueues;   // every queue needs a workgroup (index mod kQueues) to drain it
-  hipLaunchKernelGGL((k_raster_bwd<BF16, UPM>), dim3((unsigned)grid), dim3(threads), lds, s, st, views,
+  hipLaunchKernelGGL((k_raster_bwd<BF16, UPM, CNT>), dim3((unsigned)grid), dim3(threads), lds, s, st, views,
                      upstream, fwd_out, targets, loss_w, ranges, vals, geom, app, npad_mask, items, qoff,
                      (uint32_t)n_items, cnt, last_idx, T_state, slot_base, partials, mask);
 }
@@ -889,9 +909,12 @@ void launch_raster_bwd(int up_mode, const Settings& st, const ViewDesc* views, c
                        hipStream_t s) {
   if (n_items <= 0) return;
 #define LGS_BWD(B, M)                                                                                     \
-  launch_bwd_t<B, M>(st, views, upstream, fwd_out, targets, loss_w, ranges, vals, geom, app, npad_mask,   \
-                     items, qoff, n_items, cnt, waves_per_group, last_idx, T_state, slot_base, partials, \
-                     mask, s)
+  (st.count ? launch_bwd_t<B, M, true>(st, views, upstream, fwd_out, targets, loss_w, ranges, vals, geom, app,  \
+                                       npad_mask, items, qoff, n_items, cnt, waves_per_group, last_idx,      \
+                                       T_state, slot_base, partials, mask, s)                                 \
+            : launch_bwd_t<B, M, false>(st, views, upstream, fwd_out, targets, loss_w, ranges, vals, geom,  \
+                                        app, npad_mask, items, qoff, n_items, cnt, waves_per_group, last_idx, \
+                                        T_state, slot_base, partials, mask, s))
   if (app_bf16) {
     if (up_mode == UP_L1) LGS_BWD(true, UP_L1);
     else if (up_mode == UP_RGB) LGS_BWD(true, UP_RGB);

@@ -140,6 +140,8 @@ lgs_status check_settings(lgs_context* ctx, const lgs_settings* st) {
   if (st->chunk != 1 && st->chunk != 2 && st->chunk != 4 && st->chunk != 8)
     return fail(ctx, LGS_ERR_INVALID_ARG, "chunk must be 1, 2, 4 or 8");
   if (st->order != 0 && st->order != 1) return fail(ctx, LGS_ERR_INVALID_ARG, "order must be 0 or 1");
+  if (st->profile & ~(LGS_PROFILE_EVENTS | LGS_PROFILE_COUNTS))
+    return fail(ctx, LGS_ERR_INVALID_ARG, "profile takes the bits LGS_PROFILE_EVENTS | LGS_PROFILE_COUNTS");
   if (!(st->z_near > 0.f) || !(st->eps2d >= 0.f) || !(st->fov_clamp > 0.f) ||
       !(st->alpha_max > 0.f && st->alpha_max < 1.f) || !(st->alpha_min > 0.f) ||
       !(st->T_eps > 0.f && st->T_eps < 1.f) || !(st->cutoff2 > 0.f))
@@ -284,6 +286,7 @@ Settings dev_settings(const lgs_settings* st, int tile_shift, int D = kFeatGroup
   s.cutoff2 = st->cutoff2; s.tile = st->tile; s.tile_shift = tile_shift;
   s.feat_dim = D;
   s.nfeat = group_nfeat(D, group);
+  s.count = (st->profile & LGS_PROFILE_COUNTS) != 0;
   return s;
 }
 
@@ -893,7 +896,7 @@ lgs_status lgs_forward(lgs_context* ctx, const lgs_settings* st, const lgs_gauss
   if ((rc = w_init(W, ctx, st, g, n_views, cams, stream)) != LGS_OK) return bail(rc);
   if ((rc = w_alloc_front(W)) != LGS_OK) return bail(rc);
   if ((rc = w_upload(W, out, stream)) != LGS_OK) return bail(rc);
-  if (st->profile)
+  if (st->profile & LGS_PROFILE_EVENTS)
     for (int i = 0; i < 8; ++i)
       if (hipEventCreate(&W->ev[i]) != hipSuccess) return bail(fail(ctx, LGS_ERR_HIP, "event creation failed"));
   w_mark(W, 0, stream);
@@ -1264,10 +1267,10 @@ lgs_status lgs_graph_create(lgs_context* ctx, const lgs_settings* st, const lgs_
   }
   if (hipStreamCreateWithFlags(&G->cap_stream, hipStreamNonBlocking) != hipSuccess)
     return bail(fail(ctx, LGS_ERR_HIP, "stream creation failed"));
-  if (st->profile)
+  G->profile = (st->profile & LGS_PROFILE_EVENTS) != 0;
+  if (G->profile)
     for (int i = 0; i < 6; ++i)
       if (hipEventCreate(&G->ev[i]) != hipSuccess) return bail(fail(ctx, LGS_ERR_HIP, "event creation failed"));
-  G->profile = st->profile != 0;
   auto stage = [&](int i) {
     switch (i) {
       case 0: enqueue_front(W, &G->g, G->cap_stream); break;
@@ -1302,6 +1305,10 @@ lgs_status lgs_graph_create(lgs_context* ctx, const lgs_settings* st, const lgs_
   } else if ((rc = capture(0, 4, &G->graph, &G->exec)) != LGS_OK) {
     return bail(rc);
   }
+  // the table uploads and the waits for reused blocks were enqueued on
+  // `stream`; the graph may later be launched on any stream, so creation
+  // ends once they have run
+  if (hipStreamSynchronize(stream) != hipSuccess) return bail(fail(ctx, LGS_ERR_HIP, "stream synchronisation failed"));
   W->counts = pc;
   *graph_out = G;
   return LGS_OK;

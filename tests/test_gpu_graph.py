@@ -128,7 +128,7 @@ def test_graph_capacity_overflow_and_recreate(ctx):
     assert np.isfinite(grads["twist"]).all()        # overflow writes zero gradients, no garbage
     assert np.all(grads["means"] == 0)
     run.destroy()
-    run = GraphRun(ctx, wl, P.Settings(tile=8), capacity=0)
+    run = GraphRun(ctx, wl, P.Settings(tile=8, profile=P.binding.PROFILE_COUNTS), capacity=0)
     run.launch()
     assert run.status() == 0
     c = run.counts()
