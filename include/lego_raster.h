@@ -250,6 +250,28 @@ lgs_status lgs_decoder_l1(lgs_context *ctx, int32_t width, int32_t height,
                           float w_feat, float *grad_feat, float *grad_weight,
                           float *grad_bias, float *loss, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation as lgs_decoder_l1, same arguments and results (the same
+ * kernels and, up to 256 work-groups, the same launch), with no allocation.
+ * Its per-work-group partial sums live in a fixed device array of 256 x 8768
+ * floats (8.98 MB) that the library holds on every GPU it runs on until the
+ * process ends (its address is resolved once per device at
+ * lgs_context_create); it calls no hipMalloc, hipFree or allocating library
+ * routine.  Every call on one GPU shares that GPU's array: calls that overlap
+ * on one GPU (other streams, other contexts, other threads) race and must be
+ * ordered by the caller.  LGS_ERR_CAPACITY if the partial sums would exceed
+ * the array (not reachable with out_dim <= 512), otherwise the errors of
+ * lgs_decoder_l1. */
+lgs_status lgs_decoder_l1_noalloc(lgs_context *ctx, int32_t width,
+                                  int32_t height, int32_t out_dim,
+                                  const float *feat, const float *weight,
+                                  const float *bias, const void *target,
+                                  lgs_dtype target_dtype, float w_feat,
+                                  float *grad_feat, float *grad_weight,
+                                  float *grad_bias, float *loss,
+                                  hipStream_t stream);
+
 /* Language-guided pruning (Sec. III-C, Eq. (4)) combined with the geometric
  * criteria.  The paper publishes neither K nor the thresholds; the defaults
  * (lgs_default_prune_params) are readings:

@@ -65,6 +65,7 @@ class lgs_counts(C.Structure):
 
 EXPORTS = ["lgs_status_string", "lgs_last_error", "lgs_default_settings", "lgs_context_create",
            "lgs_context_destroy", "lgs_forward", "lgs_backward", "lgs_backward_l1", "lgs_loss", "lgs_decoder_l1",
+           "lgs_decoder_l1_noalloc",
            "lgs_default_prune_params", "lgs_prune",
            "lgs_state_counts",
            "lgs_state_stage_ms",
@@ -104,6 +105,9 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.lgs_decoder_l1.restype = C.c_int
     lib.lgs_decoder_l1.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, P, P, P, P, C.c_int32, C.c_float,
                                    P, P, P, P, P]
+    lib.lgs_decoder_l1_noalloc.restype = C.c_int
+    lib.lgs_decoder_l1_noalloc.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, P, P, P, P, C.c_int32,
+                                           C.c_float, P, P, P, P, P]
     lib.lgs_default_prune_params.restype = lgs_prune_params
     lib.lgs_default_prune_params.argtypes = []
     lib.lgs_prune.restype = C.c_int
@@ -301,9 +305,12 @@ class Context:
             self._raise(st)
         return grad, terms
 
-    def decoder_l1(self, feat, weight, bias, target, w_feat: float = 1.0, stream=None, out=None):
+    def decoder_l1(self, feat, weight, bias, target, w_feat: float = 1.0, stream=None, out=None,
+                   noalloc: bool = False):
         """Feature-distillation loss of Eq. (2) through the 1x1-conv decoder
-        (lgs_decoder_l1).  feat [16,H,W] FP32, weight [C,16], bias [C] FP32,
+        (lgs_decoder_l1, or lgs_decoder_l1_noalloc with noalloc=True: no
+        device allocation in the library; pass `out` to allocate nothing
+        here either).  feat [16,H,W] FP32, weight [C,16], bias [C] FP32,
         target [C,H,W] BF16 or FP32 (CUDA, contiguous).  Returns (loss [1],
         grad_feat, grad_weight, grad_bias)."""
         d, H, W = feat.shape
@@ -320,8 +327,9 @@ class Context:
                    torch.empty_like(bias))
         loss, gf, gw, gb = out
         dt = LGS_BF16 if target.dtype == torch.bfloat16 else LGS_F32
-        st = lib().lgs_decoder_l1(self._h, W, H, Cd, _ptr(feat), _ptr(weight), _ptr(bias), _ptr(target), dt,
-                                  float(w_feat), _ptr(gf), _ptr(gw), _ptr(gb), _ptr(loss), _stream(stream))
+        fn = lib().lgs_decoder_l1_noalloc if noalloc else lib().lgs_decoder_l1
+        st = fn(self._h, W, H, Cd, _ptr(feat), _ptr(weight), _ptr(bias), _ptr(target), dt,
+                float(w_feat), _ptr(gf), _ptr(gw), _ptr(gb), _ptr(loss), _stream(stream))
         if st != LGS_OK:
             self._raise(st)
         return loss, gf, gw, gb

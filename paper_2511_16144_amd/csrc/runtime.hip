@@ -13,6 +13,7 @@
 #include <deque>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <cstddef>
 #include <type_traits>
@@ -58,7 +59,21 @@ struct lgs_context {
   // lgs_decoder_l1 workspace: per-work-group partial sums
   float* dec_part = nullptr;
   int64_t dec_part_cap = 0;
+  // device address of this GPU's copy of the fixed scratch array used by
+  // lgs_decoder_l1_noalloc
+  float* scratch = nullptr;
 };
+
+// Partial sums of lgs_decoder_l1_noalloc: a fixed device array instead of an
+// allocation, sized for kScratchGroups work-groups of the widest decoder
+// (C = 512: 17 C + 1 floats rounded up to 64, 8768 floats = 35 KB each),
+// 8.98 MB in all.  Every GPU the library runs on holds its own copy until
+// the process ends; host code reaches it only through the address that
+// hipGetSymbolAddress returns for the current device (scratch_address).
+constexpr int kScratchGroups = 256;
+constexpr int64_t kScratchStride = ((17 * 512 + 1 + 63) / 64) * 64;
+constexpr int64_t kScratchFloats = (int64_t)kScratchGroups * kScratchStride;
+static __device__ __align__(256) float scratch[kScratchFloats];
 
 namespace {
 
@@ -811,6 +826,21 @@ lgs_settings lgs_default_settings(void) {
   return s;
 }
 
+// Device address of the scratch array on `device` (which must be current),
+// looked up once per device and kept for the life of the process; null when
+// the lookup fails.
+static float* scratch_address(int device) {
+  static std::mutex mu;
+  static std::map<int, float*> table;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = table.find(device);
+  if (it != table.end()) return it->second;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+  table[device] = (float*)p;
+  return (float*)p;
+}
+
 lgs_status lgs_context_create(int hip_device, lgs_context** out) {
   if (!out) return LGS_ERR_INVALID_ARG;
   *out = nullptr;
@@ -818,8 +848,11 @@ lgs_status lgs_context_create(int hip_device, lgs_context** out) {
   if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return LGS_ERR_HIP;
   if (hip_device < 0 || hip_device >= count) return LGS_ERR_INVALID_ARG;
   if (hipSetDevice(hip_device) != hipSuccess) return LGS_ERR_HIP;
+  float* sp = scratch_address(hip_device);
+  if (!sp) return LGS_ERR_HIP;
   lgs_context* c = new lgs_context();
   c->device = hip_device;
+  c->scratch = sp;
   *out = c;
   return LGS_OK;
 }
@@ -1031,12 +1064,11 @@ lgs_status lgs_loss(lgs_context* ctx, int32_t n_views, const lgs_camera* cams, i
   return LGS_OK;
 }
 
-lgs_status lgs_decoder_l1(lgs_context* ctx, int32_t width, int32_t height, int32_t out_dim, const float* feat,
-                          const float* weight, const float* bias, const void* target, lgs_dtype target_dtype,
-                          float w_feat, float* grad_feat, float* grad_weight, float* grad_bias, float* loss,
-                          hipStream_t stream) {
-  if (!ctx) return LGS_ERR_INVALID_ARG;
-  ctx->err.clear();
+// Validation and launch arguments shared by the two decoder entry points.
+static lgs_status decoder_args(lgs_context* ctx, int32_t width, int32_t height, int32_t out_dim, const float* feat,
+                               const float* weight, const float* bias, const void* target, lgs_dtype target_dtype,
+                               float w_feat, float* grad_feat, float* grad_weight, float* grad_bias, float* loss,
+                               DecArgs* a) {
   if (width < 1 || height < 1) return fail(ctx, LGS_ERR_INVALID_ARG, "width and height must be >= 1");
   const int64_t n = (int64_t)width * height;
   if (n > ((int64_t)1 << 31)) return fail(ctx, LGS_ERR_UNSUPPORTED, "more than 2^31 pixels");
@@ -1050,11 +1082,30 @@ lgs_status lgs_decoder_l1(lgs_context* ctx, int32_t width, int32_t height, int32
       !aligned4(grad_bias) || (loss && !aligned4(loss)) ||
       ((uintptr_t)target & (target_dtype == LGS_BF16 ? 1u : 3u)) != 0)
     return fail(ctx, LGS_ERR_INVALID_ARG, "misaligned array");
+  a->feat = feat; a->weight = weight; a->bias = bias;
+  a->grad_feat = grad_feat; a->grad_weight = grad_weight; a->grad_bias = grad_bias; a->loss = loss;
+  a->n = n;
+  a->part_stride = ((17 * (int64_t)out_dim + 1 + 63) / 64) * 64;
+  a->C = out_dim;
+  a->vec = n % 8 == 0 && ((uintptr_t)target & 15u) == 0;
+  a->scale = (float)((double)w_feat / ((double)out_dim * (double)n));
+  return LGS_OK;
+}
+
+lgs_status lgs_decoder_l1(lgs_context* ctx, int32_t width, int32_t height, int32_t out_dim, const float* feat,
+                          const float* weight, const float* bias, const void* target, lgs_dtype target_dtype,
+                          float w_feat, float* grad_feat, float* grad_weight, float* grad_bias, float* loss,
+                          hipStream_t stream) {
+  if (!ctx) return LGS_ERR_INVALID_ARG;
+  ctx->err.clear();
+  DecArgs a;
+  lgs_status rc = decoder_args(ctx, width, height, out_dim, feat, weight, bias, target, target_dtype, w_feat,
+                               grad_feat, grad_weight, grad_bias, loss, &a);
+  if (rc != LGS_OK) return rc;
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   (void)hipGetLastError();   // launch checks below see only this call's errors
-  const int grid = decoder_grid(n);
-  const int64_t stride = ((17 * (int64_t)out_dim + 1 + 63) / 64) * 64;
-  const int64_t need = (int64_t)grid * stride;
+  const int grid = decoder_grid(a.n);
+  const int64_t need = (int64_t)grid * a.part_stride;
   if (need > ctx->dec_part_cap) {
     HIP_TRY(ctx, hipDeviceSynchronize());   // earlier calls may still use the old buffer
     if (ctx->dec_part) hipFree(ctx->dec_part);
@@ -1063,15 +1114,33 @@ lgs_status lgs_decoder_l1(lgs_context* ctx, int32_t width, int32_t height, int32
     HIP_TRY(ctx, hipMalloc((void**)&ctx->dec_part, sizeof(float) * need));
     ctx->dec_part_cap = need;
   }
-  DecArgs a;
-  a.feat = feat; a.weight = weight; a.bias = bias;
-  a.grad_feat = grad_feat; a.grad_weight = grad_weight; a.grad_bias = grad_bias; a.loss = loss;
-  a.n = n;
-  a.part_stride = stride;
-  a.C = out_dim;
-  a.vec = n % 8 == 0 && ((uintptr_t)target & 15u) == 0;
-  a.scale = (float)((double)w_feat / ((double)out_dim * (double)n));
   launch_decoder(a, target, target_dtype == LGS_BF16, ctx->dec_part, grid, stream);
+  HIP_TRY(ctx, hipGetLastError());
+  return LGS_OK;
+}
+
+lgs_status lgs_decoder_l1_noalloc(lgs_context* ctx, int32_t width, int32_t height, int32_t out_dim,
+                                  const float* feat, const float* weight, const float* bias, const void* target,
+                                  lgs_dtype target_dtype, float w_feat, float* grad_feat, float* grad_weight,
+                                  float* grad_bias, float* loss, hipStream_t stream) {
+  if (!ctx) return LGS_ERR_INVALID_ARG;
+  ctx->err.clear();
+  DecArgs a;
+  lgs_status rc = decoder_args(ctx, width, height, out_dim, feat, weight, bias, target, target_dtype, w_feat,
+                               grad_feat, grad_weight, grad_bias, loss, &a);
+  if (rc != LGS_OK) return rc;
+  if (!ctx->scratch) return fail(ctx, LGS_ERR_STATE, "no scratch address for this context's device");
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  (void)hipGetLastError();   // launch checks below see only this call's errors
+  const int grid = std::min(decoder_grid(a.n), kScratchGroups);
+  const int64_t need = (int64_t)grid * a.part_stride;
+  if (need > kScratchFloats)
+    return fail(ctx, LGS_ERR_CAPACITY, "decoder partial sums need " + std::to_string(need) +
+                                           " floats, more than the fixed scratch array's " +
+                                           std::to_string(kScratchFloats));
+  // every work-group writes its whole partial row before the reduction
+  // reads it, so nothing left by an earlier call needs clearing
+  launch_decoder(a, target, target_dtype == LGS_BF16, ctx->scratch, grid, stream);
   HIP_TRY(ctx, hipGetLastError());
   return LGS_OK;
 }
