@@ -86,7 +86,11 @@ typedef struct {
   float cutoff2;    /* 9.0     largest m2 that contributes */
   int32_t tile;     /* 16      binning tile side: 8, 16 or 32 */
   int32_t chunk;    /* 4       8x8 pixel blocks per work-group (1, 2, 4, 8) */
-  int32_t order;    /* 0       1: work queue in descending list length, 0: raster order */
+  int32_t order;    /* 0       work order of the compositing kernels' per-XCD queues:
+                     *         0 raster order, neighbouring tiles on different XCDs;
+                     *         1 descending tile-list length; 2 descending list length
+                     *         with each 128 x 128-px region on one XCD (the tiles
+                     *         of a region share that XCD's L2) */
   int32_t profile;  /* 0       bit LGS_PROFILE_EVENTS: record HIP events around each
                      *         stage (lgs_state_stage_ms, lgs_graph_stage_ms);
                      *         bit LGS_PROFILE_COUNTS: run the compositing kernels'

@@ -251,39 +251,26 @@ __global__ void k_set_overflow(Counters* cnt, uint64_t cap_pairs, uint64_t cap_s
 constexpr int kOrderThreads = 1024;
 constexpr int kOrderBins = kQueues * 256;
 
-__device__ __forceinline__ uint32_t item_key(const ViewDesc* __restrict__ views, const uint2* __restrict__ ranges,
-                                             int tile_shift, uint32_t it) {
-  const uint32_t bx = it & 255u, by = (it >> 8) & 255u, v = it >> 16;
-  const ViewDesc& V = views[v];
-  const uint32_t t = (uint32_t)V.tile_off + (by >> tile_shift) * (uint32_t)V.tiles_x + (bx >> tile_shift);
-  const uint2 r = ranges[t];
+__device__ __forceinline__ uint32_t tile_key(const uint2* __restrict__ ranges, const TileItems& T) {
+  const uint2 r = ranges[T.tile];
   const uint32_t bucket = min(255u, (uint32_t)(4.f * sqrtf((float)(r.y - r.x))));
-  return (tile_queue(t) << 8) | (255u - bucket);
+  return (T.queue << 8) | (255u - bucket);
 }
 
-__global__ void __launch_bounds__(kOrderThreads) k_order_items(const ViewDesc* __restrict__ views,
-                                                             const uint2* __restrict__ ranges, int tile_shift,
-                                                             const uint32_t* __restrict__ items, int64_t n_items,
+// One work-group: a counting sort of the tiles by (queue, descending list
+// length bucket); each tile's blocks are copied as a run, so they stay
+// together in the output and are taken up by the queue's waves side by side.
+__global__ void __launch_bounds__(kOrderThreads) k_order_items(const uint2* __restrict__ ranges,
+                                                             const uint32_t* __restrict__ items,
+                                                             const TileItems* __restrict__ tiles, int64_t n_tiles,
                                                              uint32_t* __restrict__ out) {
   __shared__ uint32_t hist[kOrderBins];
   __shared__ uint32_t wsum[kOrderThreads / 64];
   for (int i = threadIdx.x; i < kOrderBins; i += kOrderThreads) hist[i] = 0u;
   __syncthreads();
-  // keys are computed 8 items at a time per thread, without branches (an
-  // index past the end reads the last item and is dropped afterwards), so
-  // that the 8 chains of dependent loads (item, view, tile range) are in
-  // flight together
-  constexpr int kU = 8;
-  for (int64_t b = threadIdx.x; b < n_items; b += (int64_t)kOrderThreads * kU) {
-    uint32_t key[kU];
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int64_t i = b + (int64_t)u * kOrderThreads;
-      key[u] = item_key(views, ranges, tile_shift, items[i < n_items ? i : n_items - 1]);
-    }
-#pragma unroll
-    for (int u = 0; u < kU; ++u)
-      if (b + (int64_t)u * kOrderThreads < n_items) atomicAdd(&hist[key[u]], 1u);
+  for (int64_t i = threadIdx.x; i < n_tiles; i += kOrderThreads) {
+    const TileItems T = tiles[i];
+    atomicAdd(&hist[tile_key(ranges, T)], T.count);
   }
   __syncthreads();
   // exclusive scan of the bins, two per thread
@@ -302,17 +289,10 @@ __global__ void __launch_bounds__(kOrderThreads) k_order_items(const ViewDesc* _
   hist[2 * threadIdx.x] = ex;
   hist[2 * threadIdx.x + 1] = ex + a;
   __syncthreads();
-  for (int64_t b = threadIdx.x; b < n_items; b += (int64_t)kOrderThreads * kU) {
-    uint32_t it[kU], key[kU];
-#pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int64_t i = b + (int64_t)u * kOrderThreads;
-      it[u] = items[i < n_items ? i : n_items - 1];
-      key[u] = item_key(views, ranges, tile_shift, it[u]);
-    }
-#pragma unroll
-    for (int u = 0; u < kU; ++u)
-      if (b + (int64_t)u * kOrderThreads < n_items) out[atomicAdd(&hist[key[u]], 1u)] = it[u];
+  for (int64_t i = threadIdx.x; i < n_tiles; i += kOrderThreads) {
+    const TileItems T = tiles[i];
+    const uint32_t pos = atomicAdd(&hist[tile_key(ranges, T)], T.count);
+    for (uint32_t k = 0; k < T.count; ++k) out[pos + k] = items[T.first + k];
   }
 }
 
@@ -385,11 +365,10 @@ void launch_set_overflow(Counters* cnt, uint64_t cap_pairs, uint64_t cap_slots, 
   hipLaunchKernelGGL(k_set_overflow, dim3(1), dim3(64), 0, s, cnt, cap_pairs, cap_slots);
 }
 
-uint32_t* launch_order_items(const ViewDesc* views, const uint2* ranges, int tile_shift, const uint32_t* items,
-                             int64_t n_items, uint32_t* out, hipStream_t s) {
-  if (n_items <= 0) return out;
-  hipLaunchKernelGGL(k_order_items, dim3(1), dim3(kOrderThreads), 0, s, views, ranges, tile_shift, items, n_items,
-                     out);
+uint32_t* launch_order_items(const uint2* ranges, const uint32_t* items, const TileItems* tiles, int64_t n_tiles,
+                             uint32_t* out, hipStream_t s) {
+  if (n_tiles <= 0) return out;
+  hipLaunchKernelGGL(k_order_items, dim3(1), dim3(kOrderThreads), 0, s, ranges, items, tiles, n_tiles, out);
   return out;
 }
 

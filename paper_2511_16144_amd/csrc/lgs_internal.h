@@ -117,8 +117,22 @@ struct __attribute__((aligned(128))) Counters {
 };
 static_assert(offsetof(Counters, work_q) % 128 == 0, "queue counters must start on a 128-byte line");
 
-// Queue of the items of binning tile t (global tile index).
+// Queue of the items of binning tile t (global tile index) in the raster
+// and list-length orders (settings.order 0 and 1): neighbouring tiles go to
+// different XCDs.
 __host__ __device__ inline uint32_t tile_queue(uint32_t t) { return LGS_XCD_QUEUES ? (t % kQueues) : 0u; }
+// Spatial order (settings.order 2): the views are cut into super-tiles of
+// kSuperPx x kSuperPx pixels and each super-tile goes to one queue (a
+// lattice over (super-tile x, y, view), so that neighbouring super-tiles go
+// to different XCDs); inside a queue items run in descending tile-list
+// length as in order 1.  The tiles of one region then share their XCD's L2
+// for the records of the Gaussians they have in common.
+constexpr int kSuperPx = 128;
+__host__ __device__ inline uint32_t super_queue(uint32_t v, uint32_t bx, uint32_t by) {
+  constexpr uint32_t sh = 4;   // log2(kSuperPx / 8): 8x8 blocks per super-tile side
+  static_assert((8u << sh) == (uint32_t)kSuperPx, "super-tile side");
+  return LGS_XCD_QUEUES ? (((bx >> sh) + 3u * (by >> sh) + 5u * v) % (uint32_t)kQueues) : 0u;
+}
 
 // ---------------------------------------------------------------------------
 // launchers (each defined next to its kernels)
@@ -168,11 +182,17 @@ void radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t
                     const uint32_t* n_dev, int64_t n_max, int begin_bit, int end_bit,
                     void* temp, hipStream_t s, bool* result_in_alt);
 
-// work queue ordering (blocks by descending tile-list length)
-// work items grouped by queue, each queue by descending length of the tile's
-// list (counting sort on coarse length buckets); returns out
-uint32_t* launch_order_items(const ViewDesc* views, const uint2* ranges, int tile_shift,
-                             const uint32_t* items, int64_t n_items, uint32_t* out, hipStream_t s);
+// work queue ordering (blocks by descending tile-list length): each queue's
+// tiles re-sorted by the length of their list (counting sort on coarse
+// length buckets), a tile's blocks kept together; returns out
+struct TileItems {
+  uint32_t first;   // index of the tile's first item in the static table
+  uint32_t count;   // its blocks (items)
+  uint32_t tile;    // global tile id
+  uint32_t queue;
+};
+uint32_t* launch_order_items(const uint2* ranges, const uint32_t* items, const TileItems* tiles, int64_t n_tiles,
+                             uint32_t* out, hipStream_t s);
 
 // compositing
 void launch_raster_fwd(const Settings& st, const ViewDesc* views, const ViewImages* out,

@@ -264,9 +264,9 @@ __global__ void __launch_bounds__(256) k_project_bwd(
     const float* __restrict__ grad2d, float* __restrict__ g_means, float* __restrict__ g_ls,
     float* __restrict__ g_q, float* __restrict__ g_logit, float* __restrict__ g_rgb,
     float* __restrict__ g_feat, double* __restrict__ twist_part) {
-  __shared__ double red[4][6];
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool active = g < n;
+  const uint32_t wave_id = (uint32_t)(g >> 6), n_waves = gridDim.x * (blockDim.x >> 6);
   double p[3] = {0, 0, 0}, ls[3] = {0, 0, 0}, q[4] = {1, 0, 0, 0}, logit = 0.0;
   if (active) {
     for (int k = 0; k < 3; ++k) p[k] = means[k * n + g];
@@ -293,7 +293,7 @@ __global__ void __launch_bounds__(256) k_project_bwd(
   double gp[3] = {0, 0, 0}, gM[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, glogit = 0.0;
   float gy[20];
   for (int k = 0; k < 20; ++k) gy[k] = 0.f;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
   uint32_t cix[kVB];   // record index of views v0 .. v0 + 7 (~0 where not visible)
   for (int v = 0; v < n_views; ++v) {
     if ((v & (kVB - 1)) == 0) {
@@ -390,17 +390,19 @@ __global__ void __launch_bounds__(256) k_project_bwd(
       glogit += (double)G[5] * P.o * (1.0 - P.o);
       for (int k = 0; k < 20; ++k) gy[k] += G[6 + k];
     }
-    // per-view twist: block reduction, fixed order
-    for (int k = 0; k < 6; ++k) {
-      double s = wave_sum_d(tw[k]);
-      if (lane == 0) red[wave][k] = s;
+    // per-view twist: this wave's sum (fixed order), one partial per wave and
+    // (view, component), stored component-major so that the final sum reads
+    // them contiguously; no work-group barrier; a view no lane of the wave
+    // sees adds 0
+    double* tp = twist_part + (size_t)v * 6 * n_waves + wave_id;
+    if (__builtin_amdgcn_ballot_w64(ci != ~0u) != 0ull) {
+      for (int k = 0; k < 6; ++k) {
+        const double s = wave_sum_d(tw[k]);
+        if (lane == 0) tp[(size_t)k * n_waves] = s;
+      }
+    } else if (lane < 6) {
+      tp[(size_t)lane * n_waves] = 0.0;
     }
-    __syncthreads();
-    if (threadIdx.x < 6) {
-      double s = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
-      twist_part[((size_t)blockIdx.x * n_views + v) * 6 + threadIdx.x] = s;
-    }
-    __syncthreads();
   }
   if (!active) return;
   // M = R diag(s) -> s, R -> qh -> q
@@ -514,14 +516,15 @@ __global__ void __launch_bounds__(256) k_group_feat_grad(int n_views, int64_t n,
     if (k < nfeat) g_feat_g[k * n + g] = acc[k];
 }
 
-// twist[v][k] = sum over the projection-backward blocks of their partial sums;
-// one workgroup per (view, component), fixed summation order.
-__global__ void __launch_bounds__(256) k_twist_final(const double* __restrict__ part, int n_blocks,
+// twist[v][k] = sum over the projection-backward waves of their partial sums
+// (stored [v][k][wave]); one workgroup per (view, component), fixed
+// summation order.
+__global__ void __launch_bounds__(256) k_twist_final(const double* __restrict__ part, int n_waves,
                                                     int n_views, float* __restrict__ twist) {
   __shared__ double red[256];
   const int idx = blockIdx.x;   // v * 6 + k
   double s = 0.0;
-  for (int b = threadIdx.x; b < n_blocks; b += 256) s += part[(size_t)b * n_views * 6 + idx];
+  for (int b = threadIdx.x; b < n_waves; b += 256) s += part[(size_t)idx * n_waves + b];
   red[threadIdx.x] = s;
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
@@ -576,8 +579,8 @@ void launch_group_feat_grad(int n_views, int64_t n, uint32_t npad_shift, const C
 }
 
 size_t twist_temp_bytes(int64_t n, int n_views) {
-  const int64_t blocks = (n + 255) / 256;
-  return (size_t)(blocks > 0 ? blocks : 1) * n_views * 6 * sizeof(double);
+  const int64_t waves = 4 * ((n + 255) / 256);   // every wave of the launch writes its partials
+  return (size_t)(waves > 0 ? waves : 1) * n_views * 6 * sizeof(double);
 }
 
 void launch_project_bwd(const Settings& st, const ViewDesc* views, int n_views, const float* means,
@@ -591,7 +594,7 @@ void launch_project_bwd(const Settings& st, const ViewDesc* views, int n_views, 
                        log_scales, quats, logits, n, npad_shift, cnt, cnt_t, cidx, grad2d, g_means, g_ls,
                        g_q, g_logit, g_rgb, g_feat, (double*)temp);
   if (twist)   // with no Gaussian block the sum is empty and the kernel writes zeros
-    hipLaunchKernelGGL(k_twist_final, dim3(n_views * 6), dim3(256), 0, s, (const double*)temp, blocks,
+    hipLaunchKernelGGL(k_twist_final, dim3(n_views * 6), dim3(256), 0, s, (const double*)temp, 4 * blocks,
                        n_views, twist);
 }
 

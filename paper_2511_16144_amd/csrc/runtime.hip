@@ -154,7 +154,7 @@ lgs_status check_settings(lgs_context* ctx, const lgs_settings* st) {
     return fail(ctx, LGS_ERR_INVALID_ARG, "tile must be 8, 16 or 32");
   if (st->chunk != 1 && st->chunk != 2 && st->chunk != 4 && st->chunk != 8)
     return fail(ctx, LGS_ERR_INVALID_ARG, "chunk must be 1, 2, 4 or 8");
-  if (st->order != 0 && st->order != 1) return fail(ctx, LGS_ERR_INVALID_ARG, "order must be 0 or 1");
+  if (st->order < 0 || st->order > 2) return fail(ctx, LGS_ERR_INVALID_ARG, "order must be 0, 1 or 2");
   if (st->profile & ~(LGS_PROFILE_EVENTS | LGS_PROFILE_COUNTS))
     return fail(ctx, LGS_ERR_INVALID_ARG, "profile takes the bits LGS_PROFILE_EVENTS | LGS_PROFILE_COUNTS");
   if (!(st->z_near > 0.f) || !(st->eps2d >= 0.f) || !(st->fov_clamp > 0.f) ||
@@ -259,27 +259,38 @@ Plan make_plan(const lgs_settings* st, int32_t n_views, const lgs_camera* cams) 
   return P;
 }
 
-// Work items (8x8 blocks) grouped by queue (tile_queue of the block's tile),
-// tile by tile inside a queue, raster order inside a tile; the kQueues + 1
-// queue offsets follow the items.
-std::vector<uint32_t> make_items(const Plan& P, int tile) {
+// Work items (8x8 blocks) grouped by queue, tile by tile inside a queue,
+// raster order inside a tile.  A tile's queue: tile_queue of its global
+// index (orders 0 and 1) or super_queue of its region (order 2).  Layout of
+// the table: the n_items items, the kQueues + 1 queue offsets, then one
+// TileItems record per tile in the same order (its first item, block count,
+// global tile id and queue), from which k_order_items re-sorts each queue
+// by list length, tile by tile (orders 1 and 2), keeping the queue sizes.
+std::vector<uint32_t> make_items(const Plan& P, int tile, bool spatial) {
   std::vector<std::vector<uint32_t>> qs(kQueues);
+  std::vector<std::vector<TileItems>> qt(kQueues);
   const int bpt = tile / kBlock;
   for (size_t v = 0; v < P.views.size(); ++v) {
     const ViewDesc& d = P.views[v];
     for (int ty = 0; ty < d.tiles_y; ++ty)
       for (int tx = 0; tx < d.tiles_x; ++tx) {
-        auto& q = qs[tile_queue((uint32_t)(d.tile_off + ty * d.tiles_x + tx))];
+        const uint32_t t = (uint32_t)(d.tile_off + ty * d.tiles_x + tx);
+        const uint32_t q = spatial ? super_queue((uint32_t)v, (uint32_t)(tx * bpt), (uint32_t)(ty * bpt))
+                                   : tile_queue(t);
+        TileItems ti{(uint32_t)qs[q].size(), 0u, t, q};
         for (int j = 0; j < bpt; ++j)
           for (int i = 0; i < bpt; ++i) {
             const int bx = tx * bpt + i, by = ty * bpt + j;
-            if (bx < d.blocks_x && by < d.blocks_y)
-              q.push_back((uint32_t)bx | ((uint32_t)by << 8) | ((uint32_t)v << 16));
+            if (bx < d.blocks_x && by < d.blocks_y) {
+              qs[q].push_back((uint32_t)bx | ((uint32_t)by << 8) | ((uint32_t)v << 16));
+              ++ti.count;
+            }
           }
+        qt[q].push_back(ti);
       }
   }
   std::vector<uint32_t> items;
-  items.reserve(P.n_items + kQueues + 1);
+  items.reserve(P.n_items + kQueues + 1 + 4 * P.n_tiles);
   std::vector<uint32_t> off(kQueues + 1, 0u);
   for (int q = 0; q < kQueues; ++q) {
     off[q] = (uint32_t)items.size();
@@ -287,6 +298,13 @@ std::vector<uint32_t> make_items(const Plan& P, int tile) {
   }
   off[kQueues] = (uint32_t)items.size();
   items.insert(items.end(), off.begin(), off.end());
+  for (int q = 0; q < kQueues; ++q)
+    for (const TileItems& ti : qt[q]) {
+      items.push_back(off[q] + ti.first);
+      items.push_back(ti.count);
+      items.push_back(ti.tile);
+      items.push_back(ti.queue);
+    }
   return items;
 }
 
@@ -474,17 +492,18 @@ void w_mark(Work* W, int i, hipStream_t s) {
   if (W->ev[i]) hipEventRecord(W->ev[i], s);
 }
 
-uint32_t* get_items(lgs_context* ctx, const Plan& P, int tile) {
-  auto it = ctx->items_cache.find(P.sig);
+uint32_t* get_items(lgs_context* ctx, const Plan& P, int tile, bool spatial) {
+  const std::string key = P.sig + (spatial ? "s" : "r");
+  auto it = ctx->items_cache.find(key);
   if (it != ctx->items_cache.end()) return it->second.first;
-  std::vector<uint32_t> items = make_items(P, tile);
+  std::vector<uint32_t> items = make_items(P, tile, spatial);
   uint32_t* d = nullptr;
   if (hipMalloc(&d, std::max<size_t>(4, items.size() * 4)) != hipSuccess) return nullptr;
   if (!items.empty() && hipMemcpy(d, items.data(), items.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
     hipFree(d);
     return nullptr;
   }
-  ctx->items_cache[P.sig] = {d, (int64_t)items.size()};
+  ctx->items_cache[key] = {d, (int64_t)items.size()};
   return d;
 }
 
@@ -546,7 +565,7 @@ lgs_status w_alloc_front(Work* W) {
   W->ranges = (uint2*)w_alloc(W, 8 * std::max<int64_t>(W->plan.n_tiles, 1), ok);
   const int64_t ni = std::max<int64_t>(W->plan.n_items, 1);
   W->ii_a = (uint32_t*)w_alloc(W, 4 * ni, ok);
-  W->items_static = get_items(W->ctx, W->plan, W->st.tile);
+  W->items_static = get_items(W->ctx, W->plan, W->st.tile, W->st.order == 2);
   if (!ok || !W->items_static) return fail(W->ctx, LGS_ERR_HIP, "device allocation failed");
   return LGS_OK;
 }
@@ -675,8 +694,10 @@ void enqueue_pairs(Work* W, hipStream_t s) {
   W->pkeys = alt ? W->k1 : W->k0;
   W->pvals = alt ? W->v1 : W->v0;
   launch_tile_ranges(W->pkeys, W->counters, W->cap_pairs, W->ranges, s);
-  if (W->st.order == 1)
-    W->items = launch_order_items(W->d_views, W->ranges, P.tile_shift, W->items_static, P.n_items, W->ii_a, s);
+  if (W->st.order != 0)
+    W->items = launch_order_items(W->ranges, W->items_static,
+                                  (const TileItems*)(W->items_static + P.n_items + kQueues + 1), P.n_tiles,
+                                  W->ii_a, s);
   else
     W->items = W->items_static;
 }
@@ -1541,9 +1562,9 @@ lgs_status lgs_autotune(lgs_context* ctx, const lgs_settings* st, const lgs_gaus
     return fail(ctx, LGS_ERR_HIP, "event creation failed");
   }
   double best_ms = 1e30;
-  const int tiles[3] = {32, 16, 8}, orders[2] = {1, 0}, chunks[3] = {4, 2, 1};
+  const int tiles[3] = {32, 16, 8}, orders[3] = {2, 1, 0}, chunks[3] = {4, 2, 1};
   for (int ti = 0; ti < 3; ++ti)
-    for (int oi = 0; oi < 2; ++oi)
+    for (int oi = 0; oi < 3; ++oi)
       for (int ci = 0; ci < 3; ++ci) {
         lgs_settings s = *st;
         s.tile = tiles[ti]; s.chunk = chunks[ci]; s.order = orders[oi]; s.profile = 0;

@@ -18,7 +18,7 @@ setting the autotuner returns; plus tunable invariance of the BF16 path.
   oracle's rendered values.  The oracle only evaluates the windows, with the
   workload's targets: none of its inputs comes from the GPU;
 * reduced batched BF16 scene: forward bitwise identical and gradients within
-  1e-5 across tile {8, 16, 32} x chunk {1, 2, 4} x order {0, 1}.
+  1e-5 across tile {8, 16, 32} x chunk {1, 2, 4} x order {0, 1, 2}.
 """
 import ctypes as C
 
@@ -222,7 +222,7 @@ def test_bf16_tunable_invariance(ctx):
     worst = 0.0
     for tile in (8, 16, 32):
         for chunk in (1, 2, 4):
-            for order in (0, 1):
+            for order in (0, 1, 2):
                 st = P.Settings(tile=tile, chunk=chunk, order=order)
                 outs, state = ctx.forward(prm, wl.cams, st, want_n=True)
                 g = grads_np(ctx.backward(state, prm, ups))

@@ -32,10 +32,10 @@ def ctx():
     c.close()
 
 
-def run_fwd(ctx, wl, tile=16, chunk=4, want_n=True):
+def run_fwd(ctx, wl, tile=16, chunk=4, want_n=True, order=0):
     import paper_2511_16144_amd as P
     prm = gpu_params(wl.scene)
-    st = P.Settings(tile=tile, chunk=chunk)
+    st = P.Settings(tile=tile, chunk=chunk, order=order)
     outs, state = ctx.forward(prm, wl.cams, st, want_n=want_n)
     torch.cuda.synchronize()
     return prm, to_np(outs), state
@@ -66,10 +66,10 @@ def test_c1_forward_parity(ctx, c1, tile):
 
 def test_c1_tile_invariance_bitwise(ctx, c1):
     wl, _ = c1
-    say("[case] C1 tile invariance 8/16/32 and chunk 1/4")
+    say("[case] C1 tile invariance 8/16/32, chunk 1/2/4, order 0/1/2")
     res = []
-    for tile, chunk in [(8, 1), (16, 4), (32, 2), (16, 1)]:
-        _, out, state = run_fwd(ctx, wl, tile=tile, chunk=chunk)
+    for tile, chunk, order in [(8, 1, 0), (16, 4, 0), (32, 2, 0), (16, 1, 0), (32, 4, 1), (32, 4, 2), (8, 2, 2)]:
+        _, out, state = run_fwd(ctx, wl, tile=tile, chunk=chunk, order=order)
         state.release()
         res.append(out[0])
     for o in res[1:]:
