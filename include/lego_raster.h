@@ -57,10 +57,15 @@ typedef enum {
   LGS_ERR_HIP = 2,          /* a HIP runtime call failed */
   LGS_ERR_CAPACITY = 3,     /* pair buffer too small (graph mode) */
   LGS_ERR_UNSUPPORTED = 4,  /* valid but not supported by this build */
-  LGS_ERR_STATE = 5         /* object used in the wrong state */
+  LGS_ERR_STATE = 5,        /* object used in the wrong state */
+  LGS_STATUS_INT32 = 0x7fffffff  /* not a status: makes every int32 a value of the type */
 } lgs_status;
 
-typedef enum { LGS_F32 = 0, LGS_BF16 = 1 } lgs_dtype;
+typedef enum {
+  LGS_F32 = 0,
+  LGS_BF16 = 1,
+  LGS_DTYPE_INT32 = 0x7fffffff  /* not a dtype: makes every int32 a value of the type */
+} lgs_dtype;
 
 /* Bits of lgs_settings.profile. */
 enum { LGS_PROFILE_EVENTS = 1, LGS_PROFILE_COUNTS = 2 };

@@ -833,6 +833,7 @@ const char* lgs_status_string(lgs_status s) {
     case LGS_ERR_CAPACITY: return "LGS_ERR_CAPACITY";
     case LGS_ERR_UNSUPPORTED: return "LGS_ERR_UNSUPPORTED";
     case LGS_ERR_STATE: return "LGS_ERR_STATE";
+    default: break;
   }
   return "LGS_ERR_UNKNOWN";
 }
