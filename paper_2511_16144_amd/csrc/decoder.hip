@@ -11,7 +11,7 @@
 // split into two BF16 terms (x = x_hi + x_lo, 16 significant bits); R is
 // -1, 0 or 1, exact in BF16.  Z^T = F^T W^T takes the two splits in one
 // instruction pair: A = [F_hi | F_lo] (K = 32) against B = [W_hi ; W_hi], then
-// A against [W_lo ; 0], i.e. F_hi W_hi + F_lo W_hi + F_hi W_lo.
+// A against [W_lo ; W_lo], i.e. all four products of the split operands.
 //
 // Work-group = 8 waves (two per SIMD: one wave's target loads overlap the
 // other's matrix products); a work-group walks a contiguous run of 32-pixel
@@ -27,6 +27,8 @@
 // kernel adds the work-groups' partials in a fixed order.
 #include "lgs_internal.h"
 
+#include <type_traits>
+
 namespace lgs {
 namespace {
 
@@ -37,6 +39,7 @@ typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 constexpr int kDecWaves = 8;
 constexpr int kDecThreads = 64 * kDecWaves;
 constexpr int kChunk = 32;            // pixels per chunk
+constexpr int kDecPF = 3;             // chunks whose inputs are in flight
 constexpr int kFA = 40;               // LDS pitch (u16) of the [pixel][k] F rows (80 B)
 constexpr int kFT = 40;               // LDS pitch (u16) of the [feature][pixel] F rows
 constexpr int kRC = 40;               // LDS pitch (u16) of the [channel][pixel] sign rows
@@ -109,10 +112,15 @@ __global__ __launch_bounds__(kDecThreads) void k_decoder(DecArgs a, const TT* __
   __shared__ __attribute__((aligned(16))) unsigned short fA[2][kChunk * kFA];     // [pixel][F_hi 16 | F_lo 16]
   __shared__ __attribute__((aligned(16))) unsigned short fT[2][2 * 16 * kFT];     // [hi/lo][feature][pixel]
   __shared__ __attribute__((aligned(16))) unsigned short rC[kDecWaves][Cw * kRC];      // [channel][pixel] signs
-  // [pixel][channel] signs; the row pitch is padded by 16 bytes so that the
-  // 2-byte sign stores of a wave's four lane groups (rows 8 apart) do not
-  // all fall on the same banks
+  // [pixel][channel] signs.  A wave's 2-byte sign stores hit four rows 8
+  // apart at once (one per lane group), and with 16-byte-aligned rows those
+  // always share banks, so each row's channels are rotated by 16 channels
+  // (32 bytes) per group of 8 rows: the four lane groups then fall on
+  // disjoint banks.  Readers take 8-channel runs, which the rotation keeps
+  // whole.
   constexpr int kRP = Cw + 8;
+  auto rp_col = [&](int row, int col) { return (col + 16 * ((row >> 3) & 3)) & (Cw - 1); };
+  static_assert((Cw & (Cw - 1)) == 0 && Cw >= 32, "rotation modulo a power-of-two channel count");
   __shared__ __attribute__((aligned(16))) unsigned short rP[kDecWaves][kChunk * kRP];
   __shared__ __attribute__((aligned(16))) float dfr[2][kDecWaves * 16 * kChunk];      // [wave][feature][pixel]
   __shared__ float red[kDecWaves];
@@ -129,7 +137,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decoder(DecArgs a, const TT* __
   for (int e = t; e < a.C * 16; e += kDecThreads) wl[e] = a.weight[e];
   __syncthreads();
   // this wave's operands of W, split hi/lo, in registers for the whole run
-  // Z^T B operand, tile nt: lane (k block q4, channel r16): [W_hi ; W_hi] and [W_lo ; 0]
+  // Z^T B operand, tile nt: lane (k block q4, channel r16): [W_hi ; W_hi] and [W_lo ; W_lo]
   bf16x8_t bz1[NT], bz2[NT];
   float bias[NT];
 #pragma unroll
@@ -142,7 +150,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decoder(DecArgs a, const TT* __
       const float x = wr[k];
       const unsigned short hi = to_bf16(x);
       h[k] = hi;
-      l[k] = q4 < 2 ? to_bf16(x - from_bf16(hi)) : (unsigned short)0;
+      l[k] = to_bf16(x - from_bf16(hi));
     }
     bz1[nt] = as_bf16x8(h);
     bz2[nt] = as_bf16x8(l);
@@ -174,26 +182,30 @@ __global__ __launch_bounds__(kDecThreads) void k_decoder(DecArgs a, const TT* __
   }
   float lsum = 0.f;
 
-  // The next chunk's targets and feature element are loaded into registers
-  // while the current chunk is processed, so the loads' latency overlaps
-  // the matrix products.
+  // The targets and feature element of the next kDecPF chunks are loaded
+  // into registers ahead of their use (kDecPF register sets, the chunk loop
+  // unrolled by kDecPF so that each set stays in the same registers), so the
+  // loads' latency overlaps the matrix products of the chunks before.  The
+  // depth is what the register file holds at two waves per SIMD without
+  // spilling: a chunk's targets take 4 NT registers in BF16, 8 NT in FP32.
+  constexpr int kDecPF = (sizeof(TT) == 2 ? 3 : 2) - (NT == 4 ? 1 : 0);
   typedef typename Raw8<TT>::type RawT;
-  RawT tr[NT];
-  float fr = 0.f;
+  RawT tr[kDecPF][NT];
+  float fr[kDecPF];
   static_assert(kDecThreads == 16 * kChunk, "one feature element per thread and chunk");
   const int fk = t >> 5, fpx = t & 31;
   // lane (q4, r16) of the Z^T products holds pixels 8 q4 .. 8 q4 + 7 of the
   // chunk (rows 4 q4 .. 4 q4 + 3 of column group cg are pixels 8 q4 + 4 cg
   // + i): its targets of one channel are one 16-byte load
-  auto fetch = [&](int64_t ck) {
+  auto fetch = [&](int64_t ck, RawT (&trs)[NT], float& frs) {
     const int64_t p0 = ck * kChunk;
     const bool full = p0 + kChunk <= n;
-    fr = p0 + fpx < n ? a.feat[(size_t)fk * n + p0 + fpx] : 0.f;
+    frs = p0 + fpx < n ? a.feat[(size_t)fk * n + p0 + fpx] : 0.f;
     const int64_t pp = p0 + 8 * q4;
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
       const TT* tp = target + (size_t)(c0 + 16 * nt + r16) * n + pp;
-      tr[nt] = load_raw8(tp, full && a.vec, n - pp);
+      trs[nt] = load_raw8(tp, full && a.vec, n - pp);
     }
   };
   // each work-group takes a contiguous run of chunks, so the two halves of
@@ -213,32 +225,32 @@ __global__ __launch_bounds__(kDecThreads) void k_decoder(DecArgs a, const TT* __
       if (q0 + px < n) a.grad_feat[(size_t)k * n + q0 + px] = a.scale * v;
     }
   };
-  if (ck0 < ck1) fetch(ck0);
-  for (int64_t ck = ck0; ck < ck1; ++ck) {
+  // one chunk; its inputs are in (cur, frc), which are refilled with chunk
+  // ck + kDecPF's as soon as they have been used
+  auto chunk = [&](int64_t ck, RawT (&cur)[NT], float& frc) {
     const int64_t p0 = ck * kChunk;
     const int par = (int)((ck - ck0) & 1);
     const unsigned short* fAc = fA[par];
     const unsigned short* fTc = fT[par];
     // (1) F chunk -> LDS: [pixel][F_hi | F_lo] and [hi/lo][feature][pixel]
     {
-      const unsigned short hi = to_bf16(fr), lo = to_bf16(fr - from_bf16(hi));
+      const unsigned short hi = to_bf16(frc), lo = to_bf16(frc - from_bf16(hi));
       fA[par][fpx * kFA + fk] = hi;
       fA[par][fpx * kFA + 16 + fk] = lo;
       fT[par][fk * kFT + fpx] = hi;
       fT[par][16 * kFT + fk * kFT + fpx] = lo;
     }
-    RawT cur[NT];
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) cur[nt] = tr[nt];
-    if (ck + 1 < ck1) fetch(ck + 1);
     // The one barrier of the chunk: the F rows of this chunk are complete, and
     // every wave has finished the previous chunk (its dF partials are in the
     // other buffer, and it no longer reads this buffer's F rows from two
     // chunks ago).  The sign rows are per wave and need no barrier.
     lds_barrier();
     if (ck > ck0) store_df(ck - 1, par ^ 1);
-    // (2) Z^T tiles, signs, loss, db; signs to LDS in both layouts
+    // (2) Z^T tiles, signs, loss, db; signs to LDS in both layouts (a
+    // chunk wholly inside the image skips the per-pixel validity tests)
     const int lim = n - p0 < kChunk ? (int)(n - p0) : kChunk;   // valid pixels of the chunk
+    auto signs = [&](auto full_tag) {
+      constexpr bool kFull = decltype(full_tag)::value;
 #pragma unroll
     for (int cg = 0; cg < 2; ++cg) {
       // A row r16 of column group cg is pixel 8 (r16 / 4) + 4 cg + r16 % 4
@@ -254,13 +266,13 @@ __global__ __launch_bounds__(kDecThreads) void k_decoder(DecArgs a, const TT* __
         unsigned short sg[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const bool valid = pl + i < lim;
+          const bool valid = kFull || pl + i < lim;
           const float d = z[i] - tv[i];
           const float s = !valid ? 0.f : (d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f));
           lsum += valid ? fabsf(d) : 0.f;
           db[nt] += s;
           sg[i] = (unsigned short)(__float_as_uint(s) >> 16);   // -1, 0, 1: exact in BF16
-          rP[w][(pl + i) * kRP + 16 * nt + r16] = sg[i];
+          rP[w][(pl + i) * kRP + rp_col(pl + i, 16 * nt + r16)] = sg[i];
         }
         uint2 packed;
         packed.x = (uint32_t)sg[0] | ((uint32_t)sg[1] << 16);
@@ -268,6 +280,10 @@ __global__ __launch_bounds__(kDecThreads) void k_decoder(DecArgs a, const TT* __
         *(uint2*)(&rC[w][(16 * nt + r16) * kRC + pl]) = packed;
       }
     }
+    };
+    if (lim == kChunk) signs(std::true_type());
+    else signs(std::false_type());
+    if (ck + kDecPF < ck1) fetch(ck + kDecPF, cur, frc);
     // (3) dW^T += F R^T over the chunk's 32 pixels (A = F hi/lo, B = signs)
     {
       const bf16x8_t fh = as_bf16x8(*(const u16x8*)(fTc + r16 * kFT + 8 * q4));
@@ -286,7 +302,8 @@ __global__ __launch_bounds__(kDecThreads) void k_decoder(DecArgs a, const TT* __
       dfa[cg] = (f32x4){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
-        const bf16x8_t rb = as_bf16x8(*(const u16x8*)(&rP[w][(16 * cg + r16) * kRP + 32 * ks + 8 * q4]));
+        const bf16x8_t rb =
+            as_bf16x8(*(const u16x8*)(&rP[w][(16 * cg + r16) * kRP + rp_col(16 * cg + r16, 32 * ks + 8 * q4)]));
         dfa[cg] = mfma(wt_h[ks], rb, dfa[cg]);
         dfa[cg] = mfma(wt_l[ks], rb, dfa[cg]);
       }
@@ -295,6 +312,14 @@ __global__ __launch_bounds__(kDecThreads) void k_decoder(DecArgs a, const TT* __
     for (int cg = 0; cg < 2; ++cg)
 #pragma unroll
       for (int i = 0; i < 4; ++i) dfr[par][(w * 16 + 4 * q4 + i) * kChunk + 16 * cg + r16] = dfa[cg][i];
+  };
+#pragma unroll
+  for (int d = 0; d < kDecPF; ++d)
+    if (ck0 + d < ck1) fetch(ck0 + d, tr[d], fr[d]);
+  for (int64_t cb = ck0; cb < ck1; cb += kDecPF) {
+#pragma unroll
+    for (int d = 0; d < kDecPF; ++d)
+      if (cb + d < ck1) chunk(cb + d, tr[d], fr[d]);
   }
   lds_barrier();
   if (ck1 > ck0) store_df(ck1 - 1, (int)((ck1 - 1 - ck0) & 1));
@@ -322,20 +347,26 @@ __global__ __launch_bounds__(kDecThreads) void k_decoder(DecArgs a, const TT* __
 }
 
 // dW, db and the loss: partials of every work-group added in a fixed order
-// (64 outputs per work-group; 4 threads per output take every 4th partial,
-// then their sums are added in a fixed order).
-__global__ __launch_bounds__(256) void k_decoder_reduce(DecArgs a, const float* __restrict__ part, int n_parts) {
-  __shared__ double red[4][64];
+// (64 outputs per work-group; kRedGroups threads per output take every
+// kRedGroups-th partial, so a thread has at most ceil(n_parts / kRedGroups)
+// independent loads in flight, then their FP64 sums are added in a fixed
+// order).
+constexpr int kRedGroups = 16;
+__global__ __launch_bounds__(64 * kRedGroups) void k_decoder_reduce(DecArgs a, const float* __restrict__ part,
+                                                                   int n_parts) {
+  __shared__ double red[kRedGroups][64];
   const int o = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int64_t i = (int64_t)blockIdx.x * 64 + o;
   const int64_t m = (int64_t)a.C * 17 + 1;
   double s = 0.0;
   if (i < m)
-    for (int b = g; b < n_parts; b += 4) s += (double)part[(size_t)b * a.part_stride + i];
+    for (int b = g; b < n_parts; b += kRedGroups) s += (double)part[(size_t)b * a.part_stride + i];
   red[g][o] = s;
   __syncthreads();
   if (g != 0 || i >= m) return;
-  s = (red[0][o] + red[1][o]) + (red[2][o] + red[3][o]);
+  s = 0.0;
+#pragma unroll
+  for (int u = 0; u < kRedGroups; ++u) s += red[u][o];
   if (i < (int64_t)a.C * 16) {
     a.grad_weight[i] = (float)(a.scale * s);
   } else if (i < (int64_t)a.C * 17) {
@@ -372,7 +403,8 @@ void launch_decoder(const DecArgs& a, const void* target, int target_bf16, float
   if (target_bf16) launch_t<unsigned short>(a, target, part, grid, s);
   else launch_t<float>(a, target, part, grid, s);
   const int64_t m = (int64_t)a.C * 17 + 1;
-  hipLaunchKernelGGL(k_decoder_reduce, dim3((unsigned)((m + 63) / 64)), dim3(256), 0, s, a, part, grid);
+  hipLaunchKernelGGL(k_decoder_reduce, dim3((unsigned)((m + 63) / 64)), dim3(64 * kRedGroups), 0, s, a, part,
+                     grid);
 }
 
 }  // namespace lgs
