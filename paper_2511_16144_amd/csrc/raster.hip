@@ -443,13 +443,20 @@ __device__ __forceinline__ int wave_max_i32(int x) {
 }
 
 constexpr int kZRow = 72;                  // bf16 per LDS row (64 pixels + pad; 144 B, 16-B aligned)
-// Staging of up to 8 partial records before they are written out: 36 floats
-// per record (the 32 of a slot + pad: 16-B aligned rows whose banks differ).
+// Blend-weight rows of a batch of 8 entries: three exact BF16 terms each.
+constexpr int kWRows = 24;
+// At each flush the batch's partial records are assembled in the weight
+// rows, whose weights the products have consumed by then: record e (36
+// floats: the 32 of a slot + pad) fills the 144 bytes of weight row e.  The
+// geometric sums of the batch's entries wait in a small area of their own.
 constexpr int kRecLds = 36;
-constexpr int kStageBytes = 8 * kRecLds * 4;
-// LDS bytes of one backward wave: upstream rows, blend-weight rows, staging
+static_assert(kRecLds * 4 == kZRow * 2, "a record fills one weight row");
+constexpr int kGeoStride = 8;              // floats per entry of the geometric staging
+constexpr int kGeoBytes = 8 * kGeoStride * 4;
+// LDS bytes of one backward wave: upstream rows, blend-weight rows,
+// geometric staging
 __host__ __device__ constexpr int bwd_wave_lds_bytes(int up_mode) {
-  return (bwd_upstream_rows(up_mode) + 16) * kZRow * 2 + kStageBytes;
+  return (bwd_upstream_rows(up_mode) + kWRows) * kZRow * 2 + kGeoBytes;
 }
 // FP32 -> BF16 bits, round to nearest even (finite inputs)
 __device__ __forceinline__ unsigned short bf16_rne(float x) {
@@ -482,9 +489,14 @@ __device__ __forceinline__ float transpose_reduce6(const float v[6], int lane) {
   return c + dpp<0xB1>(c);
 }
 
-// Six waves per SIMD (80 VGPRs; measured fastest for this kernel).
+// Waves per SIMD: what the LDS of each upstream form allows (six for the
+// fused L1 gradient, 80 VGPRs, measured fastest; five with the colour
+// gradient's extra rows; four with a given upstream's hi + lo rows), so that
+// the VGPR budget is no tighter than the occupancy LDS permits.
+constexpr int bwd_waves_per_eu(int up_mode) { return up_mode == UP_L1 ? 6 : (up_mode == UP_RGB ? 5 : 4); }
 template <bool BF16, int UPM, bool CNT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))) k_raster_bwd(
+__global__ void __launch_bounds__(256)
+    __attribute__((amdgpu_waves_per_eu(bwd_waves_per_eu(UPM), bwd_waves_per_eu(UPM)))) k_raster_bwd(
     Settings st, const ViewDesc* __restrict__ views, const ViewImages* __restrict__ upstream,
     const ViewImages* __restrict__ fwd_out, const ViewImages* __restrict__ targets,
     const float* __restrict__ loss_w, const uint2* __restrict__ ranges,
@@ -503,12 +515,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
   constexpr bool kSignDF = UPM != UP_EXPLICIT;
   // this wave's LDS rows (BF16, 64 pixels + pad each): the block's upstream
   // per channel, hi (20) and lo (for the given channels: 20, or the 3 colour
-  // channels), and the blend weights of up to 8 batched entries, hi (8) and
-  // lo (8)
+  // channels), and the blend weights of up to 8 batched entries in three
+  // exact terms (rows 0-7, 8-15, 16-23); then the geometric staging
   constexpr int kGRows = bwd_upstream_rows(UPM);
   unsigned short* lz = lds_z + (threadIdx.x >> 6) * (bwd_wave_lds_bytes(UPM) / 2);
   unsigned short* wz = lz + kGRows * kZRow;
-  float* stage = (float*)(wz + 16 * kZRow);         // 8 records of kRecLds floats
+  float* recs = (float*)wz;                         // records, at flush time
+  float* geo = (float*)(wz + kWRows * kZRow);       // 8 entries x kGeoStride floats
   const int grp = lane >> 4, col = lane & 15;
   if (cnt->overflow) return;
   // this wave's work (CNT: the profiling variant), added to the 64-bit
@@ -617,11 +630,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
     }
     int nb = 0;
     uint32_t slotv = 0;   // lane e: the slot of the batch's entry e
-    // Write the batch's nb partial records: the colour partials join the
-    // geometric ones in the staged records, then lanes store 16-byte
-    // quarters of the records (seven quarters, 112 bytes, of each 128-byte
-    // slot; 8 lanes per record) and the first lane of each record sets the
-    // slot's mask byte.
+    // Write the batch's nb partial records: the colour partials, sum_p w_p
+    // g_p, come from the matrix cores; the three weight terms go through
+    // K-stacked products (each term against the same upstream rows), so
+    // with a sign upstream every product is exact and only the FP32
+    // accumulation rounds.  Then the records are assembled in the consumed
+    // weight rows (colour partials and the staged geometric sums), lanes
+    // store 16-byte quarters of them (seven quarters, 112 bytes, of each
+    // 128-byte slot; 8 lanes per record) and the first lane of each record
+    // sets the slot's mask byte.
     auto flush = [&]() {
       f32x4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
       const int er = col & 7;
@@ -629,40 +646,56 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
 #pragma unroll
       for (int ks = 0; ks < 2; ++ks) {
         const int off = 32 * ks + 8 * grp;
-        const bf16x8_t ah = *(const bf16x8_t*)(wz + er * kZRow + off);
-        const bf16x8_t al = *(const bf16x8_t*)(wz + (8 + er) * kZRow + off);
+        bf16x8_t aw[3];   // output rows 8..15 repeat rows 0..7
+#pragma unroll
+        for (int t = 0; t < 3; ++t) aw[t] = *(const bf16x8_t*)(wz + (8 * t + er) * kZRow + off);
         const bf16x8_t bh0 = *(const bf16x8_t*)(lz + col * kZRow + off);
         bf16x8_t bh1 = *(const bf16x8_t*)(lz + ch1 * kZRow + off);
         if (col >= 4) bh1 = (bf16x8_t){};
-        c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh0, c0, 0, 0, 0);
-        c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh0, c0, 0, 0, 0);
-        c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh1, c1, 0, 0, 0);
-        c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh1, c1, 0, 0, 0);
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+          c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw[t], bh0, c0, 0, 0, 0);
+          c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw[t], bh1, c1, 0, 0, 0);
+        }
         if (UPM == UP_EXPLICIT) {
+          // the given upstream's lo term (relative 2^-8 of hi) against the two
+          // leading weight terms: the dropped products are below 2^-24
           const bf16x8_t bl0 = *(const bf16x8_t*)(lz + (20 + col) * kZRow + off);
           bf16x8_t bl1 = *(const bf16x8_t*)(lz + (20 + ch1) * kZRow + off);
           if (col >= 4) bl1 = (bf16x8_t){};
-          c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl0, c0, 0, 0, 0);
-          c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl1, c1, 0, 0, 0);
+#pragma unroll
+          for (int t = 0; t < 2; ++t) {
+            c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw[t], bl0, c0, 0, 0, 0);
+            c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw[t], bl1, c1, 0, 0, 0);
+          }
         } else if (UPM == UP_RGB) {
           // lo rows exist for the three colour channels only
           bf16x8_t bl0 = *(const bf16x8_t*)(lz + (20 + (col < 3 ? col : 0)) * kZRow + off);
           if (col >= 3) bl0 = (bf16x8_t){};
-          c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl0, c0, 0, 0, 0);
+#pragma unroll
+          for (int t = 0; t < 2; ++t) c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw[t], bl0, c0, 0, 0, 0);
         }
       }
+      // every read of the weight rows above precedes the record writes below
+      // (LDS operations of a wave run in order; this keeps the compiler from
+      // moving the differently typed accesses across each other)
+      asm volatile("" ::: "memory");
       const float s0 = col < 3 ? gscale[0] : (col == 3 ? gscale[1] : gscale[2]);
       const float s1 = gscale[2];
       if (grp < 2) {   // output rows 8..15 repeat rows 0..7
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          float* rec = stage + (4 * grp + i) * kRecLds;
+          float* rec = recs + (4 * grp + i) * kRecLds;
           rec[6 + col] = c0[i] * s0;
           if (col < 4) rec[22 + col] = c1[i] * s1;
         }
       }
+      if (lane < 48) {   // the geometric sums of the batch's entries
+        const int e = lane / 6, k = lane - 6 * e;
+        recs[e * kRecLds + k] = geo[e * kGeoStride + k];
+      }
       const int er4 = lane >> 3, q4 = lane & 7;
-      const float4 v4 = *(const float4*)(stage + er4 * kRecLds + 4 * q4);
+      const float4 v4 = *(const float4*)(recs + er4 * kRecLds + 4 * q4);
       const uint32_t sl = (uint32_t)__builtin_amdgcn_ds_bpermute(er4 * 4, (int)slotv);
       // quarters 0..6 hold the kPartials values; the eighth is padding that
       // the reduction never reads, so it is not written
@@ -671,6 +704,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
         *(float4*)(partials + (size_t)sl * kSlotFloats + 4 * q4) = v4;
         if (q4 == 0) mask[sl] = 1;
       }
+      // the record reads above precede the next batch's weight writes
+      asm volatile("" ::: "memory");
       nb = 0;
     };
     for (int top = kmax; top >= (int)kbeg; top -= 64) {
@@ -756,17 +791,22 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6, 6))
           vv[3] = mxd * dy;
           vv[4] = myd * dy;
           vv[5] = dgeo * e.G;
-          // hi = RNE(wc), lo = RNE(wc - hi): the hardware conversion
-          const __bf16 wh = (__bf16)wc;
-          wz[nb * kZRow + lane] = __builtin_bit_cast(unsigned short, wh);
-          wz[(8 + nb) * kZRow + lane] = __builtin_bit_cast(unsigned short, (__bf16)(wc - (float)wh));
+          // wc = hi + mid + lo exactly: each term keeps the top 8 significant
+          // bits of what is left (truncation), so each is a BF16 value
+          const float whi = __uint_as_float(__float_as_uint(wc) & 0xffff0000u);
+          const float r1 = wc - whi;
+          const float wmid = __uint_as_float(__float_as_uint(r1) & 0xffff0000u);
+          const float wlo = r1 - wmid;
+          wz[nb * kZRow + lane] = (unsigned short)(__float_as_uint(whi) >> 16);
+          wz[(8 + nb) * kZRow + lane] = (unsigned short)(__float_as_uint(wmid) >> 16);
+          wz[(16 + nb) * kZRow + lane] = (unsigned short)(__float_as_uint(wlo) >> 16);
         }
         const uint32_t bb = gr.bbox;
         const uint32_t bw = ((bb >> 8) & 255u) - (bb & 255u) + 1u;
         const uint32_t slot = sbase + (by - (uint32_t)by0) * bw + (bx - (uint32_t)bx0);
         const float s6 = transpose_reduce6(vv, lane);
         // one lane per value: 0, 8, 16, 32, 40, 48 (24 and 56 repeat 8 and 40)
-        if ((lane & 7) == 0 && (lane & 24) != 24) stage[nb * kRecLds + red6_index(lane)] = s6;
+        if ((lane & 7) == 0 && (lane & 24) != 24) geo[nb * kGeoStride + red6_index(lane)] = s6;
         slotv = lane == nb ? slot : slotv;   // lane nb: this entry's slot
         ++nb;
         if (nb == 8) flush();
