@@ -58,12 +58,14 @@ FLOPS_FWD_EVAL_ALT = 52
 FLOPS_BWD_EVAL_ALT = 140
 
 
-def measured_traffic(kernel, settings, workload, mode):
+def measured_traffic(kernel, settings, workload, mode, field="bytes_per_launch"):
     """HBM bytes per launch of `kernel` (or per step: kernel == "step") from
-    the committed counter summary (two rocprofv3 passes, FETCH_SIZE then
-    WRITE_SIZE, scaled against a kernel of known traffic), or None when the
-    kernel sources changed since, or the settings, mode or workload differ
-    from the profiled ones."""
+    the committed counter summary, or None when the kernel sources changed
+    since, or the settings, mode or workload differ from the profiled ones.
+    field "bytes_per_launch": two rocprofv3 passes, FETCH_SIZE then
+    WRITE_SIZE, each scaled against a kernel of known traffic;
+    "request_size_bytes": the reads counted by request size (32/64/128 B
+    requests at the L2's memory side) plus WRITE_SIZE."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "hbm_traffic_compositing_batched_c4.md")
     if not os.path.exists(path) or workload != "batched":
@@ -82,7 +84,7 @@ def measured_traffic(kernel, settings, workload, mode):
         if len(f) >= 3 and f[0] == "traffic" and f[1] == kernel:
             kv = dict(x.split("=", 1) for x in f[2:] if "=" in x)
             if all(kv.get(k) == v for k, v in want.items()):
-                return float(kv["bytes_per_launch"])
+                return float(kv[field]) if field in kv else None
     return None
 
 
@@ -529,6 +531,8 @@ def main():
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
             "frac": (achieved / PEAK_FP32_TFLOPS) if achieved else None,
             "traffic": measured_traffic("k_raster_bwd", r["settings"], args.workload, mode),
+            "traffic_by_request_size": measured_traffic("k_raster_bwd", r["settings"], args.workload, mode,
+                                                        "request_size_bytes"),
             "kernel": "k_raster_bwd", "kernel_ms": kms,
             "units": {"bwd_evals": c["bwd_evals"], "bwd_contrib": c["bwd_contrib"]},
             "flops_per_unit": {"eval": FLOPS_EVAL, "contrib": FLOPS_BWD_CONTRIB},
@@ -548,6 +552,7 @@ def main():
     # whole-step HBM traffic (both counter passes, every kernel, same mode and
     # settings) over the step time
     step_bytes = measured_traffic("step", r["settings"], args.workload, mode)
+    step_bytes_rs = measured_traffic("step", r["settings"], args.workload, mode, "request_size_bytes")
     hbm = {"algorithmic_bytes_per_step": ab, "algorithmic_GB/s": round(ab_gbs, 1),
            "algorithmic_frac": round(ab_gbs / PEAK_HBM_GBS, 4),
            "algorithmic_frac_of_copy": round(ab_gbs / copy_gbs, 4),
@@ -557,6 +562,11 @@ def main():
         hbm.update({"measured_bytes_per_step": step_bytes, "measured_GB/s": round(gbs, 1),
                     "measured_frac": round(gbs / PEAK_HBM_GBS, 4), "measured_frac_of_copy": round(gbs / copy_gbs, 4),
                     "source": "profiles/hbm_traffic_compositing_batched_c4.md (FETCH_SIZE + WRITE_SIZE, calibrated)"})
+    if step_bytes_rs is not None:
+        gbs = step_bytes_rs / (r["ms"] / 1e3) / 1e9
+        hbm.update({"measured_bytes_per_step_by_request_size": step_bytes_rs,
+                    "measured_GB/s_by_request_size": round(gbs, 1),
+                    "measured_frac_by_request_size": round(gbs / PEAK_HBM_GBS, 4)})
     out = {"metric": METRIC, "value": round(mpx, 3), "unit": "Mpixel/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(r["ms"], 4), "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "bf16" if wl.scene.dtype == "bf16" else "f32",
