@@ -132,9 +132,19 @@ __global__ __launch_bounds__(kDecThreads) void k_decoder(DecArgs a, const TT* __
 
   // W is staged in LDS once (over the sign rows, unused until the first
   // chunk's first barrier), then every wave builds its operands from there
+  // (C = 16 NT kDecWaves: every thread copies the same number of values,
+  // all requested before the first is stored)
   float* wl = (float*)&rC[0][0];
   static_assert(sizeof(rC) >= (size_t)kDecWaves * Cw * 16 * sizeof(float), "W fits over the sign rows");
-  for (int e = t; e < a.C * 16; e += kDecThreads) wl[e] = a.weight[e];
+  {
+    constexpr int kWv = kDecWaves * Cw * 16 / kDecThreads;   // values per thread
+    static_assert(kWv * kDecThreads == kDecWaves * Cw * 16, "W divides evenly among the threads");
+    float wv[kWv];
+#pragma unroll
+    for (int i = 0; i < kWv; ++i) wv[i] = a.weight[t + i * kDecThreads];
+#pragma unroll
+    for (int i = 0; i < kWv; ++i) wl[t + i * kDecThreads] = wv[i];
+  }
   __syncthreads();
   // this wave's operands of W, split hi/lo, in registers for the whole run
   // Z^T B operand, tile nt: lane (k block q4, channel r16): [W_hi ; W_hi] and [W_lo ; W_lo]
@@ -358,9 +368,22 @@ __global__ __launch_bounds__(64 * kRedGroups) void k_decoder_reduce(DecArgs a, c
   const int o = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int64_t i = (int64_t)blockIdx.x * 64 + o;
   const int64_t m = (int64_t)a.C * 17 + 1;
+  // the partials of up to kRedBatch work-groups per thread are requested
+  // before the first is added (n_parts <= kRedGroups kRedBatch in one pass)
   double s = 0.0;
-  if (i < m)
-    for (int b = g; b < n_parts; b += kRedGroups) s += (double)part[(size_t)b * a.part_stride + i];
+  if (i < m) {
+    constexpr int kRedBatch = 16;
+    for (int b0 = g; b0 < n_parts; b0 += kRedGroups * kRedBatch) {
+      float v[kRedBatch];
+#pragma unroll
+      for (int u = 0; u < kRedBatch; ++u) {
+        const int b = b0 + u * kRedGroups;
+        v[u] = b < n_parts ? part[(size_t)b * a.part_stride + i] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < kRedBatch; ++u) s += (double)v[u];
+    }
+  }
   red[g][o] = s;
   __syncthreads();
   if (g != 0 || i >= m) return;
