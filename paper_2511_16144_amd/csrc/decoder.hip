@@ -164,7 +164,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decoder(DecArgs a, const TT* __
     }
     bz1[nt] = as_bf16x8(h);
     bz2[nt] = as_bf16x8(l);
-    bias[nt] = a.bias[ch];
+    bias[nt] = a.bias[ch] + 0.f;   // +0 for a -0 bias: Z is then never -0
   }
   // dF A operand (W^T), step ks: lane (feature r16, channels 32 ks + 8 q4 .. + 7)
   bf16x8_t wt_h[KS], wt_l[KS];
@@ -184,11 +184,11 @@ __global__ __launch_bounds__(kDecThreads) void k_decoder(DecArgs a, const TT* __
   }
 
   f32x4 dw[NT];            // dW^T tiles: lane (features 4 q4 + i, channel 16 nt + r16)
-  float db[NT];            // per lane: channel 16 nt + r16, its pixels 4 q4 .. + 3
+  int db[NT];              // per lane: channel 16 nt + r16, its pixels 4 q4 .. + 3 (sum of signs)
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) {
     dw[nt] = (f32x4){0.f, 0.f, 0.f, 0.f};
-    db[nt] = 0.f;
+    db[nt] = 0;
   }
   float lsum = 0.f;
 
@@ -278,9 +278,16 @@ __global__ __launch_bounds__(kDecThreads) void k_decoder(DecArgs a, const TT* __
         for (int i = 0; i < 4; ++i) {
           const bool valid = kFull || pl + i < lim;
           const float d = z[i] - tv[i];
-          const float s = !valid ? 0.f : (d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f));
+          // Z is never -0 (its sum starts from the bias plus +0) and a
+          // difference of equal values is +0, so d is never -0: its bits as a
+          // signed integer are > 0, 0 or < 0 as d is, and their clamp to
+          // [-1, 1] (one v_med3_i32) is the sign of d
+          int si;
+          asm("v_med3_i32 %0, %1, -1, 1" : "=v"(si) : "v"(__float_as_uint(d)));
+          if (!kFull) si = valid ? si : 0;
           lsum += valid ? fabsf(d) : 0.f;
-          db[nt] += s;
+          db[nt] += si;
+          const float s = (float)si;
           sg[i] = (unsigned short)(__float_as_uint(s) >> 16);   // -1, 0, 1: exact in BF16
           rP[w][(pl + i) * kRP + rp_col(pl + i, 16 * nt + r16)] = sg[i];
         }
@@ -340,10 +347,10 @@ __global__ __launch_bounds__(kDecThreads) void k_decoder(DecArgs a, const TT* __
   for (int nt = 0; nt < NT; ++nt) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) pb[(size_t)(c0 + 16 * nt + r16) * 16 + 4 * q4 + i] = dw[nt][i];
-    float s = db[nt];
+    int s = db[nt];
     s += __shfl_xor(s, 16);
     s += __shfl_xor(s, 32);
-    if (q4 == 0) pb[(size_t)a.C * 16 + c0 + 16 * nt + r16] = s;
+    if (q4 == 0) pb[(size_t)a.C * 16 + c0 + 16 * nt + r16] = (float)s;
   }
   for (int o = 32; o > 0; o >>= 1) lsum += __shfl_xor(lsum, o);
   if (lane == 0) red[w] = lsum;
