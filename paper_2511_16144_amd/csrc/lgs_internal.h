@@ -80,6 +80,7 @@ struct Settings {
   int32_t feat_dim;           // D: feature planes of the inputs
   int32_t nfeat;              // feature channels of the group being processed (8 or 16)
   int32_t count;              // 1: the compositing kernels' profiling variants, which count their work
+  float log2_alpha_min;       // log2(alpha_min), for the compositing kernels' block cull
 };
 
 // Device-resident counters of one forward (written by kernels, read by

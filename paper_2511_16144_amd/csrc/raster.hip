@@ -77,14 +77,17 @@ __device__ __forceinline__ bool block_in_bbox(uint32_t bb, uint32_t bx, uint32_t
 // margin that covers the FP32 rounding of both this test and the per-pixel
 // evaluation (whose error grows with (qa + qc) |d|^2), so the test never
 // drops an entry that eval_entry would accept at some pixel of the block.
+// The edge minimisers use the hardware reciprocal (about 1 ulp): a minimiser
+// off by that much raises the edge minimum by a second-order amount, far
+// inside the margin.
 __device__ __forceinline__ bool cull_hit(const GeomRec& g, uint32_t bx, uint32_t by, float cutoff2,
-                                         float alpha_min) {
+                                         float log2_alpha_min) {
   const int bx0 = (int)(g.bbox & 255u), by0 = (int)((g.bbox >> 16) & 255u);
   const float x0 = (float)(8 * ((int)bx - bx0)) - g.mx, x1 = x0 + 7.f;
   const float y0 = (float)(8 * ((int)by - by0)) - g.my, y1 = y0 + 7.f;
   float m = 0.f;
   if (!(x0 <= 0.f && x1 >= 0.f && y0 <= 0.f && y1 >= 0.f)) {
-    const float ia = -g.qb2 / (2.f * g.qa), ic = -g.qb2 / (2.f * g.qc);
+    const float ia = -g.qb2 * __builtin_amdgcn_rcpf(2.f * g.qa), ic = -g.qb2 * __builtin_amdgcn_rcpf(2.f * g.qc);
     auto qf = [&](float dx, float dy) { return g.qa * dx * dx + g.qb2 * dx * dy + g.qc * dy * dy; };
     const float e0 = qf(x0, fminf(fmaxf(ic * x0, y0), y1));
     const float e1 = qf(x1, fminf(fmaxf(ic * x1, y0), y1));
@@ -92,8 +95,7 @@ __device__ __forceinline__ bool cull_hit(const GeomRec& g, uint32_t bx, uint32_t
     const float e3 = qf(fminf(fmaxf(ia * y1, x0), x1), y1);
     m = fminf(fminf(e0, e1), fminf(e2, e3));
   }
-  const float r2 = fminf(cutoff2, 1.3862943611198906f * (__builtin_amdgcn_logf(g.o) -
-                                                          __builtin_amdgcn_logf(alpha_min)));
+  const float r2 = fminf(cutoff2, 1.3862943611198906f * (__builtin_amdgcn_logf(g.o) - log2_alpha_min));
   const float d2 = fmaxf(x0 * x0, x1 * x1) + fmaxf(y0 * y0, y1 * y1);
   return m <= r2 * 1.0001f + 1e-3f + 4e-6f * (g.qa + g.qc) * d2;
 }
@@ -264,7 +266,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ?
       if (kl < r.y) {
         rid_l = vals[kl];
         g_l = geom[rid_l];
-        hit = block_in_bbox(g_l.bbox, bx, by) && cull_hit(g_l, bx, by, st.cutoff2, st.alpha_min);
+        hit = block_in_bbox(g_l.bbox, bx, by) && cull_hit(g_l, bx, by, st.cutoff2, st.log2_alpha_min);
       }
       uint64_t hm = __builtin_amdgcn_ballot_w64(hit);
       // the appearance of the entry to visit next is requested at the end of
@@ -717,7 +719,7 @@ __global__ void __launch_bounds__(256)
       if (kl >= (int)kbeg) {
         rid_l = vals[kl];
         const GeomRec g_l = geom[rid_l];
-        hit = block_in_bbox(g_l.bbox, bx, by) && cull_hit(g_l, bx, by, st.cutoff2, st.alpha_min);
+        hit = block_in_bbox(g_l.bbox, bx, by) && cull_hit(g_l, bx, by, st.cutoff2, st.log2_alpha_min);
       }
       uint64_t hm = __builtin_amdgcn_ballot_w64(hit);
       while (hm) {

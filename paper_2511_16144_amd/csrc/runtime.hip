@@ -320,6 +320,7 @@ Settings dev_settings(const lgs_settings* st, int tile_shift, int D = kFeatGroup
   s.feat_dim = D;
   s.nfeat = group_nfeat(D, group);
   s.count = (st->profile & LGS_PROFILE_COUNTS) != 0;
+  s.log2_alpha_min = log2f(st->alpha_min);
   return s;
 }
 
