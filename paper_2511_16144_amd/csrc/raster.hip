@@ -735,6 +735,13 @@ __global__ void __launch_bounds__(256)
         uint32_t yw[BF16 ? 10 : 20];
         load_app_words<BF16>(app, rid & npad_mask, yw);
         const uint32_t sbase = slot_base[rid];
+        // the compiler would sink the appearance and slot-base loads below the
+        // no-contribution exit, a second round trip after the evaluation's;
+        // using every loaded word here, before the geometry's first use,
+        // keeps the three requests and their one wait together
+        asm volatile("" ::"s"(sbase));
+#pragma unroll
+        for (int k = 0; k < (BF16 ? 10 : 20); ++k) asm volatile("" ::"s"(yw[k]));
         const uint64_t lm = __builtin_amdgcn_ballot_w64(k <= last);   // lanes this entry can reach
         if (CNT) {
           n_eval += (uint32_t)__popcll(lm);
