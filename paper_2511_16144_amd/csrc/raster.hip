@@ -100,6 +100,16 @@ __device__ __forceinline__ bool cull_hit(const GeomRec& g, uint32_t bx, uint32_t
   return m <= r2 * 1.0001f + 1e-3f + 4e-6f * (g.qa + g.qc) * d2;
 }
 
+// A list entry's whole record for the cull test, requested as one: its
+// fields are used at once, so the compiler cannot defer those the box test
+// does not need below that test's branch (a further dependent round trip
+// per chunk).
+__device__ __forceinline__ GeomRec load_rec_whole(const GeomRec* __restrict__ p) {
+  const GeomRec g = *p;
+  asm volatile("" ::"v"(g.mx), "v"(g.my), "v"(g.qa), "v"(g.qb2), "v"(g.qc), "v"(g.o), "v"(g.z), "v"(g.bbox));
+  return g;
+}
+
 __device__ __forceinline__ float bcast(float x, uint32_t j) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), j));
 }
@@ -257,17 +267,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ?
     // inverse ballots, so the bookkeeping costs scalar instructions only
     uint64_t live = __builtin_amdgcn_ballot_w64(inside);
     bool finished = live == 0ull;
+    // the list entries of the next chunk are requested a chunk ahead
+    uint32_t rid_n = 0;
+    if (r.x + (uint32_t)lane < r.y) rid_n = vals[r.x + (uint32_t)lane];
     for (uint32_t base = r.x; base < r.y && !finished; base += 64) {
-      // lane l loads entry base + l and decides whether the wave visits it
+      // lane l takes entry base + l and decides whether the wave visits it
       const uint32_t kl = base + (uint32_t)lane;
-      uint32_t rid_l = 0;
+      const uint32_t rid_l = rid_n;
       GeomRec g_l{};
       bool hit = false;
       if (kl < r.y) {
-        rid_l = vals[kl];
-        g_l = geom[rid_l];
+        g_l = load_rec_whole(geom + rid_l);
         hit = block_in_bbox(g_l.bbox, bx, by) && cull_hit(g_l, bx, by, st.cutoff2, st.log2_alpha_min);
       }
+      if (kl + 64u < r.y) rid_n = vals[kl + 64u];
       uint64_t hm = __builtin_amdgcn_ballot_w64(hit);
       // the appearance of the entry to visit next is requested at the end of
       // the current one, so its latency overlaps that entry's evaluation
@@ -710,17 +723,20 @@ __global__ void __launch_bounds__(256)
       asm volatile("" ::: "memory");
       nb = 0;
     };
+    // the list entries of the next chunk are requested a chunk ahead
+    uint32_t rid_n = 0;
+    if (kmax - lane >= (int)kbeg) rid_n = vals[kmax - lane];
     for (int top = kmax; top >= (int)kbeg; top -= 64) {
-      // lane l loads entry top - l (the list backwards) and decides whether
+      // lane l takes entry top - l (the list backwards) and decides whether
       // the wave visits it
       const int kl = top - lane;
-      uint32_t rid_l = 0;
+      const uint32_t rid_l = rid_n;
       bool hit = false;
       if (kl >= (int)kbeg) {
-        rid_l = vals[kl];
-        const GeomRec g_l = geom[rid_l];
+        const GeomRec g_l = load_rec_whole(geom + rid_l);
         hit = block_in_bbox(g_l.bbox, bx, by) && cull_hit(g_l, bx, by, st.cutoff2, st.log2_alpha_min);
       }
+      if (kl - 64 >= (int)kbeg) rid_n = vals[kl - 64];
       uint64_t hm = __builtin_amdgcn_ballot_w64(hit);
       while (hm) {
         const uint32_t j = (uint32_t)__builtin_ctzll(hm);
