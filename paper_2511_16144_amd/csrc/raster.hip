@@ -181,11 +181,14 @@ typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
 // into three BF16 terms (8 significant bits each) and the BF16 appearance is
 // exact, so every product is exact and only the FP32 accumulation rounds.
 // The depth slot is accumulated separately in FP32.
-// LDS of one wave: the batch's appearance [20 slots][8 entries], a zero block
-// of the same size, and the weights [3 terms][64 pixels][8 entries] (BF16).
+// LDS of one wave: the batch's appearance [20 slots][8 entries] in rows 0-19
+// of a [64][8] area (lane l stores into row l, so the per-entry store needs
+// no lane mask; rows 20-63 are never read), a zero block [20][8], and the
+// weights [3 terms][64 pixels][8 entries] (BF16).
 constexpr int kFwdY = 20 * 8;
+constexpr int kFwdYRows = 64 * 8;
 constexpr int kFwdW = 64 * 8;
-constexpr int kFwdWaveLds = (2 * kFwdY + 3 * kFwdW) * 2;
+constexpr int kFwdWaveLds = (kFwdYRows + kFwdY + 3 * kFwdW) * 2;
 
 // FP32 appearance: eight waves per SIMD (64 VGPRs), measured faster than the
 // compiler's own register choice, which leaves room for only seven.  BF16
@@ -203,11 +206,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ?
   if (cnt->overflow) return;
   extern __shared__ unsigned short lds_f[];
   unsigned short* ys = lds_f + (threadIdx.x >> 6) * (kFwdWaveLds / 2);
-  unsigned short* yz = ys + kFwdY;
+  unsigned short* yz = ys + kFwdYRows;
   unsigned short* ws = yz + kFwdY;
   // A-operand rows: lane l reads slot 4 j + (l & 3) when its row group
   // (l & 15) / 4 equals its k-block l / 16, else the zero block
   const unsigned short* abase = (((lane & 15) >> 2) == (lane >> 4) ? ys : yz) + (lane & 3) * 8;
+  // the appearance slot this lane loads per entry (lanes past the 20 slots
+  // repeat the last one, into rows no product reads)
+  const uint32_t ylane = lane < 20 ? (uint32_t)lane : 19u;
   const unsigned short* __restrict__ app16 = (const unsigned short*)app;
   if (BF16) {
     // the zero block, and the weights: a partial batch leaves the weights of
@@ -296,7 +302,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ?
         if (BF16) gn = geom[__builtin_amdgcn_readlane(rid_l, j)];
         const uint32_t g0 = __builtin_amdgcn_readlane(rid_l, j) & npad_mask;
         if (BF16) {
-          if (lane < 20) yh = app16[(size_t)g0 * 20 + lane];
+          yh = app16[(size_t)g0 * 20 + ylane];
         } else {
           load_app_words<BF16>(app, g0, aw);
         }
@@ -346,7 +352,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ?
             ws[lane * 8 + nb] = (unsigned short)(__float_as_uint(whi) >> 16);
             ws[kFwdW + lane * 8 + nb] = (unsigned short)(__float_as_uint(wmid) >> 16);
             ws[2 * kFwdW + lane * 8 + nb] = (unsigned short)(__float_as_uint(wlo) >> 16);
-            if (lane < 20) ys[lane * 8 + nb] = yh;
+            ys[lane * 8 + nb] = yh;
           } else {
             float y[20];
             y_from_words<BF16>(aw, y);
@@ -368,7 +374,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ?
           if (BF16) gn = geom[__builtin_amdgcn_readlane(rid_l, j)];
           const uint32_t g0 = __builtin_amdgcn_readlane(rid_l, j) & npad_mask;
           if (BF16) {
-            if (lane < 20) yh = app16[(size_t)g0 * 20 + lane];
+            yh = app16[(size_t)g0 * 20 + ylane];
           } else {
             load_app_words<BF16>(app, g0, aw);
           }
