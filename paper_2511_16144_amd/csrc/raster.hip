@@ -110,6 +110,14 @@ __device__ __forceinline__ GeomRec load_rec_whole(const GeomRec* __restrict__ p)
   return g;
 }
 
+// Record of list entry j's Gaussian (rid in lane j) by a scalar load whose
+// offset is a 32-bit register (records sit below 2^32 bytes): one shift of
+// the index instead of 64-bit address arithmetic per entry.
+__device__ __forceinline__ GeomRec rec_of_lane(const GeomRec* __restrict__ geom, uint32_t rid_l, uint32_t j) {
+  const uint32_t off = (uint32_t)__builtin_amdgcn_readlane((int)rid_l, (int)j) << 5;
+  return *(const GeomRec*)((const char*)geom + off);
+}
+
 __device__ __forceinline__ float bcast(float x, uint32_t j) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), j));
 }
@@ -212,7 +220,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ?
   // (l & 15) / 4 equals its k-block l / 16, else the zero block
   const unsigned short* abase = (((lane & 15) >> 2) == (lane >> 4) ? ys : yz) + (lane & 3) * 8;
   // the appearance slot this lane loads per entry (lanes past the 20 slots
-  // repeat the last one, into rows no product reads)
+  // repeat the last one, into rows no product reads); the records' byte
+  // offsets stay below 2^32, so each load takes a 32-bit lane offset
   const uint32_t ylane = lane < 20 ? (uint32_t)lane : 19u;
   const unsigned short* __restrict__ app16 = (const unsigned short*)app;
   if (BF16) {
@@ -299,10 +308,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ?
       // words) broadcast from the lane that loaded it
       GeomRec gn{};
       if (hm) {
-        if (BF16) gn = geom[__builtin_amdgcn_readlane(rid_l, j)];
+        if (BF16) gn = rec_of_lane(geom, rid_l, j);
         const uint32_t g0 = __builtin_amdgcn_readlane(rid_l, j) & npad_mask;
         if (BF16) {
-          yh = app16[(size_t)g0 * 20 + ylane];
+          yh = *(const unsigned short*)((const char*)app16 + (g0 * 40u + 2u * ylane));
         } else {
           load_app_words<BF16>(app, g0, aw);
         }
@@ -371,10 +380,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ?
         }
         if (hm) {
           j = (uint32_t)__builtin_ctzll(hm);
-          if (BF16) gn = geom[__builtin_amdgcn_readlane(rid_l, j)];
+          if (BF16) gn = rec_of_lane(geom, rid_l, j);
           const uint32_t g0 = __builtin_amdgcn_readlane(rid_l, j) & npad_mask;
           if (BF16) {
-            yh = app16[(size_t)g0 * 20 + ylane];
+            yh = *(const unsigned short*)((const char*)app16 + (g0 * 40u + 2u * ylane));
           } else {
             load_app_words<BF16>(app, g0, aw);
           }
