@@ -127,7 +127,8 @@ __device__ __forceinline__ float bcast(float x, uint32_t j) {
 // 3 is filled by the caller with the view's depth.
 template <bool BF16>
 __device__ __forceinline__ void load_app_words(const void* __restrict__ app, uint32_t g, uint32_t w[20]) {
-  const uint32_t* a = (const uint32_t*)app + (size_t)g * (BF16 ? 10 : 20);
+  // (a 32-bit byte offset: the records stay below 2^32 bytes)
+  const uint32_t* a = (const uint32_t*)((const char*)app + g * (BF16 ? 40u : 80u));
 #pragma unroll
   for (int k = 0; k < (BF16 ? 10 : 20); ++k) w[k] = a[k];
 }
@@ -762,10 +763,10 @@ __global__ void __launch_bounds__(256)
         // evaluation, so their latencies overlap (the appearance and the slot
         // base are not needed when no lane contributes, but loading them
         // anyway costs less than a second round trip when one does)
-        const GeomRec gr = geom[rid];
+        const GeomRec gr = *(const GeomRec*)((const char*)geom + (rid << 5));
         uint32_t yw[BF16 ? 10 : 20];
         load_app_words<BF16>(app, rid & npad_mask, yw);
-        const uint32_t sbase = slot_base[rid];
+        const uint32_t sbase = *(const uint32_t*)((const char*)slot_base + (rid << 2));
         // the compiler would sink the appearance and slot-base loads below the
         // no-contribution exit, a second round trip after the evaluation's;
         // using every loaded word here, before the geometry's first use,
