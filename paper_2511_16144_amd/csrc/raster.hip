@@ -89,11 +89,12 @@ __device__ __forceinline__ bool cull_hit(const GeomRec& g, uint32_t bx, uint32_t
   if (!(x0 <= 0.f && x1 >= 0.f && y0 <= 0.f && y1 >= 0.f)) {
     const float ia = -g.qb2 * __builtin_amdgcn_rcpf(2.f * g.qa), ic = -g.qb2 * __builtin_amdgcn_rcpf(2.f * g.qc);
     auto qf = [&](float dx, float dy) { return g.qa * dx * dx + g.qb2 * dx * dy + g.qc * dy * dy; };
-    const float e0 = qf(x0, fminf(fmaxf(ic * x0, y0), y1));
-    const float e1 = qf(x1, fminf(fmaxf(ic * x1, y0), y1));
-    const float e2 = qf(fminf(fmaxf(ia * y0, x0), x1), y0);
-    const float e3 = qf(fminf(fmaxf(ia * y1, x0), x1), y1);
-    m = fminf(fminf(e0, e1), fminf(e2, e3));
+    // clamps as one v_med3_f32 each (finite operands: no NaN handling)
+    const float e0 = qf(x0, __builtin_amdgcn_fmed3f(ic * x0, y0, y1));
+    const float e1 = qf(x1, __builtin_amdgcn_fmed3f(ic * x1, y0, y1));
+    const float e2 = qf(__builtin_amdgcn_fmed3f(ia * y0, x0, x1), y0);
+    const float e3 = qf(__builtin_amdgcn_fmed3f(ia * y1, x0, x1), y1);
+    m = __builtin_fminf(__builtin_fminf(e0, e1), __builtin_fminf(e2, e3));
   }
   const float r2 = fminf(cutoff2, 1.3862943611198906f * (__builtin_amdgcn_logf(g.o) - log2_alpha_min));
   const float d2 = fmaxf(x0 * x0, x1 * x1) + fmaxf(y0 * y0, y1 * y1);
