@@ -58,6 +58,10 @@ FLOPS_FWD_EVAL_ALT = 52
 FLOPS_BWD_EVAL_ALT = 140
 
 
+# (tile, chunk, order) of the committed counter summaries
+PROFILED_SETTINGS = (32, 4, 2)
+
+
 def measured_traffic(kernel, settings, workload, mode, field="bytes_per_launch"):
     """HBM bytes per launch of `kernel` (or per step: kernel == "step") from
     the committed counter summary, or None when the kernel sources changed
@@ -453,7 +457,10 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="batched", choices=["batched", "plain", "precision", "differentiation"])
-    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="plain FP32 leg: library defaults instead of the autotuner")
+    ap.add_argument("--tune", action="store_true",
+                    help="batched step: the autotuner's settings instead of the profiled ones")
     ap.add_argument("--mode", default="graph", choices=["eager", "graph"],
                     help="eager: lgs_forward + lgs_backward_l1 per step; graph: one captured launch per step")
     ap.add_argument("--tile", type=int, default=None, help="fix the tile size (skips the autotuner)")
@@ -496,6 +503,13 @@ def main():
         del a, b
     ctx = P.Context(0)
     settings = P.Settings(profile=1)
+    # The batched step runs at the settings its committed rocprofv3 counters
+    # were taken at (the autotuner's pick among them moves between boxes
+    # within timing noise, and measured traffic is only valid for the
+    # profiled settings); --tune lets the autotuner choose, any of --tile /
+    # --chunk / --order fixes the rest at the library defaults.
+    if not args.tune and all(x is None for x in (args.tile, args.chunk, args.order)):
+        args.tile, args.chunk, args.order = PROFILED_SETTINGS
     fixed = any(x is not None for x in (args.tile, args.chunk, args.order))
     if args.tile is not None:
         settings.tile = args.tile
@@ -505,7 +519,7 @@ def main():
         settings.order = args.order
     log(f"[bench] timing C{cfg}: {wl.scene.n} Gaussians, {len(wl.cams)} views, {wl.pixels} px")
     timer = time_workload_graph if args.mode == "graph" else time_workload
-    r = timer(ctx, wl, args.steps, args.warmup, dev, not (args.no_tune or fixed), settings)
+    r = timer(ctx, wl, args.steps, args.warmup, dev, args.tune and not fixed, settings)
     mpx = wl.pixels / (r["ms"] / 1e3) / 1e6
     c = r["counts"]
     st = r["stages"]
@@ -578,6 +592,9 @@ def main():
                                     "operands split exactly where the appearance is bf16",
                       "loss_w": list(wl.loss_w), "mode": args.mode,
                       **r["settings"],
+                      "settings_from": "autotuner" if args.tune and not fixed else
+                                       ("profiled settings" if tuple(r["settings"][k] for k in ("tile", "chunk", "order"))
+                                        == PROFILED_SETTINGS else "command line"),
                       "parallelism": "single GPU"},
            "timing": {"ms_per_step": "median of the timed steps (HIP events around each step)",
                       "ms_per_step_mean": round(r["ms_mean"], 4)},
