@@ -178,7 +178,11 @@ void lgs_context_destroy(lgs_context *ctx);
  * Eq. (1) depth D^).  cams[n_views] and out[n_views] are host arrays of
  * structs whose image pointers are device memory.  On success *state_out
  * holds what lgs_backward needs; release it with lgs_state_release.  The
- * Gaussian arrays must stay unmodified until the backward has run. */
+ * Gaussian arrays must stay unmodified until the backward has run.
+ * LGS_ERR_UNSUPPORTED when n > 2^30, when n rounded up to a power of two
+ * exceeds 2^26 (BF16 appearance) or 2^25 (FP32), or n_views times it
+ * exceeds 2^27 (the compositing kernels address their records by 32-bit
+ * byte offsets), or for more than 2^31 8x8 pixel blocks. */
 lgs_status lgs_forward(lgs_context *ctx, const lgs_settings *st,
                        const lgs_gaussians *g, int32_t n_views,
                        const lgs_camera *cams, const lgs_images *out,

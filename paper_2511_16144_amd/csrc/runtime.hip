@@ -520,7 +520,12 @@ lgs_status w_init(Work* W, lgs_context* ctx, const lgs_settings* st, const lgs_g
   W->G = (W->D + kFeatGroup - 1) / kFeatGroup;
   W->npad_shift = (int)ceil_log2((uint64_t)std::max<int64_t>(g->n, 1));
   W->n_rid = (int64_t)n_views << W->npad_shift;
-  if (W->n_rid > ((int64_t)1 << 32)) return fail(ctx, LGS_ERR_UNSUPPORTED, "n_views * 2^ceil(log2 n) exceeds 2^32");
+  // the compositing kernels address the per-(view, Gaussian) records (32
+  // bytes) and the per-Gaussian appearance records (40 bytes BF16, 80 FP32)
+  // by 32-bit byte offsets
+  if (W->n_rid > ((int64_t)1 << 27)) return fail(ctx, LGS_ERR_UNSUPPORTED, "n_views * 2^ceil(log2 n) exceeds 2^27");
+  if (((int64_t)(W->app_bf16 ? 40 : 80) << W->npad_shift) > ((int64_t)1 << 32))
+    return fail(ctx, LGS_ERR_UNSUPPORTED, "2^ceil(log2 n) exceeds 2^26 (BF16 appearance) or 2^25 (FP32)");
   if (W->plan.n_items > ((int64_t)1 << 31)) return fail(ctx, LGS_ERR_UNSUPPORTED, "too many pixels");
   return LGS_OK;
 }

@@ -8,7 +8,7 @@
 // tables of every order and tile size (each 8x8 block exactly once, queue
 // offsets, per-tile records consistent with the items and the queue rule),
 // and the autotuner cache file (round trip, replacement of a key, keys too
-// long for the line buffer).
+// long for the line buffer), and the size limits of the record addressing.
 #include "../../paper_2511_16144_amd/csrc/runtime.hip"
 
 #include <set>
@@ -121,6 +121,31 @@ void check_tune_cache(const char* path) {
 
 }  // namespace
 
+// The size limits of w_init: the compositing kernels address the records by
+// 32-bit byte offsets (32-byte geometry per (view, Gaussian), 40 / 80-byte
+// appearance per Gaussian); w_init makes no HIP call before these checks.
+void check_record_limits() {
+  lgs_context ctx;
+  const lgs_settings st = lgs_default_settings();
+  const std::vector<lgs_camera> cams(4, cam(64, 48));
+  auto init = [&](int64_t n, lgs_dtype dt, int views) {
+    lgs_gaussians g;
+    memset(&g, 0, sizeof g);
+    g.n = n;
+    g.appearance_dtype = dt;
+    g.feat_dim = 16;
+    Work W;
+    return w_init(&W, &ctx, &st, &g, views, cams.data(), nullptr);
+  };
+  const int64_t e25 = (int64_t)1 << 25, e26 = (int64_t)1 << 26;
+  CHECK(init(e25, LGS_F32, 1) == LGS_OK);                      // 80 B x 2^25 < 2^32
+  CHECK(init(e25 + 1, LGS_F32, 1) == LGS_ERR_UNSUPPORTED);     // 80 B x 2^26
+  CHECK(init(e26, LGS_BF16, 2) == LGS_OK);                     // 40 B x 2^26; 2 x 2^26 = 2^27 records
+  CHECK(init(e26 + 1, LGS_BF16, 1) == LGS_ERR_UNSUPPORTED);    // 40 B x 2^27
+  CHECK(init(e26, LGS_BF16, 3) == LGS_ERR_UNSUPPORTED);        // 3 x 2^26 records > 2^27
+  CHECK(init(e25, LGS_F32, 4) == LGS_OK);                      // 4 x 2^25 = 2^27 records
+}
+
 extern "C" int lgs_host_selftest(const char* tmp_path) {
   g_fail = 0;
   const std::vector<std::vector<lgs_camera>> sets = {
@@ -135,5 +160,6 @@ extern "C" int lgs_host_selftest(const char* tmp_path) {
     for (int tile : {8, 16, 32})
       for (bool spatial : {false, true}) check_items(cs, tile, spatial);
   check_tune_cache(tmp_path);
+  check_record_limits();
   return g_fail;
 }
