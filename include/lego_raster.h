@@ -263,6 +263,29 @@ lgs_status lgs_decoder_l1(lgs_context *ctx, int32_t width, int32_t height,
                           float w_feat, float *grad_feat, float *grad_weight,
                           float *grad_bias, float *loss, hipStream_t stream);
 
+/* The loss of lgs_decoder_l1 over several views in one launch: the sum over
+ * views v of w_feat * mean over C x height[v] x width[v] of |Z_v - F_gt,v|
+ * (each view normalised by its own size, as the per-view Eq. (2) terms are
+ * summed over the views of a step), with the shared weight and bias.
+ *   width, height  host int32 [n_views], each >= 1
+ *   feat, target, grad_feat   host arrays of n_views device pointers, the
+ *                  per-view planes of lgs_decoder_l1 (grad_feat[v] = dL/dF_v,
+ *                  overwritten)
+ *   grad_weight, grad_bias, loss   as in lgs_decoder_l1, summed over views
+ * The host arrays are read during the call only.  Results equal the sums of
+ * lgs_decoder_l1 over the views up to FP32 summation order.  n_views 1..16
+ * (LGS_ERR_UNSUPPORTED above 16, LGS_ERR_INVALID_ARG below 1); otherwise the
+ * errors of lgs_decoder_l1, for every view. */
+lgs_status lgs_decoder_l1_views(lgs_context *ctx, int32_t n_views,
+                                const int32_t *width, const int32_t *height,
+                                int32_t out_dim, const float *const *feat,
+                                const float *weight, const float *bias,
+                                const void *const *target,
+                                lgs_dtype target_dtype, float w_feat,
+                                float *const *grad_feat, float *grad_weight,
+                                float *grad_bias, float *loss,
+                                hipStream_t stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * computation as lgs_decoder_l1, same arguments and results (the same

@@ -65,7 +65,7 @@ class lgs_counts(C.Structure):
 
 EXPORTS = ["lgs_status_string", "lgs_last_error", "lgs_default_settings", "lgs_context_create",
            "lgs_context_destroy", "lgs_forward", "lgs_backward", "lgs_backward_l1", "lgs_loss", "lgs_decoder_l1",
-           "lgs_decoder_l1_noalloc",
+           "lgs_decoder_l1_views", "lgs_decoder_l1_noalloc",
            "lgs_default_prune_params", "lgs_prune",
            "lgs_state_counts",
            "lgs_state_stage_ms",
@@ -105,6 +105,10 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     lib.lgs_decoder_l1.restype = C.c_int
     lib.lgs_decoder_l1.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, P, P, P, P, C.c_int32, C.c_float,
                                    P, P, P, P, P]
+    lib.lgs_decoder_l1_views.restype = C.c_int
+    lib.lgs_decoder_l1_views.argtypes = [P, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32,
+                                         C.POINTER(P), P, P, C.POINTER(P), C.c_int32, C.c_float, C.POINTER(P),
+                                         P, P, P, P]
     lib.lgs_decoder_l1_noalloc.restype = C.c_int
     lib.lgs_decoder_l1_noalloc.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, P, P, P, P, C.c_int32,
                                            C.c_float, P, P, P, P, P]
@@ -333,6 +337,45 @@ class Context:
         if st != LGS_OK:
             self._raise(st)
         return loss, gf, gw, gb
+
+    def decoder_l1_views(self, feats, weight, bias, targets, w_feat: float = 1.0, stream=None, out=None):
+        """The decoder loss summed over views in one launch
+        (lgs_decoder_l1_views): feats / targets lists of per-view tensors as
+        for decoder_l1 (sizes may differ between views, the targets share one
+        dtype).  Returns (loss [1], [grad_feat per view], grad_weight,
+        grad_bias)."""
+        nv = len(feats)
+        if nv != len(targets) or nv < 1:
+            raise ValueError("feats and targets: one tensor per view, at least one view")
+        Cd = weight.shape[0]
+        for t, shp, name in ((weight, (Cd, 16), "weight"), (bias, (Cd,), "bias")):
+            if tuple(t.shape) != shp or t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+                raise ValueError(f"{name}: expected contiguous FP32 CUDA tensor of shape {shp}")
+        tdt = targets[0].dtype
+        for v, (f, tg) in enumerate(zip(feats, targets)):
+            if (f.dim() != 3 or f.shape[0] != 16 or f.dtype != torch.float32 or not f.is_cuda
+                    or not f.is_contiguous()):
+                raise ValueError(f"feats[{v}]: expected contiguous FP32 CUDA tensor [16, H, W]")
+            if (tuple(tg.shape) != (Cd,) + tuple(f.shape[1:]) or tg.dtype != tdt
+                    or tdt not in (torch.float32, torch.bfloat16) or not tg.is_cuda or not tg.is_contiguous()):
+                raise ValueError(f"targets[{v}]: expected contiguous CUDA tensor [{Cd}, H, W], "
+                                 "BF16 or FP32 like targets[0]")
+        dev = weight.device
+        if out is None:
+            out = (torch.empty(1, device=dev), [torch.empty_like(f) for f in feats], torch.empty_like(weight),
+                   torch.empty_like(bias))
+        loss, gfs, gw, gb = out
+        ws = (C.c_int32 * nv)(*[int(f.shape[2]) for f in feats])
+        hs = (C.c_int32 * nv)(*[int(f.shape[1]) for f in feats])
+        fp = (C.c_void_p * nv)(*[_ptr(f) for f in feats])
+        tp = (C.c_void_p * nv)(*[_ptr(t) for t in targets])
+        gp = (C.c_void_p * nv)(*[_ptr(g) for g in gfs])
+        dt = LGS_BF16 if tdt == torch.bfloat16 else LGS_F32
+        st = lib().lgs_decoder_l1_views(self._h, nv, ws, hs, Cd, fp, _ptr(weight), _ptr(bias), tp, dt,
+                                        float(w_feat), gp, _ptr(gw), _ptr(gb), _ptr(loss), _stream(stream))
+        if st != LGS_OK:
+            self._raise(st)
+        return loss, gfs, gw, gb
 
     def prune(self, params, k=None, tau_dist=None, tau_sim=None, min_opacity=None, max_scale=None,
               stream=None, mask=None):

@@ -102,8 +102,7 @@ __device__ __forceinline__ void unpack4(const F8& v, int h, float t[4]) {
 }
 
 template <typename TT, int NT>   // NT: 16-channel tiles per wave (C = 16 NT kDecWaves, NT >= 2)
-__global__ __launch_bounds__(kDecThreads) void k_decoder(DecArgs a, const TT* __restrict__ target,
-                                                         float* __restrict__ part) {
+__global__ __launch_bounds__(kDecThreads) void k_decoder(DecArgs a, float* __restrict__ part) {
   constexpr int Cw = 16 * NT;             // channels per wave
   constexpr int KS = Cw / 32;             // 32-channel steps of the dF product
   static_assert(KS >= 1, "at least 32 channels per wave");
@@ -127,8 +126,17 @@ __global__ __launch_bounds__(kDecThreads) void k_decoder(DecArgs a, const TT* __
 
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int r16 = lane & 15, q4 = lane >> 4;
-  const int64_t n = a.n;
   const int c0 = w * Cw;   // first channel of this wave
+  // the view of this work-group (views own consecutive runs of work-groups)
+  int vi = 0;
+  for (int u = 1; u < a.n_views; ++u)
+    if ((int)blockIdx.x >= a.v[u].g0) vi = u;
+  const int64_t n = a.v[vi].n;
+  const float* __restrict__ feat = a.v[vi].feat;
+  const TT* __restrict__ target = (const TT*)a.v[vi].target;
+  float* __restrict__ grad_feat = a.v[vi].grad_feat;
+  const float scale = a.v[vi].scale;
+  const bool vec = a.v[vi].vec != 0;
 
   // W is staged in LDS once (over the sign rows, unused until the first
   // chunk's first barrier), then every wave builds its operands from there
@@ -210,19 +218,20 @@ __global__ __launch_bounds__(kDecThreads) void k_decoder(DecArgs a, const TT* __
   auto fetch = [&](int64_t ck, RawT (&trs)[NT], float& frs) {
     const int64_t p0 = ck * kChunk;
     const bool full = p0 + kChunk <= n;
-    frs = p0 + fpx < n ? a.feat[(size_t)fk * n + p0 + fpx] : 0.f;
+    frs = p0 + fpx < n ? feat[(size_t)fk * n + p0 + fpx] : 0.f;
     const int64_t pp = p0 + 8 * q4;
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
       const TT* tp = target + (size_t)(c0 + 16 * nt + r16) * n + pp;
-      trs[nt] = load_raw8(tp, full && a.vec, n - pp);
+      trs[nt] = load_raw8(tp, full && vec, n - pp);
     }
   };
-  // each work-group takes a contiguous run of chunks, so the two halves of
-  // a 128-byte target line are read by the same work-group one chunk apart
+  // each work-group takes a contiguous run of its view's chunks, so the two
+  // halves of a 128-byte target line are read by the same work-group one
+  // chunk apart
   const int64_t n_chunks = (n + kChunk - 1) / kChunk;
-  const int64_t per = (n_chunks + gridDim.x - 1) / gridDim.x;
-  const int64_t ck0 = (int64_t)blockIdx.x * per;
+  const int64_t per = (n_chunks + a.v[vi].groups - 1) / a.v[vi].groups;
+  const int64_t ck0 = (int64_t)((int)blockIdx.x - a.v[vi].g0) * per;
   const int64_t ck1 = ck0 + per < n_chunks ? ck0 + per : n_chunks;
   // chunk pc's dL/dF: the 8 waves' partials (buffer par) summed in a fixed order
   auto store_df = [&](int64_t pc, int par) {
@@ -232,7 +241,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decoder(DecArgs a, const TT* __
       float v = 0.f;
 #pragma unroll
       for (int u = 0; u < kDecWaves; ++u) v += dfr[par][(u * 16 + k) * kChunk + px];
-      if (q0 + px < n) a.grad_feat[(size_t)k * n + q0 + px] = a.scale * v;
+      if (q0 + px < n) grad_feat[(size_t)k * n + q0 + px] = scale * v;
     }
   };
   // one chunk; its inputs are in (cur, frc), which are refilled with chunk
@@ -341,17 +350,19 @@ __global__ __launch_bounds__(kDecThreads) void k_decoder(DecArgs a, const TT* __
   lds_barrier();
   if (ck1 > ck0) store_df(ck1 - 1, (int)((ck1 - 1 - ck0) & 1));
 
-  // partials of this work-group: dW [C][16], db [C], loss
+  // partials of this work-group, times its view's loss scale: dW [C][16],
+  // db [C], loss
   float* pb = part + (size_t)blockIdx.x * a.part_stride;
 #pragma unroll
   for (int nt = 0; nt < NT; ++nt) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) pb[(size_t)(c0 + 16 * nt + r16) * 16 + 4 * q4 + i] = dw[nt][i];
+    for (int i = 0; i < 4; ++i) pb[(size_t)(c0 + 16 * nt + r16) * 16 + 4 * q4 + i] = scale * dw[nt][i];
     int s = db[nt];
     s += __shfl_xor(s, 16);
     s += __shfl_xor(s, 32);
-    if (q4 == 0) pb[(size_t)a.C * 16 + c0 + 16 * nt + r16] = (float)s;
+    if (q4 == 0) pb[(size_t)a.C * 16 + c0 + 16 * nt + r16] = scale * (float)s;
   }
+  lsum *= scale;
   for (int o = 32; o > 0; o >>= 1) lsum += __shfl_xor(lsum, o);
   if (lane == 0) red[w] = lsum;
   __syncthreads();
@@ -398,40 +409,66 @@ __global__ __launch_bounds__(64 * kRedGroups) void k_decoder_reduce(DecArgs a, c
 #pragma unroll
   for (int u = 0; u < kRedGroups; ++u) s += red[u][o];
   if (i < (int64_t)a.C * 16) {
-    a.grad_weight[i] = (float)(a.scale * s);
+    a.grad_weight[i] = (float)s;
   } else if (i < (int64_t)a.C * 17) {
-    a.grad_bias[i - (int64_t)a.C * 16] = (float)(a.scale * s);
+    a.grad_bias[i - (int64_t)a.C * 16] = (float)s;
   } else if (a.loss) {
-    *a.loss = (float)(a.scale * s);
+    *a.loss = (float)s;
   }
 }
 
 template <typename TT>
-void launch_t(const DecArgs& a, const void* target, float* part, int grid, hipStream_t s) {
-  const TT* tp = (const TT*)target;
+void launch_t(const DecArgs& a, float* part, int grid, hipStream_t s) {
   if (a.C == 256)
-    hipLaunchKernelGGL((k_decoder<TT, 2>), dim3(grid), dim3(kDecThreads), 0, s, a, tp, part);
+    hipLaunchKernelGGL((k_decoder<TT, 2>), dim3(grid), dim3(kDecThreads), 0, s, a, part);
   else
-    hipLaunchKernelGGL((k_decoder<TT, 4>), dim3(grid), dim3(kDecThreads), 0, s, a, tp, part);
+    hipLaunchKernelGGL((k_decoder<TT, 4>), dim3(grid), dim3(kDecThreads), 0, s, a, part);
 }
 
 }  // namespace
 
 bool decoder_dim_ok(int C) { return C == 256 || C == 512; }
 
-int decoder_grid(int64_t n) {
+int decoder_assign(DecArgs& a, int cap) {
   int dev = 0, cus = 256;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  const int64_t chunks = (n + kChunk - 1) / kChunk;
-  int64_t g = (int64_t)cus;   // one 8-wave work-group per CU
-  if (g > chunks) g = chunks;
-  return (int)(g > 0 ? g : 1);
+  const int budget = cus < cap ? cus : cap;   // one 8-wave work-group per CU
+  int64_t ch[kDecMaxViews];
+  int g[kDecMaxViews], total = 0;
+  for (int v = 0; v < a.n_views; ++v) {
+    ch[v] = (a.v[v].n + kChunk - 1) / kChunk;
+    g[v] = 1;
+    ++total;
+  }
+  // each further work-group goes to the view whose work-groups have the
+  // most chunks each (the first such view), while it has chunks to spare
+  while (total < budget) {
+    int best = -1;
+    int64_t most = 0;
+    for (int v = 0; v < a.n_views; ++v) {
+      const int64_t per = (ch[v] + g[v] - 1) / g[v];
+      if (g[v] < ch[v] && per > most) {
+        most = per;
+        best = v;
+      }
+    }
+    if (best < 0) break;
+    ++g[best];
+    ++total;
+  }
+  int g0 = 0;
+  for (int v = 0; v < a.n_views; ++v) {
+    a.v[v].g0 = g0;
+    a.v[v].groups = g[v];
+    g0 += g[v];
+  }
+  return g0;
 }
 
-void launch_decoder(const DecArgs& a, const void* target, int target_bf16, float* part, int grid, hipStream_t s) {
-  if (target_bf16) launch_t<unsigned short>(a, target, part, grid, s);
-  else launch_t<float>(a, target, part, grid, s);
+void launch_decoder(const DecArgs& a, int target_bf16, float* part, int grid, hipStream_t s) {
+  if (target_bf16) launch_t<unsigned short>(a, part, grid, s);
+  else launch_t<float>(a, part, grid, s);
   const int64_t m = (int64_t)a.C * 17 + 1;
   hipLaunchKernelGGL(k_decoder_reduce, dim3((unsigned)((m + 63) / 64)), dim3(64 * kRedGroups), 0, s, a, part,
                      grid);

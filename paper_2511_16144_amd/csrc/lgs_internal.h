@@ -232,21 +232,36 @@ void launch_loss_df(const LossView* views, int n_views, int64_t n_blocks, float2
 void launch_loss_terms(const LossView* views, int n_views, int ssim, const float2* part_rgb,
                        const float2* part_df, float* terms, hipStream_t s);
 
-// feature decoder (1x1 convolution 16 -> C) and its L1 distillation loss:
-// dL/dF, dL/dW, dL/db and the loss; part holds grid x part_stride floats of
-// per-work-group partial sums (dW [C][16], db [C], loss)
-struct DecArgs {
-  const float *feat, *weight, *bias;   // F [16][n], W [C][16], b [C]
-  float *grad_feat, *grad_weight, *grad_bias, *loss;
+// feature decoder (1x1 convolution 16 -> C) and its L1 distillation loss
+// over one or more views (each view's loss normalised by its own C H W, the
+// views' losses summed): dL/dF per view, dL/dW, dL/db and the loss.  Every
+// work-group works on one view's chunks; part holds grid x part_stride
+// floats of per-work-group partial sums (dW [C][16], db [C], loss), already
+// times the view's scale
+constexpr int kDecMaxViews = 16;
+struct DecView {
+  const float* feat;                   // F [16][n]
+  const void* target;                  // F* [C][n], BF16 or FP32
+  float* grad_feat;                    // dL/dF [16][n]
   int64_t n;                           // pixels
+  float scale;                         // w_feat / (C n)
+  int32_t vec;                         // targets allow 8-element vector loads (n % 8 == 0, 16-B base)
+  int32_t g0, groups;                  // its work-groups g0 .. g0 + groups - 1 (decoder_assign)
+};
+struct DecArgs {
+  const float *weight, *bias;          // W [C][16], b [C]
+  float *grad_weight, *grad_bias, *loss;
   int64_t part_stride;                 // >= 17 C + 1
   int32_t C;                           // 256 or 512
-  int32_t vec;                         // targets allow 8-element vector loads (n % 8 == 0, 16-B base)
-  float scale;                         // w_feat / (C n)
+  int32_t n_views;                     // 1 .. kDecMaxViews
+  DecView v[kDecMaxViews];
 };
 bool decoder_dim_ok(int C);
-int decoder_grid(int64_t n);
-void launch_decoder(const DecArgs& a, const void* target, int target_bf16, float* part, int grid, hipStream_t s);
+// shares out the work-groups of the launch among the views (at most one per
+// CU and at most `cap` in all, unless there are more views; at least one per
+// view, at most one per 32-pixel chunk) and returns the grid
+int decoder_assign(DecArgs& a, int cap);
+void launch_decoder(const DecArgs& a, int target_bf16, float* part, int grid, hipStream_t s);
 
 // language-guided pruning (K nearest neighbours in a uniform grid of cell
 // side tau_dist) and the geometric criteria

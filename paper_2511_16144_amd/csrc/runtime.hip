@@ -1092,31 +1092,68 @@ lgs_status lgs_loss(lgs_context* ctx, int32_t n_views, const lgs_camera* cams, i
   return LGS_OK;
 }
 
-// Validation and launch arguments shared by the two decoder entry points.
-static lgs_status decoder_args(lgs_context* ctx, int32_t width, int32_t height, int32_t out_dim, const float* feat,
-                               const float* weight, const float* bias, const void* target, lgs_dtype target_dtype,
-                               float w_feat, float* grad_feat, float* grad_weight, float* grad_bias, float* loss,
+// Validation and launch arguments shared by the decoder entry points: views
+// v < n_views of width[v] x height[v] pixels, with their planes feat[v],
+// target[v], grad_feat[v].
+static lgs_status decoder_args(lgs_context* ctx, int32_t n_views, const int32_t* width, const int32_t* height,
+                               int32_t out_dim, const float* const* feat, const float* weight, const float* bias,
+                               const void* const* target, lgs_dtype target_dtype, float w_feat,
+                               float* const* grad_feat, float* grad_weight, float* grad_bias, float* loss,
                                DecArgs* a) {
-  if (width < 1 || height < 1) return fail(ctx, LGS_ERR_INVALID_ARG, "width and height must be >= 1");
-  const int64_t n = (int64_t)width * height;
-  if (n > ((int64_t)1 << 31)) return fail(ctx, LGS_ERR_UNSUPPORTED, "more than 2^31 pixels");
+  if (n_views < 1 || n_views > kDecMaxViews)
+    return fail(ctx, n_views < 1 ? LGS_ERR_INVALID_ARG : LGS_ERR_UNSUPPORTED,
+                "n_views must be 1 .. " + std::to_string(kDecMaxViews));
+  if (!width || !height || !feat || !target || !grad_feat) return fail(ctx, LGS_ERR_INVALID_ARG, "NULL view array");
   if (!decoder_dim_ok(out_dim)) return fail(ctx, LGS_ERR_UNSUPPORTED, "out_dim must be 256 or 512");
   if (target_dtype != LGS_F32 && target_dtype != LGS_BF16)
     return fail(ctx, LGS_ERR_INVALID_ARG, "unknown target dtype");
   if (!isfinite(w_feat)) return fail(ctx, LGS_ERR_INVALID_ARG, "non-finite w_feat");
-  if (!feat || !weight || !bias || !target || !grad_feat || !grad_weight || !grad_bias)
-    return fail(ctx, LGS_ERR_INVALID_ARG, "NULL array");
-  if (!aligned4(feat) || !aligned4(weight) || !aligned4(bias) || !aligned4(grad_feat) || !aligned4(grad_weight) ||
-      !aligned4(grad_bias) || (loss && !aligned4(loss)) ||
-      ((uintptr_t)target & (target_dtype == LGS_BF16 ? 1u : 3u)) != 0)
+  if (!weight || !bias || !grad_weight || !grad_bias) return fail(ctx, LGS_ERR_INVALID_ARG, "NULL array");
+  if (!aligned4(weight) || !aligned4(bias) || !aligned4(grad_weight) || !aligned4(grad_bias) ||
+      (loss && !aligned4(loss)))
     return fail(ctx, LGS_ERR_INVALID_ARG, "misaligned array");
-  a->feat = feat; a->weight = weight; a->bias = bias;
-  a->grad_feat = grad_feat; a->grad_weight = grad_weight; a->grad_bias = grad_bias; a->loss = loss;
-  a->n = n;
+  memset(a, 0, sizeof *a);
+  a->weight = weight; a->bias = bias;
+  a->grad_weight = grad_weight; a->grad_bias = grad_bias; a->loss = loss;
   a->part_stride = ((17 * (int64_t)out_dim + 1 + 63) / 64) * 64;
   a->C = out_dim;
-  a->vec = n % 8 == 0 && ((uintptr_t)target & 15u) == 0;
-  a->scale = (float)((double)w_feat / ((double)out_dim * (double)n));
+  a->n_views = n_views;
+  for (int v = 0; v < n_views; ++v) {
+    if (width[v] < 1 || height[v] < 1) return fail(ctx, LGS_ERR_INVALID_ARG, "width and height must be >= 1");
+    const int64_t n = (int64_t)width[v] * height[v];
+    if (n > ((int64_t)1 << 31)) return fail(ctx, LGS_ERR_UNSUPPORTED, "more than 2^31 pixels");
+    if (!feat[v] || !target[v] || !grad_feat[v]) return fail(ctx, LGS_ERR_INVALID_ARG, "NULL array");
+    if (!aligned4(feat[v]) || !aligned4(grad_feat[v]) ||
+        ((uintptr_t)target[v] & (target_dtype == LGS_BF16 ? 1u : 3u)) != 0)
+      return fail(ctx, LGS_ERR_INVALID_ARG, "misaligned array");
+    DecView& d = a->v[v];
+    d.feat = feat[v];
+    d.target = target[v];
+    d.grad_feat = grad_feat[v];
+    d.n = n;
+    d.scale = (float)((double)w_feat / ((double)out_dim * (double)n));
+    d.vec = n % 8 == 0 && ((uintptr_t)target[v] & 15u) == 0;
+  }
+  return LGS_OK;
+}
+
+// The allocating entry points: partial sums in the context's buffer, grown
+// when a call needs more.
+static lgs_status decoder_run(lgs_context* ctx, DecArgs& a, lgs_dtype target_dtype, hipStream_t stream) {
+  HIP_TRY(ctx, hipSetDevice(ctx->device));
+  (void)hipGetLastError();   // launch checks below see only this call's errors
+  const int grid = decoder_assign(a, INT32_MAX);
+  const int64_t need = (int64_t)grid * a.part_stride;
+  if (need > ctx->dec_part_cap) {
+    HIP_TRY(ctx, hipDeviceSynchronize());   // earlier calls may still use the old buffer
+    if (ctx->dec_part) hipFree(ctx->dec_part);
+    ctx->dec_part = nullptr;
+    ctx->dec_part_cap = 0;
+    HIP_TRY(ctx, hipMalloc((void**)&ctx->dec_part, sizeof(float) * need));
+    ctx->dec_part_cap = need;
+  }
+  launch_decoder(a, target_dtype == LGS_BF16, ctx->dec_part, grid, stream);
+  HIP_TRY(ctx, hipGetLastError());
   return LGS_OK;
 }
 
@@ -1127,24 +1164,24 @@ lgs_status lgs_decoder_l1(lgs_context* ctx, int32_t width, int32_t height, int32
   if (!ctx) return LGS_ERR_INVALID_ARG;
   ctx->err.clear();
   DecArgs a;
-  lgs_status rc = decoder_args(ctx, width, height, out_dim, feat, weight, bias, target, target_dtype, w_feat,
-                               grad_feat, grad_weight, grad_bias, loss, &a);
+  lgs_status rc = decoder_args(ctx, 1, &width, &height, out_dim, &feat, weight, bias, &target, target_dtype,
+                               w_feat, &grad_feat, grad_weight, grad_bias, loss, &a);
   if (rc != LGS_OK) return rc;
-  HIP_TRY(ctx, hipSetDevice(ctx->device));
-  (void)hipGetLastError();   // launch checks below see only this call's errors
-  const int grid = decoder_grid(a.n);
-  const int64_t need = (int64_t)grid * a.part_stride;
-  if (need > ctx->dec_part_cap) {
-    HIP_TRY(ctx, hipDeviceSynchronize());   // earlier calls may still use the old buffer
-    if (ctx->dec_part) hipFree(ctx->dec_part);
-    ctx->dec_part = nullptr;
-    ctx->dec_part_cap = 0;
-    HIP_TRY(ctx, hipMalloc((void**)&ctx->dec_part, sizeof(float) * need));
-    ctx->dec_part_cap = need;
-  }
-  launch_decoder(a, target, target_dtype == LGS_BF16, ctx->dec_part, grid, stream);
-  HIP_TRY(ctx, hipGetLastError());
-  return LGS_OK;
+  return decoder_run(ctx, a, target_dtype, stream);
+}
+
+lgs_status lgs_decoder_l1_views(lgs_context* ctx, int32_t n_views, const int32_t* width, const int32_t* height,
+                                int32_t out_dim, const float* const* feat, const float* weight, const float* bias,
+                                const void* const* target, lgs_dtype target_dtype, float w_feat,
+                                float* const* grad_feat, float* grad_weight, float* grad_bias, float* loss,
+                                hipStream_t stream) {
+  if (!ctx) return LGS_ERR_INVALID_ARG;
+  ctx->err.clear();
+  DecArgs a;
+  lgs_status rc = decoder_args(ctx, n_views, width, height, out_dim, feat, weight, bias, target, target_dtype,
+                               w_feat, grad_feat, grad_weight, grad_bias, loss, &a);
+  if (rc != LGS_OK) return rc;
+  return decoder_run(ctx, a, target_dtype, stream);
 }
 
 lgs_status lgs_decoder_l1_noalloc(lgs_context* ctx, int32_t width, int32_t height, int32_t out_dim,
@@ -1154,13 +1191,13 @@ lgs_status lgs_decoder_l1_noalloc(lgs_context* ctx, int32_t width, int32_t heigh
   if (!ctx) return LGS_ERR_INVALID_ARG;
   ctx->err.clear();
   DecArgs a;
-  lgs_status rc = decoder_args(ctx, width, height, out_dim, feat, weight, bias, target, target_dtype, w_feat,
-                               grad_feat, grad_weight, grad_bias, loss, &a);
+  lgs_status rc = decoder_args(ctx, 1, &width, &height, out_dim, &feat, weight, bias, &target, target_dtype,
+                               w_feat, &grad_feat, grad_weight, grad_bias, loss, &a);
   if (rc != LGS_OK) return rc;
   if (!ctx->scratch) return fail(ctx, LGS_ERR_STATE, "no scratch address for this context's device");
   HIP_TRY(ctx, hipSetDevice(ctx->device));
   (void)hipGetLastError();   // launch checks below see only this call's errors
-  const int grid = std::min(decoder_grid(a.n), kScratchGroups);
+  const int grid = decoder_assign(a, kScratchGroups);   // one view: at most kScratchGroups
   const int64_t need = (int64_t)grid * a.part_stride;
   if (need > kScratchFloats)
     return fail(ctx, LGS_ERR_CAPACITY, "decoder partial sums need " + std::to_string(need) +
@@ -1168,7 +1205,7 @@ lgs_status lgs_decoder_l1_noalloc(lgs_context* ctx, int32_t width, int32_t heigh
                                            std::to_string(kScratchFloats));
   // every work-group writes its whole partial row before the reduction
   // reads it, so nothing left by an earlier call needs clearing
-  launch_decoder(a, target, target_dtype == LGS_BF16, ctx->scratch, grid, stream);
+  launch_decoder(a, target_dtype == LGS_BF16, ctx->scratch, grid, stream);
   HIP_TRY(ctx, hipGetLastError());
   return LGS_OK;
 }
