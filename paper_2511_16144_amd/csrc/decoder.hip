@@ -198,6 +198,18 @@ __global__ __launch_bounds__(kDecThreads) void k_decoder(DecArgs a, float* __res
     dw[nt] = (f32x4){0.f, 0.f, 0.f, 0.f};
     db[nt] = 0;
   }
+  // BF16 targets: for Z^T row m of column group cg (pixel 8 (m / 4) + 4 cg
+  // + m % 4) the A row that is -1 at that pixel's K index and 0 elsewhere;
+  // lane (r16, q4) holds K indices 8 q4 .. 8 q4 + 7 of row r16
+  constexpr bool kTsel = sizeof(TT) == 2;
+  bf16x8_t tsel[2];
+#pragma unroll
+  for (int cg = 0; cg < 2; ++cg) {
+    u16x8 v;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = ((r16 >> 2) == q4 && j == 4 * cg + (r16 & 3)) ? (unsigned short)0xBF80u : 0;
+    tsel[cg] = as_bf16x8(v);
+  }
   float lsum = 0.f;
 
   // The targets and feature element of the next kDecPF chunks are loaded
@@ -278,31 +290,41 @@ __global__ __launch_bounds__(kDecThreads) void k_decoder(DecArgs a, float* __res
 #pragma unroll
       for (int nt = 0; nt < NT; ++nt) {
         f32x4 z = {bias[nt], bias[nt], bias[nt], bias[nt]};
+        // BF16 targets enter the product as they are: the selector rows of
+        // -1 pick each row's own target (one non-zero product, exact), so
+        // the tile comes out as Z - T
+        if constexpr (kTsel) z = mfma(tsel[cg], __builtin_bit_cast(bf16x8_t, cur[nt]), z);
         z = mfma(af, bz1[nt], z);
         z = mfma(af, bz2[nt], z);
         float tv[4];
-        unpack4(cur[nt], cg, tv);
-        unsigned short sg[4];
+        if constexpr (!kTsel) unpack4(cur[nt], cg, tv);
+        uint32_t sb[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const bool valid = kFull || pl + i < lim;
-          const float d = z[i] - tv[i];
-          // Z is never -0 (its sum starts from the bias plus +0) and a
-          // difference of equal values is +0, so d is never -0: its bits as a
-          // signed integer are > 0, 0 or < 0 as d is, and their clamp to
-          // [-1, 1] (one v_med3_i32) is the sign of d
-          int si;
-          asm("v_med3_i32 %0, %1, -1, 1" : "=v"(si) : "v"(__float_as_uint(d)));
-          if (!kFull) si = valid ? si : 0;
+          const float d = kTsel ? z[i] : z[i] - tv[i];
+          // Z is never -0 (its sum starts from the bias plus +0, and a sum
+          // of +0 and -0 is +0), so d is never -0: its bits as a signed
+          // integer are > 0, 0 or < 0 as d is, and their clamp to [-1, 1]
+          // (one v_med3_i32) is the sign of d
           lsum += valid ? fabsf(d) : 0.f;
+          int si;
+          // d may come straight from a matrix-core result, which a vector
+          // instruction may read only some cycles after it is written: the
+          // compiler pads its own readers but not an asm statement, so the
+          // clamp takes the loss sum (a compiler read of d) as an operand
+          // and is issued after it
+          asm("v_med3_i32 %0, %1, -1, 1" : "=v"(si) : "v"(__float_as_uint(d)), "v"(lsum));
+          if (!kFull) si = valid ? si : 0;
           db[nt] += si;
-          const float s = (float)si;
-          sg[i] = (unsigned short)(__float_as_uint(s) >> 16);   // -1, 0, 1: exact in BF16
-          rP[w][(pl + i) * kRP + rp_col(pl + i, 16 * nt + r16)] = sg[i];
+          // -1, 0, 1 as FP32: the high half is the same value in BF16 (the
+          // store of that half alone is one ds_write_b16_d16_hi)
+          sb[i] = __float_as_uint((float)si);
+          rP[w][(pl + i) * kRP + rp_col(pl + i, 16 * nt + r16)] = (unsigned short)(sb[i] >> 16);
         }
         uint2 packed;
-        packed.x = (uint32_t)sg[0] | ((uint32_t)sg[1] << 16);
-        packed.y = (uint32_t)sg[2] | ((uint32_t)sg[3] << 16);
+        packed.x = __builtin_amdgcn_perm(sb[1], sb[0], 0x07060302u);
+        packed.y = __builtin_amdgcn_perm(sb[3], sb[2], 0x07060302u);
         *(uint2*)(&rC[w][(16 * nt + r16) * kRC + pl]) = packed;
       }
     }
