@@ -200,7 +200,8 @@ void launch_raster_fwd(const Settings& st, const ViewDesc* views, const ViewImag
                        const uint2* ranges, const uint32_t* vals, const GeomRec* geom,
                        const void* app, int app_bf16, uint32_t npad_mask,
                        const uint32_t* items, const uint32_t* qoff, int64_t n_items, Counters* cnt,
-                       int waves_per_group, int32_t* last_idx, float* T_state, hipStream_t s);
+                       int waves_per_group, int32_t* last_idx, float* T_state, int n_contrib,
+                       hipStream_t s);   // n_contrib: some view's out table asks for contributor counts
 // Upstream of the backward compositing kernel: dL/dY given per channel
 // (upstream), the L1 loss gradient formed from the forward's images and the
 // targets (loss_w), or the colour channels given and depth + features from

@@ -205,7 +205,9 @@ constexpr int kFwdWaveLds = (kFwdYRows + kFwdY + 3 * kFwdW) * 2;
 // appearance: seven (72 VGPRs), so that a batch's weight operands stay in
 // registers across its five channel blocks (faster than eight waves that
 // re-read them).
-template <bool BF16, bool CNT>
+// NC: per-pixel contributor counts are written (a caller asked for them);
+// without them the entry loop keeps no count.
+template <bool BF16, bool CNT, bool NC>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ? 7 : 8, BF16 ? 7 : 8))) k_raster_fwd(
     Settings st, const ViewDesc* __restrict__ views, const ViewImages* __restrict__ out,
     const uint2* __restrict__ ranges, const uint32_t* __restrict__ vals,
@@ -373,7 +375,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ?
           }
           T = con ? Tn : T;
           last = con ? (int32_t)(base + j) : last;
-          ncon += con ? 1 : 0;
+          if (NC) ncon += con ? 1 : 0;
           if (BF16 && ++nb == 8) flush();
         }
         if (live == 0ull) {
@@ -410,7 +412,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF16 ?
       for (int c = 0; c < 16; ++c)
         if (c < st.nfeat) o.feat[c * HW + p] = acc[4 + c];
       o.T[p] = T;
-      if (o.n_contrib) o.n_contrib[p] = ncon;
+      if (NC && o.n_contrib) o.n_contrib[p] = ncon;
       last_idx[(size_t)V->pix_off + p] = last;
       T_state[(size_t)V->pix_off + p] = T;
     }
@@ -923,7 +925,7 @@ __global__ void __launch_bounds__(256) k_seg_reduce(const uint32_t* __restrict__
 
 }  // namespace
 
-template <bool BF16, bool CNT>
+template <bool BF16, bool CNT, bool NC>
 static void launch_fwd_t(const Settings& st, const ViewDesc* views, const ViewImages* out, const uint2* ranges,
                          const uint32_t* vals, const GeomRec* geom, const void* app, uint32_t npad_mask,
                          const uint32_t* items, const uint32_t* qoff, int64_t n_items, Counters* cnt,
@@ -934,30 +936,35 @@ static void launch_fwd_t(const Settings& st, const ViewDesc* views, const ViewIm
   hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   int occ = 1;
   const size_t lds = BF16 ? (size_t)waves_per_group * kFwdWaveLds : 0;
-  hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_raster_fwd<BF16, CNT>, threads, lds);
+  hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_raster_fwd<BF16, CNT, NC>, threads, lds);
   int64_t grid = (int64_t)cus * (occ > 0 ? occ : 1);
   const int64_t need = (n_items + waves_per_group - 1) / waves_per_group;
   if (grid > need) grid = need;
   if (grid < kQueues) grid = kQueues;   // every queue needs a workgroup (index mod kQueues) to drain it
-  hipLaunchKernelGGL((k_raster_fwd<BF16, CNT>), dim3((unsigned)grid), dim3(threads), lds, s, st, views, out,
+  hipLaunchKernelGGL((k_raster_fwd<BF16, CNT, NC>), dim3((unsigned)grid), dim3(threads), lds, s, st, views, out,
                      ranges, vals, geom, app, npad_mask, items, qoff, (uint32_t)n_items, cnt, last_idx, T_state);
 }
 
 void launch_raster_fwd(const Settings& st, const ViewDesc* views, const ViewImages* out, const uint2* ranges,
                        const uint32_t* vals, const GeomRec* geom, const void* app, int app_bf16,
                        uint32_t npad_mask, const uint32_t* items, const uint32_t* qoff, int64_t n_items,
-                       Counters* cnt, int waves_per_group, int32_t* last_idx, float* T_state, hipStream_t s) {
+                       Counters* cnt, int waves_per_group, int32_t* last_idx, float* T_state, int n_contrib,
+                       hipStream_t s) {
   if (n_items <= 0) return;
-#define LGS_FWD(B, K)                                                                                        \
-  launch_fwd_t<B, K>(st, views, out, ranges, vals, geom, app, npad_mask, items, qoff, n_items, cnt,          \
-                     waves_per_group, last_idx, T_state, s)
+#define LGS_FWD(B, K, N)                                                                                     \
+  launch_fwd_t<B, K, N>(st, views, out, ranges, vals, geom, app, npad_mask, items, qoff, n_items, cnt,       \
+                        waves_per_group, last_idx, T_state, s)
+#define LGS_FWD_N(B, K)        \
+  if (n_contrib) LGS_FWD(B, K, true); \
+  else LGS_FWD(B, K, false)
   if (app_bf16) {
-    if (st.count) LGS_FWD(true, true);
-    else LGS_FWD(true, false);
+    if (st.count) LGS_FWD_N(true, true);
+    else LGS_FWD_N(true, false);
   } else {
-    if (st.count) LGS_FWD(false, true);
-    else LGS_FWD(false, false);
+    if (st.count) LGS_FWD_N(false, true);
+    else LGS_FWD_N(false, false);
   }
+#undef LGS_FWD_N
 #undef LGS_FWD
 }
 

@@ -411,6 +411,7 @@ struct Work {
   // loss gradient (d_fo), targets (d_tgt); loss weights (4 per group)
   ViewImages *d_out = nullptr, *d_up = nullptr, *d_fo = nullptr, *d_tgt = nullptr;
   float* d_lossw = nullptr;
+  int want_ncon = 0;                         // some view of the forward's outputs asks for contributor counts
   int D = kFeatGroup, G = 1;                 // feature dimension and groups
   std::vector<void*> app_g;                  // appearance records of groups 1 ..
   float* scratch_img = nullptr;              // groups 1 ..: their RGB / depth / T outputs (discarded)
@@ -654,6 +655,8 @@ std::vector<float> group_lossw(const Work* W, const float loss_w[3]) {
 lgs_status w_upload(Work* W, const lgs_images* out, hipStream_t stream) {
   const int V = (int)W->plan.views.size();
   const std::vector<ViewImages> himg = group_tables(W, out, TAB_OUT);
+  W->want_ncon = 0;
+  for (int v = 0; v < V; ++v) W->want_ncon |= out[v].n_contrib != nullptr;
   HIP_TRY(W->ctx, upload_table(W, W->d_views, W->plan.views.data(), (size_t)V, stream));
   HIP_TRY(W->ctx, upload_table(W, W->d_out, himg.data(), himg.size(), stream));
   return LGS_OK;
@@ -718,7 +721,7 @@ void enqueue_raster_fwd(Work* W, hipStream_t s) {
     launch_raster_fwd(ds, W->d_views, W->d_out + (size_t)gi * V, W->ranges, W->pvals, W->geom,
                       gi == 0 ? W->app : W->app_g[gi - 1], W->app_bf16, (uint32_t)((1ull << W->npad_shift) - 1),
                       W->items, W->items_static + W->plan.n_items, W->plan.n_items, W->counters, W->st.chunk,
-                      W->last_idx, W->T_state, s);
+                      W->last_idx, W->T_state, gi == 0 && W->want_ncon, s);
   }
 }
 

@@ -48,9 +48,9 @@ def _kernels(asm, pattern):
 def test_persistent_compositing_loops_are_wave_uniform(tmp_path):
     asm = _asm("raster.hip", tmp_path)
     ks = _kernels(asm, "k_raster_(?:fwd|bwd)")
-    # (fwd x {f32, bf16} + bwd x {f32, bf16} x {upstream, fused L1, colour given})
-    # x {timed, counting}
-    assert len(ks) == 16
+    # (fwd x {f32, bf16} x {contributor counts, none} + bwd x {f32, bf16} x
+    # {upstream, fused L1, colour given}) x {timed, counting}
+    assert len(ks) == 20
     for name, lines in ks.items():
         bad = [l for l in lines if l.startswith("s_andn2_b64 exec, exec")]
         assert not bad, (name, bad)
