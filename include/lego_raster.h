@@ -253,9 +253,11 @@ lgs_status lgs_loss(lgs_context *ctx, int32_t n_views, const lgs_camera *cams,
  * FP32 operands split into two BF16 terms each (relative error of Z about
  * 2^-16 of |W||F|; the signs are exact).  Enqueued on `stream` (the context
  * keeps a small partial-sum buffer; calls on one context are ordered by its
- * stream).  Deterministic (fixed-order reductions).  LGS_ERR_INVALID_ARG for
- * NULL or misaligned arrays, sizes < 1 or a non-finite w_feat;
- * LGS_ERR_UNSUPPORTED for another out_dim. */
+ * stream).  Deterministic (fixed-order reductions).  Targets must be finite:
+ * BF16 targets enter a matrix product as they are, so a non-finite one turns
+ * its channel's results over its 32-pixel chunk into NaN.
+ * LGS_ERR_INVALID_ARG for NULL or misaligned arrays, sizes < 1 or a
+ * non-finite w_feat; LGS_ERR_UNSUPPORTED for another out_dim. */
 lgs_status lgs_decoder_l1(lgs_context *ctx, int32_t width, int32_t height,
                           int32_t out_dim, const float *feat,
                           const float *weight, const float *bias,
