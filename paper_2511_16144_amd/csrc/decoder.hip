@@ -13,16 +13,16 @@
 // instruction pair: A = [F_hi | F_lo] (K = 32) against B = [W_hi ; W_hi], then
 // A against [W_lo ; W_lo], i.e. all four products of the split operands.
 //
-// Work-group = 8 waves (two per SIMD: one wave's target loads overlap the
-// other's matrix products); a work-group walks a contiguous run of 32-pixel
-// chunks of the image (a fixed assignment, so its partial sums are
-// deterministic), loading the next chunk's inputs while it works on one,
-// with one work-group barrier per chunk.  Wave w owns the channels
-// [C/8 w, C/8 (w+1)): per chunk it
+// Work-group = 16 waves of 32 channels for C = 512 (four per SIMD, 128
+// VGPRs each), 8 waves of 32 channels for C = 256; a work-group walks a
+// contiguous run of 32-pixel chunks of one view (a fixed assignment, so its
+// partial sums are deterministic), loading the next chunk's inputs while it
+// works on one, with one work-group barrier per chunk.  Wave w owns the
+// channels [32 w, 32 (w+1)): per chunk it
 // forms its Z^T tiles (16 pixels x 16 channels; the pixel order of the rows
 // gives lane l 8 consecutive pixels of one channel over the chunk's two
 // column groups, so its targets are one 16-byte load per channel), the
-// signs, its share of dL/dF (summed over the 8 waves through LDS) and its
+// signs, its share of dL/dF (summed over the waves through LDS) and its
 // rows of dL/dW and dL/db (kept in registers over all chunks).  A second
 // kernel adds the work-groups' partials in a fixed order.
 #include "lgs_internal.h"
@@ -36,10 +36,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int kDecWaves = 8;
-constexpr int kDecThreads = 64 * kDecWaves;
 constexpr int kChunk = 32;            // pixels per chunk
-constexpr int kDecPF = 3;             // chunks whose inputs are in flight
 constexpr int kFA = 40;               // LDS pitch (u16) of the [pixel][k] F rows (80 B)
 constexpr int kFT = 40;               // LDS pitch (u16) of the [feature][pixel] F rows
 constexpr int kRC = 40;               // LDS pitch (u16) of the [channel][pixel] sign rows
@@ -101,8 +98,13 @@ __device__ __forceinline__ void unpack4(const F8& v, int h, float t[4]) {
   t[0] = u.x; t[1] = u.y; t[2] = u.z; t[3] = u.w;
 }
 
-template <typename TT, int NT>   // NT: 16-channel tiles per wave (C = 16 NT kDecWaves, NT >= 2)
-__global__ __launch_bounds__(kDecThreads) void k_decoder(DecArgs a, float* __restrict__ part) {
+// NT: 16-channel tiles per wave, NW: waves per work-group (C = 16 NT NW,
+// NT >= 2); at most 1024 threads, so NW = 16 leaves 128 VGPRs per lane (four
+// waves per SIMD) and NW = 8 leaves 256 (two)
+template <typename TT, int NT, int NW>
+__global__ __launch_bounds__(64 * NW) void k_decoder(DecArgs a, float* __restrict__ part) {
+  constexpr int kDecWaves = NW;
+  constexpr int kDecThreads = 64 * NW;
   constexpr int Cw = 16 * NT;             // channels per wave
   constexpr int KS = Cw / 32;             // 32-channel steps of the dF product
   static_assert(KS >= 1, "at least 32 channels per wave");
@@ -216,21 +218,23 @@ __global__ __launch_bounds__(kDecThreads) void k_decoder(DecArgs a, float* __res
   // into registers ahead of their use (kDecPF register sets, the chunk loop
   // unrolled by kDecPF so that each set stays in the same registers), so the
   // loads' latency overlaps the matrix products of the chunks before.  The
-  // depth is what the register file holds at two waves per SIMD without
-  // spilling: a chunk's targets take 4 NT registers in BF16, 8 NT in FP32.
-  constexpr int kDecPF = (sizeof(TT) == 2 ? 3 : 2) - (NT == 4 ? 1 : 0);
+  // depth is what the register file holds without spilling: a chunk's
+  // targets take 4 NT registers in BF16, 8 NT in FP32; at 16 waves (128
+  // VGPRs) one chunk ahead.
+  constexpr int kDecPF = NW == 16 ? 1 : (sizeof(TT) == 2 ? 3 : 2) - (NT == 4 ? 1 : 0);
   typedef typename Raw8<TT>::type RawT;
   RawT tr[kDecPF][NT];
   float fr[kDecPF];
-  static_assert(kDecThreads == 16 * kChunk, "one feature element per thread and chunk");
-  const int fk = t >> 5, fpx = t & 31;
+  static_assert(kDecThreads >= 16 * kChunk, "at most one feature element per thread and chunk");
+  const int fk = (t >> 5) & 15, fpx = t & 31;
+  const bool fth = t < 16 * kChunk;   // the threads that carry the chunk's feature elements
   // lane (q4, r16) of the Z^T products holds pixels 8 q4 .. 8 q4 + 7 of the
   // chunk (rows 4 q4 .. 4 q4 + 3 of column group cg are pixels 8 q4 + 4 cg
   // + i): its targets of one channel are one 16-byte load
   auto fetch = [&](int64_t ck, RawT (&trs)[NT], float& frs) {
     const int64_t p0 = ck * kChunk;
     const bool full = p0 + kChunk <= n;
-    frs = p0 + fpx < n ? feat[(size_t)fk * n + p0 + fpx] : 0.f;
+    frs = fth && p0 + fpx < n ? feat[(size_t)fk * n + p0 + fpx] : 0.f;
     const int64_t pp = p0 + 8 * q4;
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
@@ -245,7 +249,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decoder(DecArgs a, float* __res
   const int64_t per = (n_chunks + a.v[vi].groups - 1) / a.v[vi].groups;
   const int64_t ck0 = (int64_t)((int)blockIdx.x - a.v[vi].g0) * per;
   const int64_t ck1 = ck0 + per < n_chunks ? ck0 + per : n_chunks;
-  // chunk pc's dL/dF: the 8 waves' partials (buffer par) summed in a fixed order
+  // chunk pc's dL/dF: the waves' partials (buffer par) summed in a fixed order
   auto store_df = [&](int64_t pc, int par) {
     const int64_t q0 = pc * kChunk;
     for (int e = t; e < 16 * kChunk; e += kDecThreads) {
@@ -264,7 +268,7 @@ __global__ __launch_bounds__(kDecThreads) void k_decoder(DecArgs a, float* __res
     const unsigned short* fAc = fA[par];
     const unsigned short* fTc = fT[par];
     // (1) F chunk -> LDS: [pixel][F_hi | F_lo] and [hi/lo][feature][pixel]
-    {
+    if (fth) {
       const unsigned short hi = to_bf16(frc), lo = to_bf16(frc - from_bf16(hi));
       fA[par][fpx * kFA + fk] = hi;
       fA[par][fpx * kFA + 16 + fk] = lo;
@@ -442,9 +446,9 @@ __global__ __launch_bounds__(64 * kRedGroups) void k_decoder_reduce(DecArgs a, c
 template <typename TT>
 void launch_t(const DecArgs& a, float* part, int grid, hipStream_t s) {
   if (a.C == 256)
-    hipLaunchKernelGGL((k_decoder<TT, 2>), dim3(grid), dim3(kDecThreads), 0, s, a, part);
+    hipLaunchKernelGGL((k_decoder<TT, 2, 8>), dim3(grid), dim3(64 * 8), 0, s, a, part);
   else
-    hipLaunchKernelGGL((k_decoder<TT, 4>), dim3(grid), dim3(kDecThreads), 0, s, a, part);
+    hipLaunchKernelGGL((k_decoder<TT, 2, 16>), dim3(grid), dim3(64 * 16), 0, s, a, part);
 }
 
 }  // namespace
