@@ -211,6 +211,14 @@ __global__ void __launch_bounds__(256) k_fill_u32(uint32_t* __restrict__ p, uint
   if (i < n) p[i] = v;
 }
 
+// two ranges of words zeroed by one launch
+__global__ void __launch_bounds__(256) k_zero2_u32(uint32_t* __restrict__ p, int64_t np, uint32_t* __restrict__ q,
+                                                   int64_t nq) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < np) p[i] = 0u;
+  if (i < nq) q[i] = 0u;
+}
+
 __global__ void __launch_bounds__(256) k_fill_u8(uint8_t* __restrict__ p, uint8_t v,
                                                  const uint32_t* n_dev, int64_t n_max) {
   const int64_t n = count_of(n_dev, n_max);
@@ -234,8 +242,12 @@ __global__ void __launch_bounds__(256) k_tile_ranges(const uint32_t* __restrict_
   if (i == P - 1 || keys[i + 1] != k) ranges[k].y = (uint32_t)(i + 1);
 }
 
-__global__ void k_set_overflow(Counters* cnt, uint64_t cap_pairs, uint64_t cap_slots) {
-  if (threadIdx.x == 0) {
+// The overflow flag and effective counts of the step, and (every thread) a
+// range of words zeroed for the stages that follow.
+__global__ void __launch_bounds__(256) k_set_overflow(Counters* cnt, uint64_t cap_pairs, uint64_t cap_slots,
+                                                      uint32_t* __restrict__ zero, int64_t n_zero) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n_zero; i += (int64_t)gridDim.x * 256) zero[i] = 0u;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     const bool ov = (uint64_t)cnt->n_pairs > cap_pairs || (uint64_t)cnt->n_slots > cap_slots;
     cnt->overflow = ov ? 1u : 0u;
     cnt->n_pairs_eff = ov ? 0u : cnt->n_pairs;
@@ -348,6 +360,12 @@ void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, v, n);
 }
 
+void launch_zero2_u32(uint32_t* p, int64_t np, uint32_t* q, int64_t nq, hipStream_t s) {
+  const int64_t n = std::max(np, nq);
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_zero2_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, np, q, nq);
+}
+
 void launch_fill_u8(uint8_t* p, uint8_t v, const uint32_t* n_dev, int64_t n_max, hipStream_t s) {
   if (n_max <= 0) return;
   const int64_t blocks = (n_max + 1023) / 1024;
@@ -361,8 +379,11 @@ void launch_tile_ranges(const uint32_t* keys, const Counters* cnt, int64_t grid_
                      cnt, ranges);
 }
 
-void launch_set_overflow(Counters* cnt, uint64_t cap_pairs, uint64_t cap_slots, hipStream_t s) {
-  hipLaunchKernelGGL(k_set_overflow, dim3(1), dim3(64), 0, s, cnt, cap_pairs, cap_slots);
+void launch_set_overflow(Counters* cnt, uint64_t cap_pairs, uint64_t cap_slots, uint32_t* zero, int64_t n_zero,
+                         hipStream_t s) {
+  const int64_t blocks = std::min<int64_t>(std::max<int64_t>((n_zero + 255) / 256, 1), 1024);
+  hipLaunchKernelGGL(k_set_overflow, dim3((unsigned)blocks), dim3(256), 0, s, cnt, cap_pairs, cap_slots, zero,
+                     n_zero);
 }
 
 uint32_t* launch_order_items(const uint2* ranges, const uint32_t* items, const TileItems* tiles, int64_t n_tiles,

@@ -166,10 +166,13 @@ void launch_emit(const GeomRec* geom, const ViewDesc* views, const uint32_t* sri
                  int64_t cap_pairs, int npad_shift, int tile_shift,
                  uint32_t* keys, uint32_t* vals, hipStream_t s);
 void launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+void launch_zero2_u32(uint32_t* p, int64_t np, uint32_t* q, int64_t nq, hipStream_t s);
 void launch_fill_u8(uint8_t* p, uint8_t v, const uint32_t* n_dev, int64_t n_max, hipStream_t s);
 void launch_tile_ranges(const uint32_t* keys, const Counters* cnt, int64_t grid_max,
                         uint2* ranges, hipStream_t s);
-void launch_set_overflow(Counters* cnt, uint64_t cap_pairs, uint64_t cap_slots, hipStream_t s);
+// the step's overflow flag and effective counts; also zeroes zero[0 .. n_zero)
+void launch_set_overflow(Counters* cnt, uint64_t cap_pairs, uint64_t cap_slots, uint32_t* zero, int64_t n_zero,
+                         hipStream_t s);
 void launch_reset_counters(Counters* cnt, hipStream_t s);
 void launch_slot_bases(const uint32_t* ent, const uint32_t* slot_off, const Counters* cnt,
                        int64_t grid_max, uint32_t* slot_base, hipStream_t s);
@@ -294,7 +297,7 @@ void launch_group_feat_grad(int n_views, int64_t n, uint32_t npad_shift, const C
                             const uint32_t* cidx, const float* grad2d_g, int nfeat, float* g_feat_g, hipStream_t s);
 
 // gradient reduction and projection backward
-void launch_seg_reduce(const uint32_t* slot_off, const float* partials, const uint8_t* mask,
+void launch_seg_reduce(const uint32_t* slot_off, const float* partials, uint8_t* mask,
                        const Counters* cnt, int64_t n_max, float* grad2d, hipStream_t s);
 size_t twist_temp_bytes(int64_t n, int n_views);
 void launch_project_bwd(const Settings& st, const ViewDesc* views, int n_views,

@@ -878,7 +878,7 @@ __global__ void __launch_bounds__(256)
 // order, so results are deterministic.
 __global__ void __launch_bounds__(256) k_seg_reduce(const uint32_t* __restrict__ slot_off,
                                                     const float* __restrict__ partials,
-                                                    const uint8_t* __restrict__ mask,
+                                                    uint8_t* __restrict__ mask,
                                                     const Counters* __restrict__ cnt,
                                                     float* __restrict__ grad2d) {
   const int lane = threadIdx.x & 63;
@@ -901,6 +901,7 @@ __global__ void __launch_bounds__(256) k_seg_reduce(const uint32_t* __restrict__
     for (uint32_t o = hl; o < maxlen; o += 32) {
       const uint32_t sl = base + o;
       if (o < len && mask[sl]) {
+        mask[sl] = 0;   // cleared for the next backward over these slots
         // the record's seven 16-byte quarters are all requested before the
         // first is added, so one memory round trip covers the slot
         const f32x4* pp = (const f32x4*)(partials + (size_t)sl * kSlotFloats);
@@ -1018,7 +1019,7 @@ void launch_raster_bwd(int up_mode, const Settings& st, const ViewDesc* views, c
 #undef LGS_BWD
 }
 
-void launch_seg_reduce(const uint32_t* slot_off, const float* partials, const uint8_t* mask,
+void launch_seg_reduce(const uint32_t* slot_off, const float* partials, uint8_t* mask,
                        const Counters* cnt, int64_t n_max, float* grad2d, hipStream_t s) {
   if (n_max <= 0) return;
   int dev = 0, cus = 256, occ = 1;

@@ -604,6 +604,8 @@ lgs_status w_alloc_bwd(Work* W) {
     W->geo_acc = (float*)w_alloc(W, sizeof(float) * 6 * std::max<int64_t>(W->n_rid, 1), ok);
   }
   if (!ok) return fail(W->ctx, LGS_ERR_HIP, "device allocation failed (backward)");
+  // the slot mask starts at zero; every reduction leaves it at zero again
+  launch_fill_u8(W->mask, 0, nullptr, S + 8, W->stream);
   W->bwd_alloc = true;
   return LGS_OK;
 }
@@ -692,8 +694,8 @@ void enqueue_front(Work* W, const lgs_gaussians* g, hipStream_t s) {
 // emission, tile sort, tile ranges, work order (capacity-bounded)
 void enqueue_pairs(Work* W, hipStream_t s) {
   const Plan& P = W->plan;
-  launch_set_overflow(W->counters, (uint64_t)W->cap_pairs, (uint64_t)W->cap_slots, s);
-  launch_fill_u32((uint32_t*)W->ranges, 0u, 2 * P.n_tiles, s);
+  launch_set_overflow(W->counters, (uint64_t)W->cap_pairs, (uint64_t)W->cap_slots, (uint32_t*)W->ranges,
+                      2 * P.n_tiles, s);
   launch_emit(W->geom, W->d_views, W->srid, W->off_t, W->counters, W->cap_pairs, W->cap_pairs, W->npad_shift,
               P.tile_shift, W->k0, W->v0, s);
   const int tile_bits = std::max<int>(1, (int)ceil_log2((uint64_t)P.n_tiles));
@@ -728,12 +730,15 @@ void enqueue_raster_fwd(Work* W, hipStream_t s) {
 // Backward compositing of one feature group; upstream by mode (UpMode):
 // d_up; dL1/dY from (d_fo, d_tgt, d_lossw); or colour channels from d_up and
 // depth + features from the L1 residual.
-void launch_group_bwd(Work* W, int gi, int mode, hipStream_t s) {
+// The slot mask needs no clearing here: it is zeroed when the backward's
+// buffers are acquired, and the reduction clears each byte it reads.  The
+// first group's launch also zeroes the backward's work counts.
+void launch_group_bwd(Work* W, int gi, int mode, bool first, hipStream_t s) {
   const int V = (int)W->plan.views.size();
   const bool sign = mode != UP_EXPLICIT;
   const Settings ds = dev_settings(&W->st, W->plan.tile_shift, W->D, gi);
-  launch_fill_u8(W->mask, 0, &W->counters->n_slots_eff, std::max<int64_t>(W->cap_slots, 1), s);
-  launch_fill_u32(W->counters->work_qb, 0u, kQueues * kLineWords, s);
+  launch_zero2_u32(W->counters->work_qb, kQueues * kLineWords, (uint32_t*)&W->counters->bwd_evals, first ? 8 : 0,
+                   s);   // bwd_evals, _contrib, _entries, _written
   if (gi == 0 && W->G == 1) w_mark(W, 5, s);   // one group: the stage is the kernel alone
   launch_raster_bwd(mode, ds, W->d_views, W->d_up + (size_t)gi * V, sign ? W->d_fo + (size_t)gi * V : nullptr,
                     sign ? W->d_tgt + (size_t)gi * V : nullptr, sign ? W->d_lossw + 4 * gi : nullptr, W->ranges,
@@ -749,16 +754,15 @@ void launch_group_bwd(Work* W, int gi, int mode, hipStream_t s) {
 // projection backward follow in enqueue_backward_reduce.
 void enqueue_backward_raster(Work* W, const lgs_grads* gr, int mode, hipStream_t s) {
   const int V = (int)W->plan.views.size();
-  launch_fill_u32((uint32_t*)&W->counters->bwd_evals, 0u, 8, s);   // bwd_evals, _contrib, _entries, _written
   if (W->G > 1) w_mark(W, 5, s);
   for (int gi = 1; gi < W->G; ++gi) {
-    launch_group_bwd(W, gi, mode, s);
+    launch_group_bwd(W, gi, mode, gi == 1, s);
     launch_seg_reduce(W->slot_off, W->partials, W->mask, W->counters, W->n_rid, W->grad2d_g, s);
     launch_group_geo_acc(W->grad2d_g, W->counters, W->n_rid, W->geo_acc, gi == 1, s);
     launch_group_feat_grad(V, W->n, (uint32_t)W->npad_shift, W->counters, W->cnt_t, W->cidx, W->grad2d_g,
                            group_nfeat(W->D, gi), gr->feat + (size_t)kFeatGroup * gi * (size_t)W->n, s);
   }
-  launch_group_bwd(W, 0, mode, s);
+  launch_group_bwd(W, 0, mode, W->G == 1, s);
   w_mark(W, 6, s);
 }
 
