@@ -75,7 +75,8 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_down(int mode, const uint
                                                             const uint32_t* __restrict__ idx,
                                                             const uint32_t* n_dev, int64_t n_max,
                                                             const uint32_t* __restrict__ bsum,
-                                                            uint32_t* __restrict__ out, uint32_t* __restrict__ total) {
+                                                            uint32_t* __restrict__ out, uint32_t* __restrict__ total,
+                                                            uint32_t* __restrict__ out_at_idx) {
   __shared__ uint32_t sh[4];
   const int64_t n = count_of(n_dev, n_max);
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
@@ -102,7 +103,10 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_down(int mode, const uint
   uint32_t run = block_excl_scan(s, sh, btot) + boff;
   for (int k = 0; k < kScanItems; ++k) {
     const int64_t i = base + (int64_t)threadIdx.x * kScanItems + k;
-    if (i < n) out[i] = run;
+    if (i < n) {
+      out[i] = run;
+      if (out_at_idx) out_at_idx[idx[i]] = run;   // gather scans: the value also at its source index
+    }
     run += v[k];
   }
   if (base + kScanTile >= n && threadIdx.x == 0) *total = boff + btot;   // the last block
@@ -261,6 +265,7 @@ __global__ void __launch_bounds__(256) k_set_overflow(Counters* cnt, uint64_t ca
 // Items of one bucket may come out in any order; the order only affects
 // scheduling, not results.
 constexpr int kOrderThreads = 1024;
+constexpr uint32_t kMaxTileItems = 16;   // 8x8 blocks of a 32-pixel tile
 constexpr int kOrderBins = kQueues * 256;
 
 __device__ __forceinline__ uint32_t tile_key(const uint2* __restrict__ ranges, const TileItems& T) {
@@ -301,24 +306,18 @@ __global__ void __launch_bounds__(kOrderThreads) k_order_items(const uint2* __re
   hist[2 * threadIdx.x] = ex;
   hist[2 * threadIdx.x + 1] = ex + a;
   __syncthreads();
+  // a tile has at most kMaxTileItems blocks: all of its loads are issued
+  // before the first store (one memory round trip per tile)
   for (int64_t i = threadIdx.x; i < n_tiles; i += kOrderThreads) {
     const TileItems T = tiles[i];
     const uint32_t pos = atomicAdd(&hist[tile_key(ranges, T)], T.count);
-    for (uint32_t k = 0; k < T.count; ++k) out[pos + k] = items[T.first + k];
+    uint32_t v[kMaxTileItems];
+#pragma unroll
+    for (uint32_t k = 0; k < kMaxTileItems; ++k) v[k] = k < T.count ? items[T.first + k] : 0u;
+#pragma unroll
+    for (uint32_t k = 0; k < kMaxTileItems; ++k)
+      if (k < T.count) out[pos + k] = v[k];
   }
-}
-
-__global__ void __launch_bounds__(256) k_reset_counters(Counters* cnt) {
-  for (uint32_t i = threadIdx.x; i < sizeof(Counters) / 4; i += 256) ((uint32_t*)cnt)[i] = 0u;
-}
-
-__global__ void __launch_bounds__(256) k_slot_bases(const uint32_t* __restrict__ ent,
-                                                    const uint32_t* __restrict__ slot_off,
-                                                    const Counters* __restrict__ cnt,
-                                                    uint32_t* __restrict__ slot_base) {
-  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (c >= (int64_t)cnt->n_visible) return;
-  slot_base[ent[c]] = slot_off[c];
 }
 
 }  // namespace
@@ -329,14 +328,14 @@ size_t scan_temp_bytes(int64_t n) {
 }
 
 void launch_scan(int mode, const uint32_t* src, const uint32_t* idx, uint32_t* out, uint32_t* total,
-                 const uint32_t* n_dev, int64_t n_max, void* temp, hipStream_t s) {
+                 const uint32_t* n_dev, int64_t n_max, void* temp, hipStream_t s, uint32_t* out_at_idx) {
   const int64_t nb = (n_max + kScanTile - 1) / kScanTile;
   uint32_t* bsum = (uint32_t*)temp;
   if (nb > 0)
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, mode, src, idx,
                        n_dev, n_max, bsum);
   hipLaunchKernelGGL(k_scan_down, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(kScanThreads), 0, s, mode, src, idx,
-                     n_dev, n_max, (const uint32_t*)bsum, out, total);
+                     n_dev, n_max, (const uint32_t*)bsum, out, total, out_at_idx);
 }
 
 void launch_compact(const uint32_t* cnt_t, const uint32_t* cidx, const uint32_t* dkey, int64_t n_rid,
@@ -391,17 +390,6 @@ uint32_t* launch_order_items(const uint2* ranges, const uint32_t* items, const T
   if (n_tiles <= 0) return out;
   hipLaunchKernelGGL(k_order_items, dim3(1), dim3(kOrderThreads), 0, s, ranges, items, tiles, n_tiles, out);
   return out;
-}
-
-void launch_reset_counters(Counters* cnt, hipStream_t s) {
-  hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(256), 0, s, cnt);
-}
-
-void launch_slot_bases(const uint32_t* ent, const uint32_t* slot_off, const Counters* cnt,
-                       int64_t grid_max, uint32_t* slot_base, hipStream_t s) {
-  if (grid_max <= 0) return;
-  hipLaunchKernelGGL(k_slot_bases, dim3((unsigned)((grid_max + 255) / 256)), dim3(256), 0, s, ent,
-                     slot_off, cnt, slot_base);
 }
 
 }  // namespace lgs

@@ -144,7 +144,7 @@ void launch_project(const Settings& st, const ViewDesc* views, int n_views,
                     const float* logits, const void* rgb, const void* feat, int app_bf16,
                     int64_t n, uint32_t npad_shift,
                     GeomRec* geom, uint32_t* cnt_t, uint32_t* cnt_b, uint32_t* dkey,
-                    void* app, hipStream_t s);
+                    void* app, Counters* cnt, hipStream_t s);   // also zeroes *cnt (the step's first kernel)
 
 // scans
 size_t scan_temp_bytes(int64_t n);
@@ -152,9 +152,11 @@ enum ScanInput { SCAN_FLAG_NONZERO = 0, SCAN_VALUE = 1, SCAN_GATHER = 2 };
 // out[i] = exclusive prefix of in(i); total written to *total.
 // in(i) = (src[i] != 0) / src[i] / src[idx[i]] by mode; n read from *n_dev
 // when n_dev != nullptr (n_max bounds the grid), else n_max.
+// out_at_idx (gather scans only, or NULL): each value also written at its
+// source index, out_at_idx[idx[i]] = out[i]
 void launch_scan(int mode, const uint32_t* src, const uint32_t* idx, uint32_t* out,
                  uint32_t* total, const uint32_t* n_dev, int64_t n_max,
-                 void* temp, hipStream_t s);
+                 void* temp, hipStream_t s, uint32_t* out_at_idx = nullptr);
 
 // compaction of visible (view, Gaussian) ids
 void launch_compact(const uint32_t* cnt_t, const uint32_t* cidx, const uint32_t* dkey, int64_t n_rid,
@@ -173,10 +175,6 @@ void launch_tile_ranges(const uint32_t* keys, const Counters* cnt, int64_t grid_
 // the step's overflow flag and effective counts; also zeroes zero[0 .. n_zero)
 void launch_set_overflow(Counters* cnt, uint64_t cap_pairs, uint64_t cap_slots, uint32_t* zero, int64_t n_zero,
                          hipStream_t s);
-void launch_reset_counters(Counters* cnt, hipStream_t s);
-void launch_slot_bases(const uint32_t* ent, const uint32_t* slot_off, const Counters* cnt,
-                       int64_t grid_max, uint32_t* slot_base, hipStream_t s);
-
 // radix sort (LSD, 8-bit digits, stable)
 size_t radix_temp_bytes(int64_t n_max);
 void radix_sort_u32(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt,

@@ -134,7 +134,11 @@ __global__ void __launch_bounds__(256) k_project(
     const float* __restrict__ quats, const float* __restrict__ logits,
     const void* __restrict__ rgb, const void* __restrict__ feat, int64_t n, uint32_t npad_shift,
     GeomRec* __restrict__ geom, uint32_t* __restrict__ cnt_t, uint32_t* __restrict__ cnt_b,
-    uint32_t* __restrict__ dkey, void* __restrict__ app) {
+    uint32_t* __restrict__ dkey, void* __restrict__ app, Counters* __restrict__ cnt) {
+  // the step's counters start at zero (the first kernel of the step; no
+  // kernel before it in the step reads them)
+  if (blockIdx.x == 0)
+    for (uint32_t i = threadIdx.x; i < sizeof(Counters) / 4; i += blockDim.x) ((uint32_t*)cnt)[i] = 0u;
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= ((int64_t)1 << npad_shift)) return;
   if (g >= n) {   // padding ids of the (view, Gaussian) index space: nothing visible
@@ -540,15 +544,15 @@ void launch_project(const Settings& st, const ViewDesc* views, int n_views, cons
                     const float* log_scales, const float* quats, const float* logits,
                     const void* rgb, const void* feat, int app_bf16, int64_t n, uint32_t npad_shift,
                     GeomRec* geom, uint32_t* cnt_t, uint32_t* cnt_b, uint32_t* dkey, void* app,
-                    hipStream_t s) {
+                    Counters* cnt, hipStream_t s) {
   const int64_t npad = (int64_t)1 << npad_shift;
   const int blocks = (int)((npad + 255) / 256);
   if (app_bf16)
     hipLaunchKernelGGL(k_project<true>, dim3(blocks), dim3(256), 0, s, st, views, n_views, means,
-                       log_scales, quats, logits, rgb, feat, n, npad_shift, geom, cnt_t, cnt_b, dkey, app);
+                       log_scales, quats, logits, rgb, feat, n, npad_shift, geom, cnt_t, cnt_b, dkey, app, cnt);
   else
     hipLaunchKernelGGL(k_project<false>, dim3(blocks), dim3(256), 0, s, st, views, n_views, means,
-                       log_scales, quats, logits, rgb, feat, n, npad_shift, geom, cnt_t, cnt_b, dkey, app);
+                       log_scales, quats, logits, rgb, feat, n, npad_shift, geom, cnt_t, cnt_b, dkey, app, cnt);
 }
 
 void launch_pack_app_group(const void* feat_g, int nfeat, int app_bf16, int64_t n, void* app, hipStream_t s) {

@@ -669,9 +669,8 @@ void enqueue_front(Work* W, const lgs_gaussians* g, hipStream_t s) {
   const Settings ds = dev_settings(&W->st, W->plan.tile_shift, W->D, 0);
   const int V = (int)W->plan.views.size();
   const int64_t n_rid = W->n_rid;
-  launch_reset_counters(W->counters, s);
   launch_project(ds, W->d_views, V, g->means, g->log_scales, g->quats, g->opacity_logits, g->rgb, g->feat,
-                 W->app_bf16, W->n, W->npad_shift, W->geom, W->cnt_t, W->cnt_b, W->dkey, W->app, s);
+                 W->app_bf16, W->n, W->npad_shift, W->geom, W->cnt_t, W->cnt_b, W->dkey, W->app, W->counters, s);
   launch_scan(SCAN_FLAG_NONZERO, W->cnt_t, nullptr, W->cidx, &W->counters->n_visible, nullptr, n_rid,
               W->scan_tmp, s);
   // the compaction writes ent (kept, index order) and a copy that the depth sort permutes
@@ -682,9 +681,9 @@ void enqueue_front(Work* W, const lgs_gaussians* g, hipStream_t s) {
   W->srid = alt ? W->ent_b : W->ent_a;
   launch_scan(SCAN_GATHER, W->cnt_t, W->srid, W->off_t, &W->counters->n_pairs, &W->counters->n_visible, n_rid,
               W->scan_tmp, s);
+  // slot offsets in visible order, and the same as each record's slot base
   launch_scan(SCAN_GATHER, W->cnt_b, W->ent, W->slot_off, &W->counters->n_slots, &W->counters->n_visible, n_rid,
-              W->scan_tmp, s);
-  launch_slot_bases(W->ent, W->slot_off, W->counters, n_rid, W->slot_base, s);
+              W->scan_tmp, s, W->slot_base);
   const size_t esz = W->app_bf16 ? 2 : 4;
   for (int gi = 1; gi < W->G; ++gi)
     launch_pack_app_group((const char*)g->feat + esz * (size_t)kFeatGroup * gi * (size_t)W->n,
