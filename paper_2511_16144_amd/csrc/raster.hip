@@ -887,20 +887,54 @@ __global__ void __launch_bounds__(256) k_seg_reduce(const uint32_t* __restrict__
   const uint32_t n_waves = (gridDim.x * blockDim.x) >> 6;
   const uint32_t w0 = __builtin_amdgcn_readfirstlane((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   const uint32_t half = (uint32_t)lane >> 5, hl = (uint32_t)lane & 31u;
-  for (uint32_t c0 = 2 * w0; c0 < nv; c0 += 2 * n_waves) {
+  // The slot range of the pair two ahead and the first mask byte of the
+  // next pair are requested before the current pair is summed, so a pair
+  // waits on one memory round trip (its records) instead of three (range,
+  // mask, records).  The requests are unconditional, at clamped indices, and
+  // their words are combined only when the pair comes up, so nothing waits
+  // on them early.
+  if (nv == 0u) return;
+  const uint32_t step = 2 * n_waves;
+  auto req = [&](uint32_t cc, uint32_t& b, uint32_t& e) {   // raw words of pair member cc
+    const uint32_t ci = min(cc, nv - 1u);
+    b = slot_off[ci];
+    e = slot_off[min(ci + 1u, nv - 1u)];
+  };
+  auto range = [&](uint32_t cc, uint32_t braw, uint32_t eraw, uint32_t& b, uint32_t& l) {
+    const bool valid = cc < nv;
+    b = valid ? braw : 0u;
+    l = valid ? (cc + 1u < nv ? eraw : ns) - braw : 0u;
+  };
+  auto req_mask = [&](uint32_t b, uint32_t l) {   // the byte of this lane's first slot (or slot 0)
+    return mask[l > 0u ? b + min(hl, l - 1u) : 0u];
+  };
+  uint32_t rb0, re0, rb1, re1;
+  req(2 * w0 + half, rb0, re0);
+  req(2 * w0 + step + half, rb1, re1);
+  uint32_t b0, l0;
+  range(2 * w0 + half, rb0, re0, b0, l0);
+  uint32_t mraw0 = req_mask(b0, l0);
+  for (uint32_t c0 = 2 * w0; c0 < nv; c0 += step) {
     const uint32_t c = c0 + half;
-    uint32_t base = 0, len = 0;
-    if (c < nv) {
-      base = slot_off[c];
-      len = (c + 1 < nv ? slot_off[c + 1] : ns) - base;
-    }
+    uint32_t rb2, re2;
+    req(c0 + 2 * step + half, rb2, re2);
+    uint32_t b1, l1;
+    range(c0 + step + half, rb1, re1, b1, l1);
+    const uint32_t mraw1 = req_mask(b1, l1);
+    // the requests above stay ahead of the summing below (no memory operation
+    // moves across this point)
+    asm volatile("" ::: "memory");
+    const uint32_t base = b0, len = l0;
+    const bool m0 = hl < len && mraw0 != 0u;
     const uint32_t maxlen = __builtin_amdgcn_readfirstlane(max(len, (uint32_t)__shfl_xor((int)len, 32, 64)));
     float vv[32];
 #pragma unroll
     for (int i = 0; i < 32; ++i) vv[i] = 0.f;
     for (uint32_t o = hl; o < maxlen; o += 32) {
       const uint32_t sl = base + o;
-      if (o < len && mask[sl]) {
+      // the first slot of each lane: the byte requested one pair ago
+      const bool written = o == hl ? m0 : (o < len && mask[sl] != 0);
+      if (written) {
         mask[sl] = 0;   // cleared for the next backward over these slots
         // the record's seven 16-byte quarters are all requested before the
         // first is added, so one memory round trip covers the slot
@@ -921,6 +955,11 @@ __global__ void __launch_bounds__(256) k_seg_reduce(const uint32_t* __restrict__
     }
     const float tot = transpose_reduce_half32(vv, lane);
     if (c < nv && hl < (uint32_t)kPartials) grad2d[(size_t)c * kPartials + hl] = tot;
+    b0 = b1;
+    l0 = l1;
+    mraw0 = mraw1;
+    rb1 = rb2;
+    re1 = re2;
   }
 }
 
