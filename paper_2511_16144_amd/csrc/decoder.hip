@@ -115,12 +115,11 @@ __global__ __launch_bounds__(64 * NW) void k_decoder(DecArgs a, float* __restric
   __shared__ __attribute__((aligned(16))) unsigned short rC[kDecWaves][Cw * kRC];      // [channel][pixel] signs
   // [pixel][channel] signs.  A wave's 2-byte sign stores hit four rows 8
   // apart at once (one per lane group), and with 16-byte-aligned rows those
-  // always share banks, so each row's channels are rotated by 16 channels
-  // (32 bytes) per group of 8 rows: the four lane groups then fall on
-  // disjoint banks.  Readers take 8-channel runs, which the rotation keeps
-  // whole.
+  // always share banks, so each row's channels are rotated by Cw / 4
+  // channels per group of 8 rows: the four lane groups then fall on disjoint
+  // banks.  Readers take 8-channel runs, which the rotation keeps whole.
   constexpr int kRP = Cw + 8;
-  auto rp_col = [&](int row, int col) { return (col + 16 * ((row >> 3) & 3)) & (Cw - 1); };
+  auto rp_col = [&](int row, int col) { return (col + (Cw / 4) * ((row >> 3) & 3)) & (Cw - 1); };
   static_assert((Cw & (Cw - 1)) == 0 && Cw >= 32, "rotation modulo a power-of-two channel count");
   __shared__ __attribute__((aligned(16))) unsigned short rP[kDecWaves][kChunk * kRP];
   __shared__ __attribute__((aligned(16))) float dfr[2][kDecWaves * 16 * kChunk];      // [wave][feature][pixel]

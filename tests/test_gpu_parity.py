@@ -124,6 +124,26 @@ def test_empty_scene_and_ragged_sizes(ctx):
         state.release()
 
 
+def test_backward_repeated_on_one_state(ctx, c1):
+    """Three backwards on one forward state (upstreams A, B, A): the third
+    equals the first bitwise.  The slot mask of the backward's partial
+    records is cleared by the reduction that reads it, so a stale mark left
+    by one backward would show up in the next."""
+    wl, _ = c1
+    say("[case] C1 backward x3 on one state")
+    ua = upstream_tensors(scenes.random_upstream(3, wl.cams))
+    ub = upstream_tensors(scenes.random_upstream(4, wl.cams))
+    prm, out, state = run_fwd(ctx, wl)
+    ga = grads_np(ctx.backward(state, prm, ua))
+    gb = grads_np(ctx.backward(state, prm, ub))
+    ga2 = grads_np(ctx.backward(state, prm, ua))
+    torch.cuda.synchronize()
+    state.release()
+    assert any(not np.array_equal(ga[k], gb[k]) for k in ga)
+    for k in ga:
+        assert np.array_equal(ga[k], ga2[k]), k
+
+
 def test_backward_run_to_run_bitwise(ctx, c1):
     wl, _ = c1
     say("[case] C1 backward determinism (two runs)")
