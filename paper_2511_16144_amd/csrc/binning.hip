@@ -260,40 +260,43 @@ __global__ void __launch_bounds__(256) k_set_overflow(Counters* cnt, uint64_t ca
 }
 
 // Work items grouped by queue and, inside a queue, by descending list length
-// (longest first), in one workgroup: a counting sort on 11-bit keys
-// (queue << 8 | 255 - length bucket, bucket = 4 sqrt(length) clamped at 255).
-// Items of one bucket may come out in any order; the order only affects
-// scheduling, not results.
-constexpr int kOrderThreads = 1024;
+// (longest first): one work-group per queue, a counting sort of the queue's
+// tiles on 256 length buckets (255 - bucket, bucket = 4 sqrt(length)
+// clamped at 255) into the queue's segment of the output (a queue's items
+// keep the segment the static table gives them).  Tiles of one bucket may
+// come out in any order; the order only affects scheduling, not results.
+constexpr int kOrderThreads = 256;
 constexpr uint32_t kMaxTileItems = 16;   // 8x8 blocks of a 32-pixel tile
-constexpr int kOrderBins = kQueues * 256;
 
-__device__ __forceinline__ uint32_t tile_key(const uint2* __restrict__ ranges, const TileItems& T) {
+__device__ __forceinline__ uint32_t tile_bin(const uint2* __restrict__ ranges, const TileItems& T) {
   const uint2 r = ranges[T.tile];
   const uint32_t bucket = min(255u, (uint32_t)(4.f * sqrtf((float)(r.y - r.x))));
-  return (T.queue << 8) | (255u - bucket);
+  return 255u - bucket;
 }
 
-// One work-group: a counting sort of the tiles by (queue, descending list
-// length bucket); each tile's blocks are copied as a run, so they stay
+// Work-group q: tiles tq[q] .. tq[q + 1] of the queue-major tile table, items
+// to out[qoff[q] ..]; each tile's blocks are copied as a run, so they stay
 // together in the output and are taken up by the queue's waves side by side.
 __global__ void __launch_bounds__(kOrderThreads) k_order_items(const uint2* __restrict__ ranges,
                                                              const uint32_t* __restrict__ items,
-                                                             const TileItems* __restrict__ tiles, int64_t n_tiles,
+                                                             const uint32_t* __restrict__ qoff,
+                                                             const TileItems* __restrict__ tiles,
+                                                             const uint32_t* __restrict__ tq,
                                                              uint32_t* __restrict__ out) {
-  __shared__ uint32_t hist[kOrderBins];
+  __shared__ uint32_t hist[256];
   __shared__ uint32_t wsum[kOrderThreads / 64];
-  for (int i = threadIdx.x; i < kOrderBins; i += kOrderThreads) hist[i] = 0u;
+  const uint32_t q = blockIdx.x, t0 = tq[q], t1 = tq[q + 1], base = qoff[q];
+  hist[threadIdx.x] = 0u;
   __syncthreads();
-  for (int64_t i = threadIdx.x; i < n_tiles; i += kOrderThreads) {
+  for (uint32_t i = t0 + threadIdx.x; i < t1; i += kOrderThreads) {
     const TileItems T = tiles[i];
-    atomicAdd(&hist[tile_key(ranges, T)], T.count);
+    atomicAdd(&hist[tile_bin(ranges, T)], T.count);
   }
   __syncthreads();
-  // exclusive scan of the bins, two per thread
+  // exclusive scan of the 256 bins, one per thread
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const uint32_t a = hist[2 * threadIdx.x], b = hist[2 * threadIdx.x + 1];
-  uint32_t inc = a + b;
+  const uint32_t a = hist[threadIdx.x];
+  uint32_t inc = a;
   for (int off = 1; off < 64; off <<= 1) {
     const uint32_t y = __shfl_up(inc, off, 64);
     if (lane >= off) inc += y;
@@ -302,15 +305,13 @@ __global__ void __launch_bounds__(kOrderThreads) k_order_items(const uint2* __re
   __syncthreads();
   uint32_t pre = 0;
   for (int w = 0; w < wave; ++w) pre += wsum[w];
-  const uint32_t ex = pre + inc - (a + b);
-  hist[2 * threadIdx.x] = ex;
-  hist[2 * threadIdx.x + 1] = ex + a;
+  hist[threadIdx.x] = base + pre + inc - a;
   __syncthreads();
   // a tile has at most kMaxTileItems blocks: all of its loads are issued
   // before the first store (one memory round trip per tile)
-  for (int64_t i = threadIdx.x; i < n_tiles; i += kOrderThreads) {
+  for (uint32_t i = t0 + threadIdx.x; i < t1; i += kOrderThreads) {
     const TileItems T = tiles[i];
-    const uint32_t pos = atomicAdd(&hist[tile_key(ranges, T)], T.count);
+    const uint32_t pos = atomicAdd(&hist[tile_bin(ranges, T)], T.count);
     uint32_t v[kMaxTileItems];
 #pragma unroll
     for (uint32_t k = 0; k < kMaxTileItems; ++k) v[k] = k < T.count ? items[T.first + k] : 0u;
@@ -385,10 +386,10 @@ void launch_set_overflow(Counters* cnt, uint64_t cap_pairs, uint64_t cap_slots, 
                      n_zero);
 }
 
-uint32_t* launch_order_items(const uint2* ranges, const uint32_t* items, const TileItems* tiles, int64_t n_tiles,
-                             uint32_t* out, hipStream_t s) {
+uint32_t* launch_order_items(const uint2* ranges, const uint32_t* items, const uint32_t* qoff, const TileItems* tiles,
+                             const uint32_t* tq, int64_t n_tiles, uint32_t* out, hipStream_t s) {
   if (n_tiles <= 0) return out;
-  hipLaunchKernelGGL(k_order_items, dim3(1), dim3(kOrderThreads), 0, s, ranges, items, tiles, n_tiles, out);
+  hipLaunchKernelGGL(k_order_items, dim3(kQueues), dim3(kOrderThreads), 0, s, ranges, items, qoff, tiles, tq, out);
   return out;
 }
 

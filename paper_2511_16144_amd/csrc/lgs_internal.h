@@ -186,15 +186,17 @@ void radix_sort_u64(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t
 
 // work queue ordering (blocks by descending tile-list length): each queue's
 // tiles re-sorted by the length of their list (counting sort on coarse
-// length buckets), a tile's blocks kept together; returns out
+// length buckets, one work-group per queue), a tile's blocks kept together;
+// qoff: the queues' item offsets, tiles: the queue-major tile table, tq: its
+// queues' tile offsets (kQueues + 1); returns out
 struct TileItems {
   uint32_t first;   // index of the tile's first item in the static table
   uint32_t count;   // its blocks (items)
   uint32_t tile;    // global tile id
   uint32_t queue;
 };
-uint32_t* launch_order_items(const uint2* ranges, const uint32_t* items, const TileItems* tiles, int64_t n_tiles,
-                             uint32_t* out, hipStream_t s);
+uint32_t* launch_order_items(const uint2* ranges, const uint32_t* items, const uint32_t* qoff, const TileItems* tiles,
+                             const uint32_t* tq, int64_t n_tiles, uint32_t* out, hipStream_t s);
 
 // compositing
 void launch_raster_fwd(const Settings& st, const ViewDesc* views, const ViewImages* out,

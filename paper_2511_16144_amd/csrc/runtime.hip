@@ -264,7 +264,8 @@ Plan make_plan(const lgs_settings* st, int32_t n_views, const lgs_camera* cams) 
 // index (orders 0 and 1) or super_queue of its region (order 2).  Layout of
 // the table: the n_items items, the kQueues + 1 queue offsets, then one
 // TileItems record per tile in the same order (its first item, block count,
-// global tile id and queue), from which k_order_items re-sorts each queue
+// global tile id and queue), then the kQueues + 1 offsets of each queue's
+// tiles among those records; from these k_order_items re-sorts each queue
 // by list length, tile by tile (orders 1 and 2), keeping the queue sizes.
 std::vector<uint32_t> make_items(const Plan& P, int tile, bool spatial) {
   std::vector<std::vector<uint32_t>> qs(kQueues);
@@ -289,8 +290,11 @@ std::vector<uint32_t> make_items(const Plan& P, int tile, bool spatial) {
         qt[q].push_back(ti);
       }
   }
+  // layout: the items queue by queue, the queues' item offsets (kQueues +
+  // 1), the tile table queue by queue (4 words a tile), the queues' tile
+  // offsets in it (kQueues + 1)
   std::vector<uint32_t> items;
-  items.reserve(P.n_items + kQueues + 1 + 4 * P.n_tiles);
+  items.reserve(P.n_items + kQueues + 1 + 4 * P.n_tiles + kQueues + 1);
   std::vector<uint32_t> off(kQueues + 1, 0u);
   for (int q = 0; q < kQueues; ++q) {
     off[q] = (uint32_t)items.size();
@@ -298,6 +302,7 @@ std::vector<uint32_t> make_items(const Plan& P, int tile, bool spatial) {
   }
   off[kQueues] = (uint32_t)items.size();
   items.insert(items.end(), off.begin(), off.end());
+  uint32_t nt = 0;
   for (int q = 0; q < kQueues; ++q)
     for (const TileItems& ti : qt[q]) {
       items.push_back(off[q] + ti.first);
@@ -305,6 +310,11 @@ std::vector<uint32_t> make_items(const Plan& P, int tile, bool spatial) {
       items.push_back(ti.tile);
       items.push_back(ti.queue);
     }
+  for (int q = 0; q < kQueues; ++q) {
+    items.push_back(nt);
+    nt += (uint32_t)qt[q].size();
+  }
+  items.push_back(nt);
   return items;
 }
 
@@ -705,9 +715,9 @@ void enqueue_pairs(Work* W, hipStream_t s) {
   W->pvals = alt ? W->v1 : W->v0;
   launch_tile_ranges(W->pkeys, W->counters, W->cap_pairs, W->ranges, s);
   if (W->st.order != 0)
-    W->items = launch_order_items(W->ranges, W->items_static,
-                                  (const TileItems*)(W->items_static + P.n_items + kQueues + 1), P.n_tiles,
-                                  W->ii_a, s);
+    W->items = launch_order_items(W->ranges, W->items_static, W->items_static + P.n_items,
+                                  (const TileItems*)(W->items_static + P.n_items + kQueues + 1),
+                                  W->items_static + P.n_items + kQueues + 1 + 4 * P.n_tiles, P.n_tiles, W->ii_a, s);
   else
     W->items = W->items_static;
 }

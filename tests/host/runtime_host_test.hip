@@ -52,8 +52,8 @@ void check_items(const std::vector<lgs_camera>& cams, int tile, bool spatial) {
   }
   CHECK(P.n_tiles == tiles && P.n_items == items_n && P.n_pix == pix);
   const std::vector<uint32_t> it = make_items(P, tile, spatial);
-  CHECK((int64_t)it.size() == P.n_items + kQueues + 1 + 4 * P.n_tiles);
-  if ((int64_t)it.size() != P.n_items + kQueues + 1 + 4 * P.n_tiles) return;
+  CHECK((int64_t)it.size() == P.n_items + kQueues + 1 + 4 * P.n_tiles + kQueues + 1);
+  if ((int64_t)it.size() != P.n_items + kQueues + 1 + 4 * P.n_tiles + kQueues + 1) return;
   const uint32_t* qoff = it.data() + P.n_items;
   CHECK(qoff[0] == 0u && qoff[kQueues] == (uint32_t)P.n_items);
   for (int q = 0; q < kQueues; ++q) CHECK(qoff[q] <= qoff[q + 1]);
@@ -86,6 +86,13 @@ void check_items(const std::vector<lgs_camera>& cams, int tile, bool spatial) {
     covered += r.count;
   }
   CHECK(covered == P.n_items && (int64_t)tile_ids.size() == P.n_tiles);
+  // the queues' tile offsets bracket exactly the records of each queue
+  const uint32_t* tq = (const uint32_t*)(T + P.n_tiles);
+  CHECK(tq[0] == 0u && tq[kQueues] == (uint32_t)P.n_tiles);
+  for (int q = 0; q < kQueues; ++q) {
+    CHECK(tq[q] <= tq[q + 1]);
+    for (uint32_t k = tq[q]; k < tq[q + 1] && k < (uint32_t)P.n_tiles; ++k) CHECK(T[k].queue == (uint32_t)q);
+  }
 }
 
 void check_tune_cache(const char* path) {
