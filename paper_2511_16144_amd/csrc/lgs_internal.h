@@ -299,13 +299,16 @@ void launch_group_feat_grad(int n_views, int64_t n, uint32_t npad_shift, const C
 // gradient reduction and projection backward
 void launch_seg_reduce(const uint32_t* slot_off, const float* partials, uint8_t* mask,
                        const Counters* cnt, int64_t n_max, float* grad2d, hipStream_t s);
-size_t twist_temp_bytes(int64_t n, int n_views);
-void launch_project_bwd(const Settings& st, const ViewDesc* views, int n_views,
-                        const float* means, const float* log_scales, const float* quats,
-                        const float* logits, int64_t n, uint32_t npad_shift, const Counters* cnt,
-                        const uint32_t* cnt_t, const uint32_t* cidx, const float* grad2d,
-                        float* g_means, float* g_ls, float* g_q, float* g_logit,
-                        float* g_rgb, float* g_feat, float* twist, void* temp,
-                        hipStream_t s);
+// workspace of launch_project_bwd for at most n_rid visible (view, Gaussian)
+size_t project_bwd_temp_bytes(int64_t n_rid, int n_views);
+// the projection backward: per visible (view, Gaussian) c the view's chain
+// rule (ent: c's record id, in (view, Gaussian) order), then per Gaussian
+// the views summed in order and the activation's chain rule
+void launch_project_bwd(const Settings& st, const ViewDesc* views, int n_views, const float* means,
+                        const float* log_scales, const float* quats, const float* logits, int64_t n,
+                        uint32_t npad_shift, int64_t n_rid, const Counters* cnt, const uint32_t* cnt_t,
+                        const uint32_t* cidx, const uint32_t* ent, const float* grad2d, float* g_means,
+                        float* g_ls, float* g_q, float* g_logit, float* g_rgb, float* g_feat, float* twist,
+                        void* temp, hipStream_t s);
 
 }  // namespace lgs

@@ -259,61 +259,43 @@ __device__ __forceinline__ double wave_sum_d(double x) {
 // 2 Q_xy dx dy + Q_yy dy^2, dx = pixel - mean, dL/dm2 = -1/2 dL/dalpha alpha):
 // so dL/dQ_xx = -1/2 Sxx, dL/dQ_xy (the symmetric off-diagonal entry,
 // counted twice in m2) = -Sxy, dL/dQ_yy = -1/2 Syy, and dL/dmean = Q (Sx, Sy).
-__global__ void __launch_bounds__(256) k_project_bwd(
-    Settings st, const ViewDesc* __restrict__ views, int n_views,
-    const float* __restrict__ means, const float* __restrict__ log_scales,
-    const float* __restrict__ quats, const float* __restrict__ logits, int64_t n,
-    uint32_t npad_shift, const Counters* __restrict__ cnt, const uint32_t* __restrict__ cnt_t,
-    const uint32_t* __restrict__ cidx,
-    const float* __restrict__ grad2d, float* __restrict__ g_means, float* __restrict__ g_ls,
-    float* __restrict__ g_q, float* __restrict__ g_logit, float* __restrict__ g_rgb,
-    float* __restrict__ g_feat, double* __restrict__ twist_part) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool active = g < n;
-  const uint32_t wave_id = (uint32_t)(g >> 6), n_waves = gridDim.x * (blockDim.x >> 6);
-  double p[3] = {0, 0, 0}, ls[3] = {0, 0, 0}, q[4] = {1, 0, 0, 0}, logit = 0.0;
-  if (active) {
-    for (int k = 0; k < 3; ++k) p[k] = means[k * n + g];
-    for (int k = 0; k < 3; ++k) ls[k] = log_scales[k * n + g];
-    for (int k = 0; k < 4; ++k) q[k] = quats[k * n + g];
-    logit = logits[g];
-  }
-  Proj P;
-  bool any = false;
-  // views are taken 8 at a time with branch-free (clamped) loads, so that
-  // their visibility and record index loads are in flight together
-  constexpr int kVB = 8;
-  if (active && cnt->overflow == 0u) {
-    for (int v0 = 0; v0 < n_views && !any; v0 += kVB) {
-      uint32_t c[kVB];
-#pragma unroll
-      for (int u = 0; u < kVB; ++u)
-        c[u] = cnt_t[((uint64_t)min(v0 + u, n_views - 1) << npad_shift) | (uint64_t)g];
-#pragma unroll
-      for (int u = 0; u < kVB; ++u) any = any || (v0 + u < n_views && c[u] != 0u);
-    }
-  }
-  if (any) activate(p, ls, q, logit, P);
-  double gp[3] = {0, 0, 0}, gM[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, glogit = 0.0;
-  float gy[20];
-  for (int k = 0; k < 20; ++k) gy[k] = 0.f;
+// The per-view chain rule, one thread per visible (view, Gaussian) c (in
+// (view, Gaussian) order, so a wave's 64 c belong to one view or a few
+// consecutive ones): its contributions to dL/d(world mean), dL/dM and
+// dL/dlogit go to contrib[c] (FP32, 16 floats: 3, 9, 1, pad), its pose-twist
+// terms are summed per block of 64 c and view into twist_part[v][k][block].
+// Every c of a view is visited by exactly one thread, with no divergence
+// between views (one thread per Gaussian looping over the views ran the
+// chain rule for every view a wave's Gaussians saw, with most lanes idle).
+__global__ void __launch_bounds__(256) k_project_bwd_view(
+    Settings st, const ViewDesc* __restrict__ views, const float* __restrict__ means,
+    const float* __restrict__ log_scales, const float* __restrict__ quats, const float* __restrict__ logits,
+    int64_t n, uint32_t npad_shift, const Counters* __restrict__ cnt, const uint32_t* __restrict__ ent,
+    const float* __restrict__ grad2d, float* __restrict__ contrib, double* __restrict__ twist_part,
+    int64_t nblk_max) {
+  if (cnt->overflow) return;
   const int lane = threadIdx.x & 63;
-  uint32_t cix[kVB];   // record index of views v0 .. v0 + 7 (~0 where not visible)
-  for (int v = 0; v < n_views; ++v) {
-    if ((v & (kVB - 1)) == 0) {
-#pragma unroll
-      for (int u = 0; u < kVB; ++u) {
-        cix[u] = ~0u;
-        if (any) {
-          const uint64_t r = ((uint64_t)min(v + u, n_views - 1) << npad_shift) | (uint64_t)g;
-          const uint32_t c = cnt_t[r], ci = cidx[r];
-          cix[u] = (v + u < n_views && c != 0u) ? ci : ~0u;
-        }
-      }
-    }
+  const uint32_t nv = cnt->n_visible;
+  const int64_t nblk = ((int64_t)nv + 63) / 64;
+  const int64_t n_waves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  const int64_t w0 = __builtin_amdgcn_readfirstlane((int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6));
+  const uint32_t gmask = (1u << npad_shift) - 1u;
+  for (int64_t blk = w0; blk < nblk; blk += n_waves) {
+    const int64_t ci = blk * 64 + lane;
+    const bool act = ci < (int64_t)nv;
+    uint32_t v = 0;
     double tw[6] = {0, 0, 0, 0, 0, 0};
-    const uint32_t ci = cix[v & (kVB - 1)];
-    if (ci != ~0u) {
+    if (act) {
+      const uint32_t rid = ent[ci];
+      v = rid >> npad_shift;
+      const int64_t g = rid & gmask;
+      double p[3], ls[3], q[4];
+      for (int k = 0; k < 3; ++k) p[k] = means[k * n + g];
+      for (int k = 0; k < 3; ++k) ls[k] = log_scales[k * n + g];
+      for (int k = 0; k < 4; ++k) q[k] = quats[k * n + g];
+      Proj P;
+      activate(p, ls, q, (double)logits[g], P);
+      double gp[3] = {0, 0, 0}, gM[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, glogit = 0.0;
       const ViewDesc V = views[v];
       const float* G = grad2d + (size_t)ci * kPartials;
       Screen S;
@@ -392,22 +374,77 @@ __global__ void __launch_bounds__(256) k_project_bwd(
       tw[4] = S.xc[2] * gx[0] - S.xc[0] * gx[2] - 2.0 * A[2];
       tw[5] = S.xc[0] * gx[1] - S.xc[1] * gx[0] - 2.0 * A[3];
       glogit += (double)G[5] * P.o * (1.0 - P.o);
-      for (int k = 0; k < 20; ++k) gy[k] += G[6 + k];
+      float* C = contrib + ci * 16;
+      for (int k = 0; k < 3; ++k) C[k] = (float)gp[k];
+      for (int k = 0; k < 9; ++k) C[3 + k] = (float)gM[k];
+      C[12] = (float)glogit;
     }
-    // per-view twist: this wave's sum (fixed order), one partial per wave and
-    // (view, component), stored component-major so that the final sum reads
-    // them contiguously; no work-group barrier; a view no lane of the wave
-    // sees adds 0
-    double* tp = twist_part + (size_t)v * 6 * n_waves + wave_id;
-    if (__builtin_amdgcn_ballot_w64(ci != ~0u) != 0ull) {
+    // the block's views: lane 0's (always a c of this block) to the last
+    // active lane's; one partial per (view, component, block), in the order
+    // of the blocks a view's c span
+    const uint32_t vlo = __builtin_amdgcn_readfirstlane(v);
+    uint32_t vmax = act ? v : 0u;
+    for (int off = 32; off > 0; off >>= 1) vmax = max(vmax, (uint32_t)__shfl_xor((int)vmax, off, 64));
+    const uint32_t vhi = __builtin_amdgcn_readfirstlane(vmax);
+    for (uint32_t vv = vlo; vv <= vhi; ++vv) {
+      const bool mine = act && v == vv;
       for (int k = 0; k < 6; ++k) {
-        const double s = wave_sum_d(tw[k]);
-        if (lane == 0) tp[(size_t)k * n_waves] = s;
+        const double s = wave_sum_d(mine ? tw[k] : 0.0);
+        if (lane == 0) twist_part[((int64_t)vv * 6 + k) * nblk_max + blk] = s;
       }
-    } else if (lane < 6) {
-      tp[(size_t)lane * n_waves] = 0.0;
     }
   }
+}
+
+// Per Gaussian: the views' contributions summed in view order (a fixed
+// order, so results are deterministic), then the activation's chain rule.
+__global__ void __launch_bounds__(256) k_project_bwd(
+    Settings st, int n_views, const float* __restrict__ means, const float* __restrict__ log_scales,
+    const float* __restrict__ quats, const float* __restrict__ logits, int64_t n,
+    uint32_t npad_shift, const Counters* __restrict__ cnt, const uint32_t* __restrict__ cnt_t,
+    const uint32_t* __restrict__ cidx, const float* __restrict__ grad2d, const float* __restrict__ contrib,
+    float* __restrict__ g_means, float* __restrict__ g_ls, float* __restrict__ g_q, float* __restrict__ g_logit,
+    float* __restrict__ g_rgb, float* __restrict__ g_feat) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool active = g < n;
+  double p[3] = {0, 0, 0}, ls[3] = {0, 0, 0}, q[4] = {1, 0, 0, 0}, logit = 0.0;
+  if (active) {
+    for (int k = 0; k < 3; ++k) p[k] = means[k * n + g];
+    for (int k = 0; k < 3; ++k) ls[k] = log_scales[k * n + g];
+    for (int k = 0; k < 4; ++k) q[k] = quats[k * n + g];
+    logit = logits[g];
+  }
+  Proj P;
+  double gp[3] = {0, 0, 0}, gM[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}, glogit = 0.0;
+  float gy[20];
+  for (int k = 0; k < 20; ++k) gy[k] = 0.f;
+  bool any = false;
+  // views are taken 8 at a time with branch-free (clamped) loads, so that
+  // their visibility and record index loads are in flight together
+  constexpr int kVB = 8;
+  if (active && cnt->overflow == 0u) {
+    for (int v0 = 0; v0 < n_views; v0 += kVB) {
+      uint32_t cix[kVB];
+#pragma unroll
+      for (int u = 0; u < kVB; ++u) {
+        const uint64_t r = ((uint64_t)min(v0 + u, n_views - 1) << npad_shift) | (uint64_t)g;
+        const uint32_t c = cnt_t[r], ci = cidx[r];
+        cix[u] = (v0 + u < n_views && c != 0u) ? ci : ~0u;
+      }
+#pragma unroll
+      for (int u = 0; u < kVB; ++u) {
+        if (cix[u] == ~0u) continue;
+        any = true;
+        const float* C = contrib + (size_t)cix[u] * 16;
+        for (int k = 0; k < 3; ++k) gp[k] += (double)C[k];
+        for (int k = 0; k < 9; ++k) gM[k] += (double)C[3 + k];
+        glogit += (double)C[12];
+        const float* G = grad2d + (size_t)cix[u] * kPartials;
+        for (int k = 0; k < 20; ++k) gy[k] += G[6 + k];
+      }
+    }
+  }
+  if (any) activate(p, ls, q, logit, P);
   if (!active) return;
   // M = R diag(s) -> s, R -> qh -> q
   double gls[3], gR[9];
@@ -523,12 +560,22 @@ __global__ void __launch_bounds__(256) k_group_feat_grad(int n_views, int64_t n,
 // twist[v][k] = sum over the projection-backward waves of their partial sums
 // (stored [v][k][wave]); one workgroup per (view, component), fixed
 // summation order.
-__global__ void __launch_bounds__(256) k_twist_final(const double* __restrict__ part, int n_waves,
-                                                    int n_views, float* __restrict__ twist) {
+// twist[v][k]: the block partials of view v's c range (the scan of the
+// visibility flags gives its first c), summed in block order.
+__global__ void __launch_bounds__(256) k_twist_final(const double* __restrict__ part, int64_t nblk_max,
+                                                    int n_views, uint32_t npad_shift,
+                                                    const uint32_t* __restrict__ cidx,
+                                                    const Counters* __restrict__ cnt, float* __restrict__ twist) {
   __shared__ double red[256];
   const int idx = blockIdx.x;   // v * 6 + k
+  const int v = idx / 6;
   double s = 0.0;
-  for (int b = threadIdx.x; b < n_waves; b += 256) s += part[(size_t)idx * n_waves + b];
+  if (cnt->overflow == 0u) {
+    const int64_t c0 = cidx[(uint64_t)v << npad_shift];
+    const int64_t c1 = v + 1 < n_views ? (int64_t)cidx[(uint64_t)(v + 1) << npad_shift] : (int64_t)cnt->n_visible;
+    if (c1 > c0)
+      for (int64_t b = c0 / 64 + threadIdx.x; b <= (c1 - 1) / 64; b += 256) s += part[(int64_t)idx * nblk_max + b];
+  }
   red[threadIdx.x] = s;
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
@@ -582,24 +629,39 @@ void launch_group_feat_grad(int n_views, int64_t n, uint32_t npad_shift, const C
                      cnt, cnt_t, cidx, grad2d_g, nfeat, g_feat_g);
 }
 
-size_t twist_temp_bytes(int64_t n, int n_views) {
-  const int64_t waves = 4 * ((n + 255) / 256);   // every wave of the launch writes its partials
-  return (size_t)(waves > 0 ? waves : 1) * n_views * 6 * sizeof(double);
+// per-view contributions (16 floats per visible c) and the twist's block
+// partials (n_views x 6 x blocks of 64 c), for at most n_rid visible c
+size_t project_bwd_temp_bytes(int64_t n_rid, int n_views) {
+  const int64_t nblk = (std::max<int64_t>(n_rid, 1) + 63) / 64;
+  return (size_t)nblk * 64 * 16 * sizeof(float) + (size_t)nblk * n_views * 6 * sizeof(double);
 }
 
 void launch_project_bwd(const Settings& st, const ViewDesc* views, int n_views, const float* means,
                         const float* log_scales, const float* quats, const float* logits, int64_t n,
-                        uint32_t npad_shift, const Counters* cnt, const uint32_t* cnt_t, const uint32_t* cidx,
-                        const float* grad2d, float* g_means, float* g_ls, float* g_q, float* g_logit,
-                        float* g_rgb, float* g_feat, float* twist, void* temp, hipStream_t s) {
+                        uint32_t npad_shift, int64_t n_rid, const Counters* cnt, const uint32_t* cnt_t,
+                        const uint32_t* cidx, const uint32_t* ent, const float* grad2d, float* g_means,
+                        float* g_ls, float* g_q, float* g_logit, float* g_rgb, float* g_feat, float* twist,
+                        void* temp, hipStream_t s) {
+  const int64_t nblk = (std::max<int64_t>(n_rid, 1) + 63) / 64;
+  float* contrib = (float*)temp;
+  double* tpart = (double*)((char*)temp + (size_t)nblk * 64 * 16 * sizeof(float));
+  int dev = 0, cus = 256, occ = 1;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_project_bwd_view, 256, 0);
+  int64_t grid = (int64_t)cus * (occ > 0 ? occ : 1);
+  const int64_t need = (nblk + 3) / 4;   // four waves (blocks of 64 c) per work-group
+  if (grid > need) grid = need;
+  hipLaunchKernelGGL(k_project_bwd_view, dim3((unsigned)grid), dim3(256), 0, s, st, views, means, log_scales,
+                     quats, logits, n, npad_shift, cnt, ent, grad2d, contrib, tpart, nblk);
   const int blocks = (int)((n + 255) / 256);
   if (blocks > 0)
-    hipLaunchKernelGGL(k_project_bwd, dim3(blocks), dim3(256), 0, s, st, views, n_views, means,
-                       log_scales, quats, logits, n, npad_shift, cnt, cnt_t, cidx, grad2d, g_means, g_ls,
-                       g_q, g_logit, g_rgb, g_feat, (double*)temp);
-  if (twist)   // with no Gaussian block the sum is empty and the kernel writes zeros
-    hipLaunchKernelGGL(k_twist_final, dim3(n_views * 6), dim3(256), 0, s, (const double*)temp, 4 * blocks,
-                       n_views, twist);
+    hipLaunchKernelGGL(k_project_bwd, dim3(blocks), dim3(256), 0, s, st, n_views, means, log_scales, quats,
+                       logits, n, npad_shift, cnt, cnt_t, cidx, grad2d, (const float*)contrib, g_means, g_ls,
+                       g_q, g_logit, g_rgb, g_feat);
+  if (twist)
+    hipLaunchKernelGGL(k_twist_final, dim3(n_views * 6), dim3(256), 0, s, (const double*)tpart, nblk, n_views,
+                       npad_shift, cidx, cnt, twist);
 }
 
 }  // namespace lgs

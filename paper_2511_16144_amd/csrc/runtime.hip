@@ -608,7 +608,7 @@ lgs_status w_alloc_bwd(Work* W) {
   W->partials = (float*)w_alloc(W, sizeof(float) * kSlotFloats * S, ok);
   W->mask = (uint8_t*)w_alloc(W, S + 8, ok);
   W->grad2d = (float*)w_alloc(W, sizeof(float) * kPartials * std::max<int64_t>(W->n_rid, 1), ok);
-  W->ttmp = w_alloc(W, twist_temp_bytes(W->n, (int)W->plan.views.size()), ok);
+  W->ttmp = w_alloc(W, project_bwd_temp_bytes(W->n_rid, (int)W->plan.views.size()), ok);
   if (W->G > 1) {
     W->grad2d_g = (float*)w_alloc(W, sizeof(float) * kPartials * std::max<int64_t>(W->n_rid, 1), ok);
     W->geo_acc = (float*)w_alloc(W, sizeof(float) * 6 * std::max<int64_t>(W->n_rid, 1), ok);
@@ -781,8 +781,8 @@ void enqueue_backward_reduce(Work* W, const lgs_gaussians* g, const lgs_grads* g
   launch_seg_reduce(W->slot_off, W->partials, W->mask, W->counters, W->n_rid, W->grad2d, s);
   if (W->G > 1) launch_group_geo_add(W->grad2d, W->counters, W->n_rid, W->geo_acc, s);
   launch_project_bwd(ds, W->d_views, V, g->means, g->log_scales, g->quats, g->opacity_logits, W->n,
-                     W->npad_shift, W->counters, W->cnt_t, W->cidx, W->grad2d, gr->means, gr->log_scales,
-                     gr->quats, gr->opacity_logits, gr->rgb, gr->feat, gr->twist, W->ttmp, s);
+                     W->npad_shift, W->n_rid, W->counters, W->cnt_t, W->cidx, W->ent, W->grad2d, gr->means,
+                     gr->log_scales, gr->quats, gr->opacity_logits, gr->rgb, gr->feat, gr->twist, W->ttmp, s);
   w_mark(W, 7, s);
 }
 
