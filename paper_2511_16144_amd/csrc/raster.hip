@@ -35,6 +35,8 @@
 // results are deterministic run to run.
 #include "lgs_internal.h"
 
+#include <type_traits>
+
 namespace lgs {
 namespace {
 
@@ -441,35 +443,6 @@ __device__ __forceinline__ float dpp(float x) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
 }
 
-// Transpose-reduction of 32 values over each half of the wave separately:
-// on entry the lanes of a half hold v[0..31]; on exit lane l holds the sum
-// over its half of value l & 31.  Partners: l ^ 16 (permlane16 swap), l ^ 8
-// (row_ror:8), 7 - (l & 7) within the half row (row_half_mirror), l ^ 2 and
-// l ^ 1 (quad_perm).
-__device__ __forceinline__ float transpose_reduce_half32(const float v[32], int lane) {
-  float s[16];
-#pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    // rows 0, 2 keep value i, rows 1, 3 keep 16 + i (sum over l, l^16)
-    auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[i]), __float_as_uint(v[16 + i]), false, false);
-    s[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
-  }
-  float t[8];
-  const bool h8 = (lane & 8) != 0;
-#pragma unroll
-  for (int i = 0; i < 8; ++i) t[i] = bsel(h8, s[i], s[8 + i]) + dpp<0x128>(bsel(h8, s[8 + i], s[i]));
-  float u[4];
-  const bool h4 = (lane & 4) != 0;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) u[i] = bsel(h4, t[i], t[4 + i]) + dpp<0x141>(bsel(h4, t[4 + i], t[i]));
-  float w[2];
-  const bool h2 = (lane & 2) != 0;
-#pragma unroll
-  for (int i = 0; i < 2; ++i) w[i] = bsel(h2, u[i], u[2 + i]) + dpp<0x4E>(bsel(h2, u[2 + i], u[i]));
-  const bool h1 = (lane & 1) != 0;
-  return bsel(h1, w[0], w[1]) + dpp<0xB1>(bsel(h1, w[1], w[0]));
-}
-
 __device__ __forceinline__ int wave_max_i32(int x) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) x = max(x, __shfl_xor(x, off, 64));
@@ -872,10 +845,14 @@ __global__ void __launch_bounds__(256)
 // owns the slot range [slot_off[c], slot_off[c + 1]) (the last one ends at
 // n_slots); a slot holds a partial only where the backward set its mask byte.
 // Each half of a wave takes one c (waves loop over pairs of c, grid-stride,
-// persistent grid), so a wave keeps two chains of dependent loads in flight;
-// lane l of a half sums slots base + l, base + l + 32, ... in order, then
-// the half sums its lanes with the butterfly transpose-reduction: a fixed
-// order, so results are deterministic.
+// persistent grid).  Lane l of a half sums value l of every written slot, in
+// slot order, so a half reads each slot as one contiguous 128-byte access
+// and needs no exchange between lanes: per window of 32 slots, lane l tests
+// slot l's mask byte, a ballot gives the half its written slots, and the
+// half walks them lowest first in batches (2 kSegBatch while that many are
+// left, else kSegBatch), each batch's loads requested before the first is
+// added.  A fixed order, so results are deterministic.
+constexpr int kSegBatch = 8;
 __global__ void __launch_bounds__(256) k_seg_reduce(const uint32_t* __restrict__ slot_off,
                                                     const float* __restrict__ partials,
                                                     uint8_t* __restrict__ mask,
@@ -925,36 +902,42 @@ __global__ void __launch_bounds__(256) k_seg_reduce(const uint32_t* __restrict__
     // moves across this point)
     asm volatile("" ::: "memory");
     const uint32_t base = b0, len = l0;
-    const bool m0 = hl < len && mraw0 != 0u;
     const uint32_t maxlen = __builtin_amdgcn_readfirstlane(max(len, (uint32_t)__shfl_xor((int)len, 32, 64)));
-    float vv[32];
+    const uint32_t safe = len > 0u ? base : 0u;   // a slot in range for a lane with nothing to add
+    float acc = 0.f;
+    for (uint32_t o = 0; o < maxlen; o += 32) {
+      const uint32_t sl = base + o + hl;
+      // the window's first byte per lane is the one requested a pair ago
+      const bool written = o == 0u ? (hl < len && mraw0 != 0u) : (o + hl < len && mask[sl] != 0);
+      if (written) mask[sl] = 0;   // cleared for the next backward over these slots
+      const uint64_t bal = __builtin_amdgcn_ballot_w64(written);
+      const uint32_t lo = (uint32_t)bal, hi = (uint32_t)(bal >> 32);
+      uint32_t mine = half ? hi : lo;
+      const uint32_t nmax = max((uint32_t)__builtin_popcount(lo), (uint32_t)__builtin_popcount(hi));
+      const uint32_t sb = base + o;
+      auto batch = [&](auto nb_tag) {
+        constexpr int NB = decltype(nb_tag)::value;
+        float t[NB];
 #pragma unroll
-    for (int i = 0; i < 32; ++i) vv[i] = 0.f;
-    for (uint32_t o = hl; o < maxlen; o += 32) {
-      const uint32_t sl = base + o;
-      // the first slot of each lane: the byte requested one pair ago
-      const bool written = o == hl ? m0 : (o < len && mask[sl] != 0);
-      if (written) {
-        mask[sl] = 0;   // cleared for the next backward over these slots
-        // the record's seven 16-byte quarters are all requested before the
-        // first is added, so one memory round trip covers the slot
-        const f32x4* pp = (const f32x4*)(partials + (size_t)sl * kSlotFloats);
-        constexpr int kQ = (kPartials + 3) / 4;
-        f32x4 t[kQ];
-#pragma unroll
-        for (int i = 0; i < kQ; ++i) t[i] = pp[i];
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int i = 0; i < kQ; ++i) {
-          vv[4 * i] += t[i][0];
-          vv[4 * i + 1] += t[i][1];
-          if (4 * i + 2 < kPartials) vv[4 * i + 2] += t[i][2];
-          if (4 * i + 3 < kPartials) vv[4 * i + 3] += t[i][3];
+        for (int j = 0; j < NB; ++j) {
+          // the lowest written slot left (once none is, a slot in range whose
+          // value is dropped)
+          const bool v = mine != 0u;
+          const uint32_t sl_j = v ? sb + (uint32_t)__builtin_ctz(mine) : safe;
+          mine &= mine - 1u;
+          const float x = partials[(size_t)sl_j * kSlotFloats + hl];
+          t[j] = v ? x : 0.f;
         }
-      }
+#pragma unroll
+        for (int j = 0; j < NB; ++j) acc += t[j];
+      };
+      // long runs (a view where a Gaussian covers many blocks) in batches of
+      // 2 kSegBatch, the rest in batches of kSegBatch
+      uint32_t k = 0;
+      for (; k + 2 * kSegBatch <= nmax; k += 2 * kSegBatch) batch(std::integral_constant<int, 2 * kSegBatch>());
+      for (; k < nmax; k += kSegBatch) batch(std::integral_constant<int, kSegBatch>());
     }
-    const float tot = transpose_reduce_half32(vv, lane);
-    if (c < nv && hl < (uint32_t)kPartials) grad2d[(size_t)c * kPartials + hl] = tot;
+    if (c < nv && hl < (uint32_t)kPartials) grad2d[(size_t)c * kPartials + hl] = acc;
     b0 = b1;
     l0 = l1;
     mraw0 = mraw1;
