@@ -903,7 +903,9 @@ __global__ void __launch_bounds__(256) k_seg_reduce(const uint32_t* __restrict__
     asm volatile("" ::: "memory");
     const uint32_t base = b0, len = l0;
     const uint32_t maxlen = __builtin_amdgcn_readfirstlane(max(len, (uint32_t)__shfl_xor((int)len, 32, 64)));
-    const uint32_t safe = len > 0u ? base : 0u;   // a slot in range for a lane with nothing to add
+    // the slot a lane with nothing to add reads: the half's last one read
+    // (already in cache), slot 0 before the first (read by every wave)
+    uint32_t last = 0u;
     float acc = 0.f;
     for (uint32_t o = 0; o < maxlen; o += 32) {
       const uint32_t sl = base + o + hl;
@@ -920,12 +922,12 @@ __global__ void __launch_bounds__(256) k_seg_reduce(const uint32_t* __restrict__
         float t[NB];
 #pragma unroll
         for (int j = 0; j < NB; ++j) {
-          // the lowest written slot left (once none is, a slot in range whose
-          // value is dropped)
+          // the lowest written slot left (once none is, the last slot read,
+          // whose value is dropped)
           const bool v = mine != 0u;
-          const uint32_t sl_j = v ? sb + (uint32_t)__builtin_ctz(mine) : safe;
+          last = v ? sb + (uint32_t)__builtin_ctz(mine) : last;
           mine &= mine - 1u;
-          const float x = partials[(size_t)sl_j * kSlotFloats + hl];
+          const float x = partials[(size_t)last * kSlotFloats + hl];
           t[j] = v ? x : 0.f;
         }
 #pragma unroll
