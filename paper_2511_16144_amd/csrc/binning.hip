@@ -51,10 +51,14 @@ __device__ __forceinline__ int64_t count_of(const uint32_t* n_dev, int64_t n_max
   return n_dev ? (int64_t)*n_dev : n_max;
 }
 
+// A gather scan reads src[idx[i]] at random once: the reduce pass leaves
+// each gathered value in out[i], where the down-sweep reads it in order
+// (and then overwrites it with the item's prefix).
 __global__ void __launch_bounds__(kScanThreads) k_scan_reduce(int mode, const uint32_t* __restrict__ src,
                                                               const uint32_t* __restrict__ idx,
                                                               const uint32_t* n_dev, int64_t n_max,
-                                                              uint32_t* __restrict__ bsum) {
+                                                              uint32_t* __restrict__ bsum,
+                                                              uint32_t* __restrict__ stash) {
   __shared__ uint32_t sh[4];
   const int64_t n = count_of(n_dev, n_max);
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
@@ -62,7 +66,11 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_reduce(int mode, const ui
   uint32_t s = 0;
   for (int k = 0; k < kScanItems; ++k) {
     const int64_t i = base + (int64_t)k * kScanThreads + threadIdx.x;
-    if (i < n) s += scan_in(mode, src, idx, i);
+    if (i < n) {
+      const uint32_t x = scan_in(mode, src, idx, i);
+      if (mode == SCAN_GATHER) stash[i] = x;
+      s += x;
+    }
   }
   uint32_t total;
   block_excl_scan(s, sh, total);
@@ -96,7 +104,7 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_down(int mode, const uint
   uint32_t s = 0;
   for (int k = 0; k < kScanItems; ++k) {
     const int64_t i = base + (int64_t)threadIdx.x * kScanItems + k;
-    v[k] = i < n ? scan_in(mode, src, idx, i) : 0u;
+    v[k] = i < n ? (mode == SCAN_GATHER ? out[i] : scan_in(mode, src, idx, i)) : 0u;
     s += v[k];
   }
   uint32_t btot;
@@ -334,7 +342,7 @@ void launch_scan(int mode, const uint32_t* src, const uint32_t* idx, uint32_t* o
   uint32_t* bsum = (uint32_t*)temp;
   if (nb > 0)
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, mode, src, idx,
-                       n_dev, n_max, bsum);
+                       n_dev, n_max, bsum, out);
   hipLaunchKernelGGL(k_scan_down, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(kScanThreads), 0, s, mode, src, idx,
                      n_dev, n_max, (const uint32_t*)bsum, out, total, out_at_idx);
 }

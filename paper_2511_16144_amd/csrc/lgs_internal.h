@@ -153,7 +153,9 @@ enum ScanInput { SCAN_FLAG_NONZERO = 0, SCAN_VALUE = 1, SCAN_GATHER = 2 };
 // in(i) = (src[i] != 0) / src[i] / src[idx[i]] by mode; n read from *n_dev
 // when n_dev != nullptr (n_max bounds the grid), else n_max.
 // out_at_idx (gather scans only, or NULL): each value also written at its
-// source index, out_at_idx[idx[i]] = out[i]
+// source index, out_at_idx[idx[i]] = out[i].  A gather scan also uses out
+// to hold the gathered values between its two passes, so out must not
+// overlap src or idx.
 void launch_scan(int mode, const uint32_t* src, const uint32_t* idx, uint32_t* out,
                  uint32_t* total, const uint32_t* n_dev, int64_t n_max,
                  void* temp, hipStream_t s, uint32_t* out_at_idx = nullptr);
