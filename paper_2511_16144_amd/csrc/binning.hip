@@ -84,7 +84,7 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_down(int mode, const uint
                                                             const uint32_t* n_dev, int64_t n_max,
                                                             const uint32_t* __restrict__ bsum,
                                                             uint32_t* __restrict__ out, uint32_t* __restrict__ total,
-                                                            uint32_t* __restrict__ out_at_idx) {
+                                                            uint32_t* __restrict__ out_at_idx, Compact cp) {
   __shared__ uint32_t sh[4];
   const int64_t n = count_of(n_dev, n_max);
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
@@ -114,6 +114,11 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_down(int mode, const uint
     if (i < n) {
       out[i] = run;
       if (out_at_idx) out_at_idx[idx[i]] = run;   // gather scans: the value also at its source index
+      if (cp.ent && v[k] != 0u) {                  // flag scans: compaction of the flagged items
+        cp.ent[run] = (uint32_t)i;
+        cp.ent_copy[run] = (uint32_t)i;
+        cp.keys[run] = cp.key_src[i];
+      }
     }
     run += v[k];
   }
@@ -122,21 +127,6 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_down(int mode, const uint
 
 // reduce kernel must sum the same items as the down-sweep: both cover the
 // block's 2048 items, only the assignment to threads differs.
-
-__global__ void __launch_bounds__(256) k_compact(const uint32_t* __restrict__ cnt_t,
-                                                 const uint32_t* __restrict__ cidx,
-                                                 const uint32_t* __restrict__ dkey, int64_t n_rid,
-                                                 uint32_t* __restrict__ ent, uint32_t* __restrict__ ent_copy,
-                                                 uint32_t* __restrict__ keys) {
-  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (r >= n_rid) return;
-  if (cnt_t[r] != 0u) {
-    const uint32_t c = cidx[r];
-    ent[c] = (uint32_t)r;
-    ent_copy[c] = (uint32_t)r;
-    keys[c] = dkey[r];
-  }
-}
 
 constexpr int kEmitThreads = 256;
 constexpr int kEmitPerThread = 4;
@@ -337,21 +327,15 @@ size_t scan_temp_bytes(int64_t n) {
 }
 
 void launch_scan(int mode, const uint32_t* src, const uint32_t* idx, uint32_t* out, uint32_t* total,
-                 const uint32_t* n_dev, int64_t n_max, void* temp, hipStream_t s, uint32_t* out_at_idx) {
+                 const uint32_t* n_dev, int64_t n_max, void* temp, hipStream_t s, uint32_t* out_at_idx,
+                 Compact cp) {
   const int64_t nb = (n_max + kScanTile - 1) / kScanTile;
   uint32_t* bsum = (uint32_t*)temp;
   if (nb > 0)
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, mode, src, idx,
                        n_dev, n_max, bsum, out);
   hipLaunchKernelGGL(k_scan_down, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(kScanThreads), 0, s, mode, src, idx,
-                     n_dev, n_max, (const uint32_t*)bsum, out, total, out_at_idx);
-}
-
-void launch_compact(const uint32_t* cnt_t, const uint32_t* cidx, const uint32_t* dkey, int64_t n_rid,
-                    uint32_t* ent, uint32_t* ent_copy, uint32_t* keys, hipStream_t s) {
-  if (n_rid <= 0) return;
-  hipLaunchKernelGGL(k_compact, dim3((unsigned)((n_rid + 255) / 256)), dim3(256), 0, s, cnt_t, cidx,
-                     dkey, n_rid, ent, ent_copy, keys);
+                     n_dev, n_max, (const uint32_t*)bsum, out, total, out_at_idx, cp);
 }
 
 void launch_emit(const GeomRec* geom, const ViewDesc* views, const uint32_t* srid, const uint32_t* off_t,

@@ -156,13 +156,17 @@ enum ScanInput { SCAN_FLAG_NONZERO = 0, SCAN_VALUE = 1, SCAN_GATHER = 2 };
 // source index, out_at_idx[idx[i]] = out[i].  A gather scan also uses out
 // to hold the gathered values between its two passes, so out must not
 // overlap src or idx.
+// Compaction (flag scans only, ent == nullptr for none): for every flagged
+// item i, with c = out[i]: ent[c] = ent_copy[c] = i and keys[c] = key_src[i].
+struct Compact {
+  const uint32_t* key_src = nullptr;
+  uint32_t* ent = nullptr;
+  uint32_t* ent_copy = nullptr;
+  uint32_t* keys = nullptr;
+};
 void launch_scan(int mode, const uint32_t* src, const uint32_t* idx, uint32_t* out,
                  uint32_t* total, const uint32_t* n_dev, int64_t n_max,
-                 void* temp, hipStream_t s, uint32_t* out_at_idx = nullptr);
-
-// compaction of visible (view, Gaussian) ids
-void launch_compact(const uint32_t* cnt_t, const uint32_t* cidx, const uint32_t* dkey, int64_t n_rid,
-                    uint32_t* ent, uint32_t* ent_copy, uint32_t* keys, hipStream_t s);
+                 void* temp, hipStream_t s, uint32_t* out_at_idx = nullptr, Compact cp = Compact());
 
 // pair emission (load-balanced over pairs), tile ranges
 void launch_emit(const GeomRec* geom, const ViewDesc* views, const uint32_t* srid,

@@ -681,10 +681,15 @@ void enqueue_front(Work* W, const lgs_gaussians* g, hipStream_t s) {
   const int64_t n_rid = W->n_rid;
   launch_project(ds, W->d_views, V, g->means, g->log_scales, g->quats, g->opacity_logits, g->rgb, g->feat,
                  W->app_bf16, W->n, W->npad_shift, W->geom, W->cnt_t, W->cnt_b, W->dkey, W->app, W->counters, s);
+  // the visibility scan also compacts: ent (kept, index order), a copy that
+  // the depth sort permutes, and the depth keys in the same order
+  Compact cp;
+  cp.key_src = W->dkey;
+  cp.ent = W->ent;
+  cp.ent_copy = W->ent_a;
+  cp.keys = W->dk0;
   launch_scan(SCAN_FLAG_NONZERO, W->cnt_t, nullptr, W->cidx, &W->counters->n_visible, nullptr, n_rid,
-              W->scan_tmp, s);
-  // the compaction writes ent (kept, index order) and a copy that the depth sort permutes
-  launch_compact(W->cnt_t, W->cidx, W->dkey, n_rid, W->ent, W->ent_a, W->dk0, s);
+              W->scan_tmp, s, nullptr, cp);
   bool alt = false;
   radix_sort_u32(W->dk0, W->ent_a, W->dk1, W->ent_b, &W->counters->n_visible, n_rid, 0, 32, W->radix_small, s,
                  &alt);
