@@ -40,13 +40,6 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t* sh, ui
   return wsum + inc - x;
 }
 
-__device__ __forceinline__ uint32_t scan_in(int mode, const uint32_t* __restrict__ src,
-                                            const uint32_t* __restrict__ idx, int64_t i) {
-  if (mode == SCAN_FLAG_NONZERO) return src[i] != 0u ? 1u : 0u;
-  if (mode == SCAN_VALUE) return src[i];
-  return src[idx[i]];
-}
-
 __device__ __forceinline__ int64_t count_of(const uint32_t* n_dev, int64_t n_max) {
   return n_dev ? (int64_t)*n_dev : n_max;
 }
@@ -54,7 +47,13 @@ __device__ __forceinline__ int64_t count_of(const uint32_t* n_dev, int64_t n_max
 // A gather scan reads src[idx[i]] at random once: the reduce pass leaves
 // each gathered value in out[i], where the down-sweep reads it in order
 // (and then overwrites it with the item's prefix).
-__global__ void __launch_bounds__(kScanThreads) k_scan_reduce(int mode, const uint32_t* __restrict__ src,
+//
+// In both passes a thread requests all of its items' words before it uses
+// any (unconditional loads at indices clamped to the last item, validity
+// applied afterwards): a load under a bounds test that is used at once
+// costs one memory round trip per item.
+template <int MODE>
+__global__ void __launch_bounds__(kScanThreads) k_scan_reduce(const uint32_t* __restrict__ src,
                                                               const uint32_t* __restrict__ idx,
                                                               const uint32_t* n_dev, int64_t n_max,
                                                               uint32_t* __restrict__ bsum,
@@ -63,14 +62,29 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_reduce(int mode, const ui
   const int64_t n = count_of(n_dev, n_max);
   const int64_t base = (int64_t)blockIdx.x * kScanTile;
   if (base >= n) return;
+  auto item = [&](int k) { return base + (int64_t)k * kScanThreads + threadIdx.x; };
+  auto clamp = [&](int64_t i) { return i < n ? i : n - 1; };
+  uint32_t x[kScanItems];
+  if constexpr (MODE == SCAN_GATHER) {
+    uint32_t id[kScanItems];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) id[k] = idx[clamp(item(k))];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) x[k] = src[id[k]];
+  } else {
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) x[k] = src[clamp(item(k))];
+  }
   uint32_t s = 0;
+#pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    const int64_t i = base + (int64_t)k * kScanThreads + threadIdx.x;
-    if (i < n) {
-      const uint32_t x = scan_in(mode, src, idx, i);
-      if (mode == SCAN_GATHER) stash[i] = x;
-      s += x;
+    const int64_t i = item(k);
+    uint32_t v = MODE == SCAN_FLAG_NONZERO ? (x[k] != 0u ? 1u : 0u) : x[k];
+    v = i < n ? v : 0u;
+    if constexpr (MODE == SCAN_GATHER) {
+      if (i < n) stash[i] = v;
     }
+    s += v;
   }
   uint32_t total;
   block_excl_scan(s, sh, total);
@@ -79,7 +93,8 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_reduce(int mode, const ui
 
 // one work-group scans the block sums in place (exclusive) and writes total
 
-__global__ void __launch_bounds__(kScanThreads) k_scan_down(int mode, const uint32_t* __restrict__ src,
+template <int MODE>
+__global__ void __launch_bounds__(kScanThreads) k_scan_down(const uint32_t* __restrict__ src,
                                                             const uint32_t* __restrict__ idx,
                                                             const uint32_t* n_dev, int64_t n_max,
                                                             const uint32_t* __restrict__ bsum,
@@ -93,31 +108,54 @@ __global__ void __launch_bounds__(kScanThreads) k_scan_down(int mode, const uint
     return;
   }
   if (base >= n) return;
+  // thread t owns the contiguous items [base + t*8, base + t*8 + 8); their
+  // words (the value, and the source index or depth key the writes below
+  // need) are requested before the block sums, so all are in flight at once
+  auto item = [&](int k) { return base + (int64_t)threadIdx.x * kScanItems + k; };
+  auto clamp = [&](int64_t i) { return i < n ? i : n - 1; };
+  uint32_t raw[kScanItems], aux[kScanItems];
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t ic = clamp(item(k));
+    raw[k] = MODE == SCAN_GATHER ? out[ic] : src[ic];
+  }
+  if (out_at_idx) {
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) aux[k] = idx[clamp(item(k))];
+  } else if (cp.ent) {
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) aux[k] = cp.key_src[clamp(item(k))];
+  } else {
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) aux[k] = 0u;
+  }
+  asm volatile("" ::: "memory");
   // offset of this block: the sum of the block sums before it (each block
   // adds them up itself, so no separate pass over the block sums is needed)
   uint32_t pre = 0;
   for (int64_t b = threadIdx.x; b < (int64_t)blockIdx.x; b += kScanThreads) pre += bsum[b];
   uint32_t boff;
   block_excl_scan(pre, sh, boff);
-  // thread t owns the contiguous items [base + t*8, base + t*8 + 8)
   uint32_t v[kScanItems];
   uint32_t s = 0;
+#pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    const int64_t i = base + (int64_t)threadIdx.x * kScanItems + k;
-    v[k] = i < n ? (mode == SCAN_GATHER ? out[i] : scan_in(mode, src, idx, i)) : 0u;
+    const uint32_t x = MODE == SCAN_FLAG_NONZERO ? (raw[k] != 0u ? 1u : 0u) : raw[k];
+    v[k] = item(k) < n ? x : 0u;
     s += v[k];
   }
   uint32_t btot;
   uint32_t run = block_excl_scan(s, sh, btot) + boff;
+#pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    const int64_t i = base + (int64_t)threadIdx.x * kScanItems + k;
+    const int64_t i = item(k);
     if (i < n) {
       out[i] = run;
-      if (out_at_idx) out_at_idx[idx[i]] = run;   // gather scans: the value also at its source index
+      if (out_at_idx) out_at_idx[aux[k]] = run;   // gather scans: the value also at its source index
       if (cp.ent && v[k] != 0u) {                  // flag scans: compaction of the flagged items
         cp.ent[run] = (uint32_t)i;
         cp.ent_copy[run] = (uint32_t)i;
-        cp.keys[run] = cp.key_src[i];
+        cp.keys[run] = aux[k];
       }
     }
     run += v[k];
@@ -326,16 +364,28 @@ size_t scan_temp_bytes(int64_t n) {
   return (size_t)(nb > 0 ? nb : 1) * sizeof(uint32_t);
 }
 
-void launch_scan(int mode, const uint32_t* src, const uint32_t* idx, uint32_t* out, uint32_t* total,
-                 const uint32_t* n_dev, int64_t n_max, void* temp, hipStream_t s, uint32_t* out_at_idx,
-                 Compact cp) {
+template <int MODE>
+static void launch_scan_t(const uint32_t* src, const uint32_t* idx, uint32_t* out, uint32_t* total,
+                   const uint32_t* n_dev, int64_t n_max, void* temp, hipStream_t s, uint32_t* out_at_idx,
+                   Compact cp) {
   const int64_t nb = (n_max + kScanTile - 1) / kScanTile;
   uint32_t* bsum = (uint32_t*)temp;
   if (nb > 0)
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, mode, src, idx,
-                       n_dev, n_max, bsum, out);
-  hipLaunchKernelGGL(k_scan_down, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(kScanThreads), 0, s, mode, src, idx,
+    hipLaunchKernelGGL(k_scan_reduce<MODE>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, src, idx, n_dev, n_max,
+                       bsum, out);
+  hipLaunchKernelGGL(k_scan_down<MODE>, dim3((unsigned)(nb > 0 ? nb : 1)), dim3(kScanThreads), 0, s, src, idx,
                      n_dev, n_max, (const uint32_t*)bsum, out, total, out_at_idx, cp);
+}
+
+void launch_scan(int mode, const uint32_t* src, const uint32_t* idx, uint32_t* out, uint32_t* total,
+                 const uint32_t* n_dev, int64_t n_max, void* temp, hipStream_t s, uint32_t* out_at_idx,
+                 Compact cp) {
+  if (mode == SCAN_FLAG_NONZERO)
+    launch_scan_t<SCAN_FLAG_NONZERO>(src, idx, out, total, n_dev, n_max, temp, s, out_at_idx, cp);
+  else if (mode == SCAN_VALUE)
+    launch_scan_t<SCAN_VALUE>(src, idx, out, total, n_dev, n_max, temp, s, out_at_idx, cp);
+  else
+    launch_scan_t<SCAN_GATHER>(src, idx, out, total, n_dev, n_max, temp, s, out_at_idx, cp);
 }
 
 void launch_emit(const GeomRec* geom, const ViewDesc* views, const uint32_t* srid, const uint32_t* off_t,

@@ -156,8 +156,9 @@ enum ScanInput { SCAN_FLAG_NONZERO = 0, SCAN_VALUE = 1, SCAN_GATHER = 2 };
 // source index, out_at_idx[idx[i]] = out[i].  A gather scan also uses out
 // to hold the gathered values between its two passes, so out must not
 // overlap src or idx.
-// Compaction (flag scans only, ent == nullptr for none): for every flagged
-// item i, with c = out[i]: ent[c] = ent_copy[c] = i and keys[c] = key_src[i].
+// Compaction (flag scans only, ent == nullptr for none; not together with
+// out_at_idx): for every flagged item i, with c = out[i]: ent[c] =
+// ent_copy[c] = i and keys[c] = key_src[i].
 struct Compact {
   const uint32_t* key_src = nullptr;
   uint32_t* ent = nullptr;
