@@ -75,10 +75,19 @@ __global__ void __launch_bounds__(kThreads) k_hist(const K* __restrict__ keys, c
   for (int d = threadIdx.x; d < 4 * 256; d += kThreads) (&cnt[0][0])[d] = 0;
   __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  // all of the wave's keys are requested before the first is ranked
+  // (unconditional loads at indices clamped to the last key)
+  K kr[kIters];
+#pragma unroll
+  for (int it = 0; it < kIters; ++it) {
+    const int64_t i = base + wave * kWaveKeys + it * 64 + lane;
+    kr[it] = keys[i < n ? i : n - 1];
+  }
+#pragma unroll
   for (int it = 0; it < kIters; ++it) {
     const int64_t i = base + wave * kWaveKeys + it * 64 + lane;
     const bool ok = i < n;
-    const uint32_t d = ok ? digit_of(keys[i], shift) : 0u;
+    const uint32_t d = ok ? digit_of(kr[it], shift) : 0u;
     const uint64_t valid = __builtin_amdgcn_ballot_w64(ok);
     const uint64_t peers = match_digit(d, valid);
     if (ok && (peers & lt) == 0ull) cnt[wave][d] += (uint32_t)__popcll(peers);
@@ -102,11 +111,14 @@ __global__ void __launch_bounds__(kThreads) k_row_scan(const uint32_t* n_dev, in
   uint32_t carry = 0;
   for (int64_t b0 = 0; b0 < nb; b0 += (int64_t)kThreads * kRowItems) {
     const int64_t i0 = b0 + (int64_t)threadIdx.x * kRowItems;
+    // every item requested before any is added (clamped unconditional loads)
     uint32_t v[kRowItems];
+#pragma unroll
+    for (int k = 0; k < kRowItems; ++k) v[k] = row[i0 + k < nb ? i0 + k : nb - 1];
     uint32_t sum = 0;
 #pragma unroll
     for (int k = 0; k < kRowItems; ++k) {
-      v[k] = i0 + k < nb ? row[i0 + k] : 0u;
+      v[k] = i0 + k < nb ? v[k] : 0u;
       sum += v[k];
     }
     uint32_t tot;
@@ -133,17 +145,28 @@ __global__ void __launch_bounds__(kThreads) k_scatter(const K* __restrict__ kin,
   const int64_t nb = (n + kTile - 1) / kTile;
   const int64_t base = (int64_t)blockIdx.x * kTile;
   if (base >= n) return;
+  // thread d's digit total and this block's row offset of digit d, requested
+  // now (they do not depend on the keys)
+  const uint32_t tot_d = dtot[threadIdx.x], off_d = off[(int64_t)threadIdx.x * nb + blockIdx.x];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int d = threadIdx.x; d < 4 * 256; d += kThreads) (&cnt[0][0])[d] = 0;
   __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   K kk[kIters];
   uint32_t vv[kIters];
+  // all of the wave's keys and values are requested before the first key is
+  // ranked (unconditional loads at indices clamped to the last key)
+#pragma unroll
+  for (int it = 0; it < kIters; ++it) {
+    const int64_t i = base + wave * kWaveKeys + it * 64 + lane;
+    const int64_t ic = i < n ? i : n - 1;
+    kk[it] = kin[ic];
+    vv[it] = vin[ic];
+  }
+#pragma unroll
   for (int it = 0; it < kIters; ++it) {
     const int64_t i = base + wave * kWaveKeys + it * 64 + lane;
     const bool ok = i < n;
-    kk[it] = ok ? kin[i] : (K)0;
-    vv[it] = ok ? vin[i] : 0u;
     const uint32_t d = digit_of(kk[it], shift);
     const uint64_t valid = __builtin_amdgcn_ballot_w64(ok);
     const uint64_t peers = match_digit(d, valid);
@@ -155,7 +178,7 @@ __global__ void __launch_bounds__(kThreads) k_scatter(const K* __restrict__ kin,
     uint32_t all;
     // first position of digit d: the keys of smaller digits, then those of
     // digit d in earlier blocks
-    uint32_t run = block_excl_scan256(dtot[d], sh, all) + off[(int64_t)d * nb + blockIdx.x];
+    uint32_t run = block_excl_scan256(tot_d, sh, all) + off_d;
     for (int w = 0; w < 4; ++w) {
       const uint32_t c = cnt[w][d];
       cnt[w][d] = run;
